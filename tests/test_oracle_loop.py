@@ -1,0 +1,76 @@
+"""Pins of the oracle's transforms, Dyson step and warm-start network (CPU)."""
+import numpy as np
+import pytest
+
+from oracle import mlp as omlp
+from oracle import transforms as otr
+from paper_2404_17744_amd import synth
+
+BETA = 100.0
+
+
+@pytest.fixture(scope="module")
+def tmat64():
+    return otr.cheb_to_matsubara(64, 256, BETA)
+
+
+def test_transform_closed_forms(tmat64):
+    """T_n0 = int exp(i w tau) = 2i/w_n and T_n1 = -4 / (beta w_n^2) exactly."""
+    wn = otr.matsubara_freqs(256, BETA)
+    assert np.abs(tmat64[:, 0] - 2j / wn).max() < 1e-12
+    assert np.abs(tmat64[:, 1] - (-4.0 / (BETA * wn ** 2))).max() < 1e-12
+
+
+def test_transform_panel_convergence(tmat64):
+    finer = otr.cheb_to_matsubara(64, 256, BETA, panels=4096)
+    assert np.abs(finer - tmat64).max() < 1e-11
+
+
+def test_forward_transform_exact_for_polynomials(tmat64):
+    """F(tau) = tau^2 is reproduced by the interpolant; its transform is
+    i beta^2/w - 2 beta/w^2 - 4i/w^3 (antiperiodic endpoints)."""
+    tau, _ = synth.cheb_tau_grid(64, BETA)
+    F = otr.tau_to_matsubara(tau ** 2, tmat64)
+    wn = otr.matsubara_freqs(256, BETA)
+    exact = 1j * BETA ** 2 / wn - 2 * BETA / wn ** 2 - 4j / wn ** 3
+    assert np.abs(F - exact).max() < 1e-9 * np.abs(exact).max()
+
+
+def test_zero_sigma_round_trip(tmat64):
+    """Sigma = 0: Dyson + least-squares fit returns the closed-form G0 and the
+    density matrix holds n_occ electrons."""
+    s = synth.make_system(20, 40, seed=2)
+    tau, _ = synth.cheb_tau_grid(64, BETA)
+    G0 = synth.g0_tau(s, tau, BETA)
+    G, gam, _ = otr.loop_step(s.F, s.mu, BETA, np.zeros_like(G0), tmat64)
+    assert np.abs(G - G0).max() < 5e-9
+    assert abs(np.trace(gam) - s.n_occ) < 1e-8
+    assert np.abs(gam - gam.T).max() < 1e-12
+
+
+def test_mlp_gradients_match_finite_differences():
+    m, H = 6, 8
+    rng = np.random.default_rng(0)
+    p = omlp.init_params(m, H, seed=1)
+    for k in p:
+        p[k] = p[k] + 0.1 * rng.standard_normal(p[k].shape)
+    x = rng.standard_normal((5, m)); t = rng.standard_normal((5, m))
+    _, g = omlp.loss_and_grads(p, x, t)
+    for k in p:
+        flat = p[k].reshape(-1)
+        for idx in range(0, flat.size, max(1, flat.size // 7)):
+            old = flat[idx]
+            flat[idx] = old + 1e-6; lp, _ = omlp.loss_and_grads(p, x, t)
+            flat[idx] = old - 1e-6; lm, _ = omlp.loss_and_grads(p, x, t)
+            flat[idx] = old
+            fd = (lp - lm) / 2e-6
+            assert abs(fd - g[k].reshape(-1)[idx]) < 1e-7 * max(1.0, abs(fd)), (k, idx)
+
+
+def test_adam_first_step_is_signed_lr():
+    """With bias correction the first Adam step is -lr * g / (|g| + eps)."""
+    p = {"w": np.array([1.0, -2.0, 3.0])}
+    g = {"w": np.array([0.5, -4.0, 1e-3])}
+    st = {}
+    omlp.adam_step(p, g, st, lr=0.01)
+    assert np.allclose(p["w"], np.array([1.0, -2.0, 3.0]) - 0.01 * g["w"] / (np.abs(g["w"]) + 1e-8))
