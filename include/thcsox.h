@@ -1,0 +1,136 @@
+/*
+ * libthcsox -- second-order exchange (SOX) self-energy with tensor-hypercontracted
+ * Coulomb integrals, on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Pokhilko, Yeh, Morales, Zgid, "Tensor hypercontraction for fully
+ * self-consistent imaginary-time GF2 and GWSOX methods", Sec. "THC-scGF2:
+ * algorithm and implementation details" (the SOX expression and the THC
+ * contraction sequence that starts with Eq. U_contraction), with the
+ * integrals in the factorised form of Eq. THC_ERI:
+ *     (ij|kl) = sum_PQ X_iP X_jP V_PQ X_kQ X_lQ        (real X, symmetric V)
+ * and the energy of Eq. E2b (Sec. "Definitions").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every array is row-major and FP64 at the boundary.  "dev" pointers must be
+ *    device memory of the current HIP device, "host" pointers host memory; a
+ *    wrong kind is rejected with THCSOX_ENOTDEV before any work is queued.
+ *  - n = number of orbitals, naux = number of THC points, ntau = number of
+ *    imaginary-time points.  G[k][p][q] = G_pq(tau_k).
+ *  - The tau grid must be ascending inside (0, beta) and mirror symmetric,
+ *    |tau_k + tau_{ntau-1-k} - beta| <= 1e-12 beta, so that the value the SOX
+ *    expression needs at -tau_k is read from index ntau-1-k (it is taken as
+ *    G(beta - tau_k), keeping the expression's leading minus sign).
+ *  - Work is queued on the plan's stream (the stream given to thcsox_plan, or the
+ *    null stream) and is asynchronous unless stated otherwise.
+ *  - Return value: 0 on success, a negative THCSOX_E* code on failure; the
+ *    message of the last failure on the calling thread is in thcsox_last_error().
+ *    No C++ exception crosses this interface.
+ *  - One plan must not be used from two threads at once; distinct plans are
+ *    independent.
+ */
+#ifndef THCSOX_H
+#define THCSOX_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Arithmetic of the contraction stages (the boundary is always FP64).  The
+ * projections, back-projection and energy always run in FP64.
+ *   FP64   : FP64 matrix cores.
+ *   FP32   : FP32 matrix cores, FP32 accumulation.
+ *   BF16X3 : every operand split into three bfloat16 terms, six products per
+ *            product kept, FP32 accumulation.
+ *   FP16X2 : every operand scaled by a power of two and split into two
+ *            half-precision terms, three products per product, FP32 accumulation.
+ * In every mode the sum over the orbital index v that forms D_PR is
+ * accumulated in FP64 and G is scaled per tau point by a power of two. */
+enum {
+  THCSOX_FP64 = 0,
+  THCSOX_FP32 = 1,
+  THCSOX_BF16X3 = 2,
+  THCSOX_FP16X2 = 3
+};
+
+enum {
+  THCSOX_OK = 0,
+  THCSOX_EINVAL = -1,     /* bad sizes, grid, precision or index range */
+  THCSOX_ENOMEM = -2,     /* device allocation failed or workspace_limit too small */
+  THCSOX_EDEVICE = -3,    /* a HIP call failed; message carries hipGetErrorString */
+  THCSOX_ENONFINITE = -4, /* NaN/Inf found in an input (only where checks are on) */
+  THCSOX_ENOTDEV = -5     /* a host pointer where device memory is required (or v.v.) */
+};
+
+typedef struct thcsox_plan_s* thcsox_plan_t;
+
+/* Build a plan for one system and precompute
+ *     U_Pqs = sum_Q V_PQ X_qQ X_sQ                   (Eq. U_contraction)
+ * once, in FP64 (stored in the plan's contraction precision).
+ *   out            : receives the plan handle (host pointer).
+ *   n, naux, ntau  : > 0.
+ *   beta           : inverse temperature, > 0.
+ *   tau_host[ntau] : ascending, mirror-symmetric grid in (0, beta).
+ *   wq_host[ntau]  : quadrature weights on [0, beta] used by thcsox_energy.
+ *   X_dev[n][naux], V_dev[naux][naux] : THC factors (V symmetric).  Copied:
+ *                    the caller may free them when this call returns.
+ *   precision      : one of THCSOX_FP64 .. THCSOX_FP16X2.
+ *   workspace_limit: upper bound in bytes on everything the plan allocates
+ *                    (0 = no bound).  The number of tau points processed per
+ *                    batch shrinks to fit; THCSOX_ENOMEM if one does not fit.
+ *   hip_stream     : hipStream_t to queue work on (NULL = null stream).
+ * Synchronises the stream before returning.  The plan owns all its memory. */
+int thcsox_plan(thcsox_plan_t* out, int n, int naux, int ntau, double beta,
+                const double* tau_host, const double* wq_host,
+                const double* X_dev, const double* V_dev, int precision,
+                size_t workspace_limit, void* hip_stream);
+
+/* Sigma^SOX(tau_k) for k in [k_begin, k_end) -- the THC sequence of the paper
+ * (Eq. U_contraction and the equations that follow it):
+ *     G_Rq  = sum_u X_uR G_uq(tau)        G_wP = sum_p G_wp(tau) X_pP
+ *     A_Pqv = sum_s U_Pqs G_sv(-tau)      B_PRv = sum_q A_Pqv G_Rq
+ *     C_RvP = sum_w U_Rvw G_wP            D_PR = sum_v C_RvP B_PRv
+ *     Sig_RP = -D_PR                      Sigma_tr = sum_PR X_tR Sig_RP X_rP
+ *   G_dev[ntau][n][n]          : Green's function on the whole grid (read).
+ *   Sigma_dev[ntau][n][n]      : slots k_begin..k_end-1 are written.
+ *   Sigma_thc_dev[ntau][naux][naux] : optional (NULL to skip); slots
+ *                    k_begin..k_end-1 receive Sig_RP (as computed above; it is
+ *                    not unique, X has rank <= n).
+ * 0 <= k_begin < k_end <= ntau.  Sigma must not alias G.  Asynchronous. */
+int thcsox_sigma_sox(thcsox_plan_t p, const double* G_dev, double* Sigma_dev,
+                     double* Sigma_thc_dev, int k_begin, int k_end);
+
+/* Galitskii-Migdal dynamic energy of Eq. E2b, read as the spin-orbital form
+ * with a factor 1/2 and evaluated on the tau grid:
+ *     E = -1/2 sum_k w_k Tr[G(beta - tau_k) Sigma(tau_k)],  G(beta-tau_k) = G[ntau-1-k]
+ * accumulated in FP64 in a fixed order (bitwise reproducible).
+ *   G_dev, Sigma_dev : [ntau][n][n] device arrays.   E_host : host scalar.
+ * Synchronises the plan's stream. */
+int thcsox_energy(thcsox_plan_t p, const double* G_dev, const double* Sigma_dev,
+                  double* E_host);
+
+/* Release a plan and all its device memory.  Accepts NULL. */
+int thcsox_destroy(thcsox_plan_t p);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char* thcsox_last_error(void);
+
+/* Sizes and per-tau work of a plan, for roofline accounting. */
+typedef struct {
+  int n, naux, ntau, precision;
+  int tau_batch;              /* tau points processed per batch */
+  size_t bytes;               /* device bytes owned by the plan */
+  double mac_per_tau;         /* algorithmic multiply-adds per tau point:
+                                 2 naux^2 n^2 + naux n^3 + 2 naux^2 n + 3 naux n^2 */
+  double fused_mac_per_tau;   /* of which in the fused B/C/D kernel: 2 naux^2 n^2 */
+  double fused_bytes_per_tau; /* compulsory HBM bytes of the fused kernel per tau:
+                                 U and A once each, plus the projected G */
+} thcsox_plan_info_t;
+int thcsox_plan_info(thcsox_plan_t p, thcsox_plan_info_t* info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* THCSOX_H */

@@ -1,0 +1,88 @@
+// Kernel launchers of libthcsox (host-side declarations).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace thcsox {
+
+// Strided FP64 GEMM on matrix cores, batched over grid.z:
+//   C(i,j) = alpha * sum_k A(i,k) B(k,j) + beta * C(i,j)
+//   A(i,k) = A[b*a_b + i*a_i + k*a_k],  B(k,j) = B[b*b_b + k*b_k + j*b_j],
+//   C(i,j) = C[b*c_b + i*c_i + (j / cj_in) * cj_out + (j % cj_in) * c_j].
+// beta == 0 never reads C.
+struct Gemm64Args {
+  int M, N, K, batch;
+  double alpha, beta;
+  const double* A; int64_t a_i, a_k, a_b;
+  const double* B; int64_t b_k, b_j, b_b;
+  double* C; int64_t c_i, c_j, c_b; int64_t cj_in, cj_out;
+};
+hipError_t gemm64(const Gemm64Args& g, hipStream_t s);
+
+// GEMM over K-major operand planes in one of the four modes:
+//   C(i,j) = alpha * sum_{k < kpad} A[i][k] B[j][k]   (operand pad must be zero)
+//   A rows:  A + p*a_plane + i*lda          (i < M)
+//   B rows:  B + p*b_plane + j*ldb          (j < N)
+//   C(i,j) = C[i*c_i + (j / cj_in) * cj_out + (j % cj_in)]  (OutT = double or float)
+// If amax != nullptr, the largest |C(i,j)| is max-reduced into *amax (as the
+// bits of a non-negative double).
+struct GemmKArgs {
+  int M, N, kpad;
+  double alpha;
+  const void* A; int64_t lda, a_plane;
+  const void* B; int64_t ldb, b_plane;
+  void* C; int64_t c_i, cj_in, cj_out;
+  unsigned long long* amax;
+};
+hipError_t gemm_kmajor(int mode, bool out_f64, const GemmKArgs& g, hipStream_t s);
+
+// The fused B/C/D stage for one tau point (v split over grid.z):
+//   Dpart[z][R][P] = sum_{v in split z} (sum_q Gt[R][q] A[v][P][q]) (sum_w U[R][v][w] GXt[P][w])
+struct FusedArgs {
+  int n, naux, ldk, vsplit, vchunk;
+  const void* Gt; const void* GXt; int64_t g_plane;   // [naux][ldk] planes
+  const void* U; int64_t u_plane;                      // [naux][n][ldk] planes
+  const void* A; int64_t a_plane;                      // [n][naux][ldk] planes
+  double* Dpart;                                       // [vsplit][naux][naux]
+};
+hipError_t sox_fused(int mode, const FusedArgs& f, hipStream_t s);
+
+// Split rows of an FP64 source into the planes of a mode, scaled by the power of
+// two 2^-floor(log2(*amax)) (scale 1 if amax is null or zero):
+//   src(r1,r2,c) = src[r1*s1 + r2*s2 + c*sc],  dst plane p:
+//   dst[p*d_plane + r1*d1 + r2*d2 + c] for c < cols, zero for cols <= c < ldk.
+struct SplitArgs {
+  int rows1, rows2, cols, ldk;
+  const void* src; bool src_f32; int64_t s1, s2, sc;
+  void* dst; int64_t d1, d2, d_plane;
+  const unsigned long long* amax;
+};
+hipError_t split_planes(int mode, const SplitArgs& a, hipStream_t s);
+
+// amax[b] = max |x[b*stride + i]| for i < len, for b < batch (max-reduced).
+hipError_t absmax64(const double* x, int64_t len, int64_t stride, int batch,
+                    unsigned long long* amax, hipStream_t s);
+hipError_t fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);
+
+// Sthc[R][P] = -factor * sum_z Dpart[z][R][P], factor = product of the inverse
+// operand scales (see scale_factor in the kernel source).
+struct DReduceArgs {
+  int naux, vsplit;
+  const double* Dpart;
+  double* Sthc; int64_t s_ld;
+  const unsigned long long* amax_gt; const unsigned long long* amax_gx;
+  const unsigned long long* amax_gb; const unsigned long long* amax_a;
+  const unsigned long long* amax_u;
+};
+hipError_t dreduce(const DReduceArgs& a, hipStream_t s);
+
+// KR[(q - q0)*n + s][Q] = X[q][Q] * X[s][Q] for q in [q0, q1).
+hipError_t khatri_rao(const double* X, int n, int naux, int q0, int q1, double* KR,
+                      hipStream_t s);
+
+// tr[k] = sum_pq G[m-1-k][q][p] Sigma[k][p][q]; then E = -1/2 sum_k w[k] tr[k].
+hipError_t energy_partials(const double* G, const double* S, int n, int m, double* tr,
+                           hipStream_t s);
+hipError_t energy_final(const double* tr, const double* w, int m, double* E, hipStream_t s);
+
+}  // namespace thcsox

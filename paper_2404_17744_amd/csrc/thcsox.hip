@@ -1,0 +1,429 @@
+// C interface of libthcsox: plan construction (the U precontraction), the
+// per-tau SOX pipeline and the Galitskii-Migdal energy.  See include/thcsox.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/thcsox.h"
+#include "kernels.hpp"
+#include "mfma.hpp"
+
+using namespace thcsox;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(THCSOX_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));  \
+  } while (0)
+
+int check_dev(const void* p, const char* name) {
+  if (p == nullptr) return fail(THCSOX_EINVAL, std::string(name) + " is NULL");
+  hipPointerAttribute_t a;
+  hipError_t e = hipPointerGetAttributes(&a, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(THCSOX_ENOTDEV, std::string(name) + " is not device memory");
+  }
+  if (a.type != hipMemoryTypeDevice && a.type != hipMemoryTypeManaged)
+    return fail(THCSOX_ENOTDEV, std::string(name) + " is not device memory");
+  return 0;
+}
+
+size_t elem_size(int mode) {
+  switch (mode) {
+    case MODE_F64: return 8;
+    case MODE_F32: return 4;
+    default: return 2;
+  }
+}
+int n_planes(int mode) { return mode == MODE_BF16X3 ? 3 : mode == MODE_F16X2 ? 2 : 1; }
+
+}  // namespace
+
+struct thcsox_plan_s {
+  int n = 0, naux = 0, m = 0, mode = 0, ldk = 0, np = 1;
+  double beta = 0;
+  size_t esize = 8;
+  hipStream_t stream = nullptr;
+  std::vector<void*> allocs;
+  size_t bytes = 0, limit = 0;
+
+  double* X = nullptr;      // [n][naux]
+  double* w = nullptr;      // [m]
+  void* U = nullptr;        // planes of [naux][n][ldk]
+  int64_t u_plane = 0;
+  void* A = nullptr;        // planes of [n][naux][ldk]
+  int64_t a_plane = 0;
+  float* A32 = nullptr;     // [n][naux][ldk], split modes only
+  void* Gt = nullptr;       // planes of [naux][ldk]
+  void* GX = nullptr;
+  int64_t g_plane = 0;
+  void* Gb = nullptr;       // planes of [n][ldk]: G(-tau)^T
+  int64_t gb_plane = 0;
+  double* Gt64 = nullptr;   // [naux][n]
+  double* GX64 = nullptr;   // [naux][n]
+  double* Dpart = nullptr;  // [vsplit][naux][naux]
+  int vsplit = 1, vchunk = 1;
+  double* Sthc = nullptr;   // [naux][naux]
+  double* T1 = nullptr;     // [n][naux]
+  unsigned long long* amax = nullptr;   // [5 + m]: U, Gt, GX, (unused), A, G[k]
+  double* tr = nullptr;     // [m]
+  double* E = nullptr;      // [1]
+
+  template <typename T>
+  int alloc(T** p, size_t count) {
+    size_t b = count * sizeof(T);
+    if (b == 0) b = 16;
+    b = (b + 255) & ~size_t(255);
+    if (limit && bytes + b > limit)
+      return fail(THCSOX_ENOMEM, "workspace_limit of " + std::to_string(limit) +
+                                     " bytes is too small (need more than " +
+                                     std::to_string(bytes + b) + ")");
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, b);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(THCSOX_ENOMEM, "hipMalloc of " + std::to_string(b) + " bytes failed: " +
+                                     hipGetErrorString(e));
+    }
+    allocs.push_back(q);
+    bytes += b;
+    *p = static_cast<T*>(q);
+    return 0;
+  }
+  ~thcsox_plan_s() {
+    for (void* q : allocs) (void)hipFree(q);
+  }
+};
+
+namespace {
+
+#define TRY(expr)            \
+  do {                       \
+    int rc_ = (expr);        \
+    if (rc_ != 0) return rc_; \
+  } while (0)
+
+// U_Pqs = sum_Q V_PQ X_qQ X_sQ in FP64, chunked over q, stored in the plan's
+// operand planes.  Split modes first take max|U| (pass 0), then store (pass 1).
+int build_u(thcsox_plan_s* p, const double* V) {
+  const int n = p->n, naux = p->naux, ldk = p->ldk;
+  const hipStream_t s = p->stream;
+  size_t per_q = (size_t)n * naux * sizeof(double);
+  int qb = (int)std::max<size_t>(1, std::min<size_t>((size_t)n, (size_t(256) << 20) / per_q));
+  double* KR = nullptr;
+  TRY(p->alloc(&KR, (size_t)qb * n * naux));
+  double* Uc = nullptr;
+  if (p->mode != MODE_F64) TRY(p->alloc(&Uc, (size_t)qb * n * naux));
+  HIP_TRY(fill_u64(p->amax, 5, 0ull, s));
+  const int passes = p->mode == MODE_F64 ? 1 : 2;
+  for (int pass = 0; pass < passes; ++pass) {
+    for (int q0 = 0; q0 < n; q0 += qb) {
+      const int q1 = std::min(n, q0 + qb), qc = q1 - q0;
+      HIP_TRY(khatri_rao(p->X, n, naux, q0, q1, KR, s));
+      Gemm64Args g{};
+      g.M = naux; g.N = qc * n; g.K = naux; g.batch = 1; g.alpha = 1.0; g.beta = 0.0;
+      g.A = V; g.a_i = naux; g.a_k = 1;
+      g.B = KR; g.b_k = 1; g.b_j = naux;
+      if (p->mode == MODE_F64) {
+        g.C = static_cast<double*>(p->U) + (int64_t)q0 * ldk;
+        g.c_i = (int64_t)n * ldk; g.c_j = 1; g.cj_in = n; g.cj_out = ldk;
+      } else {
+        g.C = Uc; g.c_i = (int64_t)qc * n; g.c_j = 1; g.cj_in = (int64_t)qc * n; g.cj_out = 0;
+      }
+      HIP_TRY(gemm64(g, s));
+      if (p->mode == MODE_F64) continue;
+      if (pass == 0) {
+        HIP_TRY(absmax64(Uc, (int64_t)naux * qc * n, 0, 1, p->amax + 0, s));
+      } else {
+        SplitArgs a{};
+        a.rows1 = naux; a.rows2 = qc; a.cols = n; a.ldk = ldk;
+        a.src = Uc; a.src_f32 = false; a.s1 = (int64_t)qc * n; a.s2 = n; a.sc = 1;
+        a.dst = static_cast<char*>(p->U) + (size_t)q0 * ldk * p->esize;
+        a.d1 = (int64_t)n * ldk; a.d2 = ldk; a.d_plane = p->u_plane;
+        a.amax = p->amax + 0;
+        HIP_TRY(split_planes(p->mode, a, s));
+      }
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  // the temporaries are the last two allocations: release them
+  for (int t = 0; t < (p->mode == MODE_F64 ? 1 : 2); ++t) {
+    void* q = p->allocs.back();
+    p->allocs.pop_back();
+    (void)hipFree(q);
+  }
+  p->bytes -= ((size_t)qb * n * naux * sizeof(double) + 255) / 256 * 256 *
+              (p->mode == MODE_F64 ? 1 : 2);
+  return 0;
+}
+
+// One tau point k: Sigma[k] (and Sig_thc[k]) from G.
+int sigma_one(thcsox_plan_s* p, const double* G, double* Sigma, double* Sthc_out, int k) {
+  const int n = p->n, naux = p->naux, ldk = p->ldk, m = p->m, mode = p->mode;
+  const hipStream_t s = p->stream;
+  const int64_t nn = (int64_t)n * n;
+  const double* Gk = G + (int64_t)k * nn;
+  const double* Gbar = G + (int64_t)(m - 1 - k) * nn;
+  unsigned long long* am = p->amax;
+  HIP_TRY(fill_u64(am + 1, 4, 0ull, s));
+
+  // projections: Gt[R][q] = sum_u X[u][R] G[u][q];  GX[P][w] = sum_p G[w][p] X[p][P]
+  Gemm64Args g{};
+  g.M = naux; g.N = n; g.K = n; g.batch = 1; g.alpha = 1.0; g.beta = 0.0;
+  g.A = p->X; g.a_i = 1; g.a_k = naux;
+  g.B = Gk; g.b_k = n; g.b_j = 1;
+  g.C = p->Gt64; g.c_i = n; g.c_j = 1; g.cj_in = n; g.cj_out = 0;
+  HIP_TRY(gemm64(g, s));
+  g.B = Gk; g.b_k = 1; g.b_j = n;
+  g.C = p->GX64;
+  HIP_TRY(gemm64(g, s));
+  HIP_TRY(absmax64(p->Gt64, (int64_t)naux * n, 0, 1, am + 1, s));
+  HIP_TRY(absmax64(p->GX64, (int64_t)naux * n, 0, 1, am + 2, s));
+
+  SplitArgs sa{};
+  sa.rows1 = naux; sa.rows2 = 1; sa.cols = n; sa.ldk = ldk;
+  sa.src_f32 = false; sa.s1 = n; sa.s2 = 0; sa.sc = 1;
+  sa.d1 = ldk; sa.d2 = 0; sa.d_plane = p->g_plane;
+  sa.src = p->Gt64; sa.dst = p->Gt; sa.amax = am + 1;
+  HIP_TRY(split_planes(mode, sa, s));
+  sa.src = p->GX64; sa.dst = p->GX; sa.amax = am + 2;
+  HIP_TRY(split_planes(mode, sa, s));
+  // G(-tau)^T: row v holds G(beta - tau)[s][v] over s
+  sa.rows1 = n; sa.src = Gbar; sa.s1 = 1; sa.sc = n;
+  sa.dst = p->Gb; sa.d_plane = p->gb_plane; sa.amax = am + 5 + (m - 1 - k);
+  HIP_TRY(split_planes(mode, sa, s));
+
+  // A[v][P][q] = sum_s U[P][q][s] G(-tau)[s][v]
+  GemmKArgs ga{};
+  ga.M = n; ga.N = naux * n; ga.kpad = ldk; ga.alpha = 1.0;
+  ga.A = p->Gb; ga.lda = ldk; ga.a_plane = p->gb_plane;
+  ga.B = p->U; ga.ldb = ldk; ga.b_plane = p->u_plane;
+  ga.c_i = (int64_t)naux * ldk; ga.cj_in = n; ga.cj_out = ldk;
+  const bool split_a = (mode == MODE_BF16X3 || mode == MODE_F16X2);
+  if (mode == MODE_F64) {
+    ga.C = p->A; ga.amax = nullptr;
+    HIP_TRY(gemm_kmajor(mode, true, ga, s));
+  } else if (mode == MODE_F32) {
+    ga.C = p->A; ga.amax = nullptr;
+    HIP_TRY(gemm_kmajor(mode, false, ga, s));
+  } else {
+    ga.C = p->A32; ga.amax = am + 4;
+    HIP_TRY(gemm_kmajor(mode, false, ga, s));
+    SplitArgs s2{};
+    s2.rows1 = n * naux; s2.rows2 = 1; s2.cols = n; s2.ldk = ldk;
+    s2.src = p->A32; s2.src_f32 = true; s2.s1 = ldk; s2.s2 = 0; s2.sc = 1;
+    s2.dst = p->A; s2.d1 = ldk; s2.d2 = 0; s2.d_plane = p->a_plane; s2.amax = am + 4;
+    HIP_TRY(split_planes(mode, s2, s));
+  }
+
+  FusedArgs f{};
+  f.n = n; f.naux = naux; f.ldk = ldk; f.vsplit = p->vsplit; f.vchunk = p->vchunk;
+  f.Gt = p->Gt; f.GXt = p->GX; f.g_plane = p->g_plane;
+  f.U = p->U; f.u_plane = p->u_plane;
+  f.A = p->A; f.a_plane = p->a_plane;
+  f.Dpart = p->Dpart;
+  HIP_TRY(sox_fused(mode, f, s));
+
+  double* St = Sthc_out ? Sthc_out + (int64_t)k * naux * naux : p->Sthc;
+  DReduceArgs d{};
+  d.naux = naux; d.vsplit = p->vsplit; d.Dpart = p->Dpart; d.Sthc = St; d.s_ld = naux;
+  d.amax_gt = am + 1; d.amax_gx = am + 2; d.amax_gb = am + 5 + (m - 1 - k);
+  d.amax_a = split_a ? am + 4 : nullptr;
+  d.amax_u = (mode == MODE_F64) ? nullptr : am + 0;
+  HIP_TRY(dreduce(d, s));
+
+  // Sigma = X Sig_thc X^T
+  Gemm64Args b{};
+  b.M = n; b.N = naux; b.K = naux; b.batch = 1; b.alpha = 1.0; b.beta = 0.0;
+  b.A = p->X; b.a_i = naux; b.a_k = 1;
+  b.B = St; b.b_k = naux; b.b_j = 1;
+  b.C = p->T1; b.c_i = naux; b.c_j = 1; b.cj_in = naux; b.cj_out = 0;
+  HIP_TRY(gemm64(b, s));
+  b.N = n;
+  b.A = p->T1; b.a_i = naux; b.a_k = 1;
+  b.B = p->X; b.b_k = 1; b.b_j = naux;
+  b.C = Sigma + (int64_t)k * nn; b.c_i = n; b.c_j = 1; b.cj_in = n; b.cj_out = 0;
+  HIP_TRY(gemm64(b, s));
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* thcsox_last_error(void) { return g_last_error.c_str(); }
+
+int thcsox_plan(thcsox_plan_t* out, int n, int naux, int ntau, double beta,
+                const double* tau_host, const double* wq_host, const double* X_dev,
+                const double* V_dev, int precision, size_t workspace_limit, void* hip_stream) {
+  g_last_error.clear();
+  if (out == nullptr) return fail(THCSOX_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n <= 0 || naux <= 0 || ntau <= 0)
+    return fail(THCSOX_EINVAL, "n, naux and ntau must be positive");
+  if (!(beta > 0.0) || !std::isfinite(beta)) return fail(THCSOX_EINVAL, "beta must be > 0");
+  if (precision < THCSOX_FP64 || precision > THCSOX_FP16X2)
+    return fail(THCSOX_EINVAL, "unknown precision " + std::to_string(precision));
+  if (tau_host == nullptr || wq_host == nullptr)
+    return fail(THCSOX_EINVAL, "tau_host and wq_host are required");
+  {
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, tau_host) == hipSuccess && a.type == hipMemoryTypeDevice)
+      return fail(THCSOX_ENOTDEV, "tau_host must be host memory");
+    (void)hipGetLastError();
+    if (hipPointerGetAttributes(&a, wq_host) == hipSuccess && a.type == hipMemoryTypeDevice)
+      return fail(THCSOX_ENOTDEV, "wq_host must be host memory");
+    (void)hipGetLastError();
+  }
+  for (int k = 0; k < ntau; ++k) {
+    if (!(tau_host[k] > 0.0 && tau_host[k] < beta))
+      return fail(THCSOX_EINVAL, "tau[" + std::to_string(k) + "] is outside (0, beta)");
+    if (k > 0 && !(tau_host[k] > tau_host[k - 1]))
+      return fail(THCSOX_EINVAL, "tau grid is not ascending");
+    if (std::fabs(tau_host[k] + tau_host[ntau - 1 - k] - beta) > 1e-12 * beta)
+      return fail(THCSOX_EINVAL, "tau grid is not mirror symmetric");
+    if (!std::isfinite(wq_host[k])) return fail(THCSOX_EINVAL, "non-finite weight");
+  }
+  TRY(check_dev(X_dev, "X_dev"));
+  TRY(check_dev(V_dev, "V_dev"));
+
+  thcsox_plan_s* p = new (std::nothrow) thcsox_plan_s();
+  if (!p) return fail(THCSOX_ENOMEM, "host allocation failed");
+  auto bail = [&](int rc) { delete p; return rc; };
+  p->n = n; p->naux = naux; p->m = ntau; p->beta = beta; p->mode = precision;
+  p->ldk = (n + 31) / 32 * 32;
+  p->np = n_planes(precision);
+  p->esize = elem_size(precision);
+  p->stream = static_cast<hipStream_t>(hip_stream);
+  p->limit = workspace_limit;
+  const int64_t ldk = p->ldk;
+
+  int tiles = ((naux + 63) / 64) * ((naux + 63) / 64);
+  int vs = std::max(1, std::min(n, (2048 + tiles - 1) / tiles));
+  p->vchunk = (n + vs - 1) / vs;
+  p->vsplit = (n + p->vchunk - 1) / p->vchunk;
+
+  int rc = 0;
+  const size_t es = p->esize, np = p->np;
+  p->u_plane = (int64_t)naux * n * ldk;
+  p->a_plane = (int64_t)n * naux * ldk;
+  p->g_plane = (int64_t)naux * ldk;
+  p->gb_plane = (int64_t)n * ldk;
+  char* tmp = nullptr;
+  if ((rc = p->alloc(&p->X, (size_t)n * naux))) return bail(rc);
+  if ((rc = p->alloc(&p->w, (size_t)ntau))) return bail(rc);
+  if ((rc = p->alloc(&p->amax, (size_t)5 + ntau))) return bail(rc);
+  if ((rc = p->alloc(&p->tr, (size_t)ntau))) return bail(rc);
+  if ((rc = p->alloc(&p->E, 1))) return bail(rc);
+  if ((rc = p->alloc(&tmp, np * es * (size_t)p->u_plane))) return bail(rc);
+  p->U = tmp;
+  if ((rc = p->alloc(&tmp, np * es * (size_t)p->a_plane))) return bail(rc);
+  p->A = tmp;
+  if (precision == THCSOX_BF16X3 || precision == THCSOX_FP16X2)
+    if ((rc = p->alloc(&p->A32, (size_t)p->a_plane))) return bail(rc);
+  if ((rc = p->alloc(&tmp, np * es * (size_t)p->g_plane))) return bail(rc);
+  p->Gt = tmp;
+  if ((rc = p->alloc(&tmp, np * es * (size_t)p->g_plane))) return bail(rc);
+  p->GX = tmp;
+  if ((rc = p->alloc(&tmp, np * es * (size_t)p->gb_plane))) return bail(rc);
+  p->Gb = tmp;
+  if ((rc = p->alloc(&p->Gt64, (size_t)naux * n))) return bail(rc);
+  if ((rc = p->alloc(&p->GX64, (size_t)naux * n))) return bail(rc);
+  if ((rc = p->alloc(&p->Dpart, (size_t)p->vsplit * naux * naux))) return bail(rc);
+  if ((rc = p->alloc(&p->Sthc, (size_t)naux * naux))) return bail(rc);
+  if ((rc = p->alloc(&p->T1, (size_t)n * naux))) return bail(rc);
+
+  const hipStream_t s = p->stream;
+  auto hip_bail = [&](hipError_t e, const char* what) {
+    delete p;
+    return fail(THCSOX_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  };
+  hipError_t e;
+  if ((e = hipMemcpyAsync(p->X, X_dev, sizeof(double) * n * naux, hipMemcpyDeviceToDevice, s)))
+    return hip_bail(e, "copy X");
+  if ((e = hipMemcpyAsync(p->w, wq_host, sizeof(double) * ntau, hipMemcpyHostToDevice, s)))
+    return hip_bail(e, "copy weights");
+  // zero the operand pads once (stages only ever write the first n of ldk columns)
+  if ((e = hipMemsetAsync(p->U, 0, np * es * (size_t)p->u_plane, s))) return hip_bail(e, "zero U");
+  if ((e = hipMemsetAsync(p->A, 0, np * es * (size_t)p->a_plane, s))) return hip_bail(e, "zero A");
+  if ((rc = build_u(p, V_dev))) return bail(rc);
+  if ((e = hipStreamSynchronize(s))) return hip_bail(e, "plan synchronise");
+  *out = p;
+  return 0;
+}
+
+int thcsox_sigma_sox(thcsox_plan_t p, const double* G_dev, double* Sigma_dev,
+                     double* Sigma_thc_dev, int k_begin, int k_end) {
+  g_last_error.clear();
+  if (p == nullptr) return fail(THCSOX_EINVAL, "plan is NULL");
+  if (k_begin < 0 || k_end > p->m || k_begin >= k_end)
+    return fail(THCSOX_EINVAL, "need 0 <= k_begin < k_end <= ntau");
+  TRY(check_dev(G_dev, "G_dev"));
+  TRY(check_dev(Sigma_dev, "Sigma_dev"));
+  if (Sigma_thc_dev) TRY(check_dev(Sigma_thc_dev, "Sigma_thc_dev"));
+  const size_t gbytes = sizeof(double) * (size_t)p->m * p->n * p->n;
+  const char* g0 = reinterpret_cast<const char*>(G_dev);
+  const char* s0 = reinterpret_cast<const char*>(Sigma_dev);
+  if (s0 < g0 + gbytes && g0 < s0 + gbytes) return fail(THCSOX_EINVAL, "Sigma aliases G");
+  const hipStream_t s = p->stream;
+  const int64_t nn = (int64_t)p->n * p->n;
+  HIP_TRY(fill_u64(p->amax + 5, p->m, 0ull, s));
+  HIP_TRY(absmax64(G_dev, nn, nn, p->m, p->amax + 5, s));
+  for (int k = k_begin; k < k_end; ++k) TRY(sigma_one(p, G_dev, Sigma_dev, Sigma_thc_dev, k));
+  return 0;
+}
+
+int thcsox_energy(thcsox_plan_t p, const double* G_dev, const double* Sigma_dev,
+                  double* E_host) {
+  g_last_error.clear();
+  if (p == nullptr) return fail(THCSOX_EINVAL, "plan is NULL");
+  if (E_host == nullptr) return fail(THCSOX_EINVAL, "E_host is NULL");
+  TRY(check_dev(G_dev, "G_dev"));
+  TRY(check_dev(Sigma_dev, "Sigma_dev"));
+  const hipStream_t s = p->stream;
+  HIP_TRY(energy_partials(G_dev, Sigma_dev, p->n, p->m, p->tr, s));
+  HIP_TRY(energy_final(p->tr, p->w, p->m, p->E, s));
+  HIP_TRY(hipMemcpyAsync(E_host, p->E, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return 0;
+}
+
+int thcsox_destroy(thcsox_plan_t p) {
+  if (p == nullptr) return 0;
+  if (p->stream) (void)hipStreamSynchronize(p->stream);
+  else (void)hipDeviceSynchronize();
+  delete p;
+  return 0;
+}
+
+int thcsox_plan_info(thcsox_plan_t p, thcsox_plan_info_t* info) {
+  g_last_error.clear();
+  if (p == nullptr || info == nullptr) return fail(THCSOX_EINVAL, "NULL argument");
+  const double n = p->n, na = p->naux;
+  info->n = p->n; info->naux = p->naux; info->ntau = p->m; info->precision = p->mode;
+  info->tau_batch = 1;
+  info->bytes = p->bytes;
+  info->mac_per_tau = 2 * na * na * n * n + na * n * n * n + 2 * na * na * n + 3 * na * n * n;
+  info->fused_mac_per_tau = 2 * na * na * n * n;
+  info->fused_bytes_per_tau =
+      (double)p->np * p->esize * (2 * na * n * n + 2 * na * n);
+  return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,160 @@
+"""Python binding of libthcsox (ctypes).  Argument marshalling only: every
+step of the SOX path runs in the library's HIP kernels.  PyTorch is used for
+device memory and streams only.
+
+The module-level functions mirror the C interface one to one (same names,
+same argument order, device pointers as integers).  ``Plan`` is a small
+convenience wrapper over torch tensors.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libthcsox.so")
+
+THCSOX_FP64, THCSOX_FP32, THCSOX_BF16X3, THCSOX_FP16X2 = 0, 1, 2, 3
+PRECISIONS = {"fp64": THCSOX_FP64, "fp32": THCSOX_FP32, "bf16x3": THCSOX_BF16X3,
+              "fp16x2": THCSOX_FP16X2}
+ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENONFINITE", -5: "ENOTDEV"}
+
+# every symbol declared in include/thcsox.h
+EXPORTS = ("thcsox_plan", "thcsox_sigma_sox", "thcsox_energy", "thcsox_destroy",
+           "thcsox_last_error", "thcsox_plan_info")
+
+
+class ThcsoxError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("naux", ctypes.c_int), ("ntau", ctypes.c_int),
+                ("precision", ctypes.c_int), ("tau_batch", ctypes.c_int),
+                ("bytes", ctypes.c_size_t), ("mac_per_tau", ctypes.c_double),
+                ("fused_mac_per_tau", ctypes.c_double),
+                ("fused_bytes_per_tau", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load the compiled library; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libthcsox is not built ({LIB_PATH} missing); run "
+                               "__graft_entry__.build() or paper_2404_17744_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i, d, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+        L.thcsox_plan.argtypes = [ctypes.POINTER(vp), i, i, i, d, vp, vp, vp, vp, i, sz, vp]
+        L.thcsox_plan.restype = i
+        L.thcsox_sigma_sox.argtypes = [vp, vp, vp, vp, i, i]
+        L.thcsox_sigma_sox.restype = i
+        L.thcsox_energy.argtypes = [vp, vp, vp, ctypes.POINTER(d)]
+        L.thcsox_energy.restype = i
+        L.thcsox_destroy.argtypes = [vp]
+        L.thcsox_destroy.restype = i
+        L.thcsox_last_error.argtypes = []
+        L.thcsox_last_error.restype = ctypes.c_char_p
+        L.thcsox_plan_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
+        L.thcsox_plan_info.restype = i
+        _lib = L
+    return _lib
+
+
+def _check(rc: int) -> None:
+    if rc != 0:
+        raise ThcsoxError(rc, thcsox_last_error())
+
+
+def thcsox_last_error() -> str:
+    return lib().thcsox_last_error().decode()
+
+
+def thcsox_plan(n: int, naux: int, ntau: int, beta: float, tau_host: np.ndarray,
+                wq_host: np.ndarray, X_dev: int, V_dev: int, precision: int,
+                workspace_limit: int = 0, hip_stream: int = 0) -> ctypes.c_void_p:
+    tau = np.ascontiguousarray(tau_host, dtype=np.float64)
+    wq = np.ascontiguousarray(wq_host, dtype=np.float64)
+    h = ctypes.c_void_p()
+    _check(lib().thcsox_plan(ctypes.byref(h), n, naux, ntau, beta,
+                             tau.ctypes.data_as(ctypes.c_void_p),
+                             wq.ctypes.data_as(ctypes.c_void_p), X_dev, V_dev,
+                             precision, workspace_limit, hip_stream))
+    return h
+
+
+def thcsox_sigma_sox(plan, G_dev: int, Sigma_dev: int, Sigma_thc_dev: int | None,
+                     k_begin: int, k_end: int) -> None:
+    _check(lib().thcsox_sigma_sox(plan, G_dev, Sigma_dev, Sigma_thc_dev, k_begin, k_end))
+
+
+def thcsox_energy(plan, G_dev: int, Sigma_dev: int) -> float:
+    e = ctypes.c_double()
+    _check(lib().thcsox_energy(plan, G_dev, Sigma_dev, ctypes.byref(e)))
+    return e.value
+
+
+def thcsox_destroy(plan) -> None:
+    _check(lib().thcsox_destroy(plan))
+
+
+def thcsox_plan_info(plan) -> dict:
+    info = PlanInfo()
+    _check(lib().thcsox_plan_info(plan, ctypes.byref(info)))
+    return {f: getattr(info, f) for f, _ in PlanInfo._fields_}
+
+
+class Plan:
+    """Owns one libthcsox plan; tensors are torch CUDA (HIP) float64 tensors."""
+
+    def __init__(self, X, V, tau, w, beta: float, precision="fp64", stream=None,
+                 workspace_limit: int = 0):
+        import torch
+        if isinstance(precision, str):
+            precision = PRECISIONS[precision]
+        self.n, self.naux = X.shape
+        self.ntau = len(tau)
+        self.device = X.device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(X.device)
+        Xc = X.contiguous().to(torch.float64)
+        Vc = V.contiguous().to(torch.float64)
+        self.handle = thcsox_plan(self.n, self.naux, self.ntau, float(beta), np.asarray(tau),
+                                  np.asarray(w), Xc.data_ptr(), Vc.data_ptr(), precision,
+                                  workspace_limit, self.stream.cuda_stream)
+        self.precision = precision
+
+    def sigma(self, G, k_begin: int = 0, k_end: int | None = None, thc: bool = False,
+              out=None, out_thc=None):
+        import torch
+        k_end = self.ntau if k_end is None else k_end
+        if out is None:
+            out = torch.zeros((self.ntau, self.n, self.n), dtype=torch.float64, device=self.device)
+        if thc and out_thc is None:
+            out_thc = torch.zeros((self.ntau, self.naux, self.naux), dtype=torch.float64,
+                                  device=self.device)
+        thcsox_sigma_sox(self.handle, G.data_ptr(), out.data_ptr(),
+                         out_thc.data_ptr() if thc else None, k_begin, k_end)
+        return (out, out_thc) if thc else out
+
+    def energy(self, G, Sigma) -> float:
+        return thcsox_energy(self.handle, G.data_ptr(), Sigma.data_ptr())
+
+    def info(self) -> dict:
+        return thcsox_plan_info(self.handle)
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            thcsox_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

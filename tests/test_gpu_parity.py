@@ -1,0 +1,124 @@
+"""GPU parity: libthcsox (through its C interface) against the FP64 CPU oracle.
+
+Tolerances (max |dSigma| / max |Sigma| and |dE| in Hartree):
+  FP64 path: 1e-10 relative in Sigma and 1e-8 Ha in energy.
+  Split/reduced paths at these small sizes: 2e-6 relative in Sigma (FP32-level
+  rounding of length-n dot products, n <= 120, with FP64 accumulation over v).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import energy as oenergy
+from oracle import sox as osox
+from paper_2404_17744_amd import synth, thcsox
+
+pytestmark = pytest.mark.gpu
+
+MIXED_TOL = {"fp32": 2e-6, "bf16x3": 2e-6, "fp16x2": 2e-6}
+
+
+def _run(dev, X, V, tau, w, beta, G, precision, k0=0, k1=None, thc=False):
+    plan = thcsox.Plan(torch.from_numpy(X).to(dev), torch.from_numpy(V).to(dev), tau, w,
+                       beta, precision=precision)
+    Gd = torch.from_numpy(G).to(dev)
+    out = plan.sigma(Gd, k0, k1, thc=thc)
+    S = out[0] if thc else out
+    E = plan.energy(Gd, S) if (k0 == 0 and (k1 is None or k1 == len(tau))) else None
+    torch.cuda.synchronize()
+    res = (S.cpu().numpy(), E) + ((out[1].cpu().numpy(),) if thc else ())
+    plan.close()
+    return res
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def test_tiny_fp64_vs_bruteforce(dev):
+    """n=8, naux=32, 12 Chebyshev points: the literal six-index definition."""
+    s, tau, w, G, beta = synth.workload("sox_n8_naux32_ntau12", seed=0)
+    print("case sox_n8_naux32_ntau12 seed 0 fp64", flush=True)
+    v = osox.thc_eri(s.X, s.V)
+    ref = osox.sigma_all_tau(osox.sigma_bruteforce, G, v)
+    E_ref = oenergy.energy_tau(G, ref, w)
+    S, E, Sthc = _run(dev, s.X, s.V, tau, w, beta, G, "fp64", thc=True)
+    _, thc_ref = osox.sigma_all_tau(osox.sigma_thc_paper, G, s.X, s.V, return_thc=True)
+    assert _rel(S, ref) <= 1e-10
+    assert abs(E - E_ref) <= 1e-8
+    assert _rel(Sthc, thc_ref) <= 1e-10
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3", "fp16x2"])
+def test_ragged_tiles(dev, precision):
+    """naux=150 (two full 64-tiles and a ragged one), n=70 (ragged k padding)."""
+    s = synth.make_system(70, 150, seed=3)
+    tau, w = synth.cheb_tau_grid(8, 100.0)
+    G = synth.g0_tau(s, tau, 100.0)
+    print(f"case n70 naux150 ntau8 seed 3 {precision}", flush=True)
+    ref = osox.sigma_all_tau(osox.sigma_thc_paper, G, s.X, s.V)
+    S, E = _run(dev, s.X, s.V, tau, w, 100.0, G, precision)
+    E_ref = oenergy.energy_tau(G, ref, w)
+    err = _rel(S, ref)
+    print(f"  sigma rel err {err:.3e}  dE {E - E_ref:.3e}")
+    if precision == "fp64":
+        assert err <= 1e-10 and abs(E - E_ref) <= 1e-8
+    else:
+        assert err <= MIXED_TOL[precision]
+
+
+def test_general_nonsymmetric_g(dev):
+    """A dense non-symmetric G exercises both projections separately."""
+    s = synth.make_system(40, 100, seed=4)
+    tau, w = synth.cheb_tau_grid(6, 100.0)
+    G = synth.random_general_g(40, 6, seed=5)
+    print("case n40 naux100 ntau6 general G fp64", flush=True)
+    ref = osox.sigma_all_tau(osox.sigma_thc_paper, G, s.X, s.V)
+    S, _ = _run(dev, s.X, s.V, tau, w, 100.0, G, "fp64")
+    assert _rel(S, ref) <= 1e-10
+
+
+def test_tau_slices_compose(dev):
+    """Two slices [0,3) and [3,m) fill the same result as one full call."""
+    s, tau, w, G, beta = synth.workload("sox_n8_naux32_ntau12", seed=1)
+    X = torch.from_numpy(s.X).to(dev); V = torch.from_numpy(s.V).to(dev)
+    Gd = torch.from_numpy(G).to(dev)
+    plan = thcsox.Plan(X, V, tau, w, beta, precision="fp64")
+    full = plan.sigma(Gd)
+    part = torch.zeros_like(full)
+    plan.sigma(Gd, 0, 3, out=part)
+    plan.sigma(Gd, 3, len(tau), out=part)
+    torch.cuda.synchronize()
+    assert torch.equal(full, part)
+    again = plan.sigma(Gd)
+    torch.cuda.synchronize()
+    assert torch.equal(full, again), "not bitwise reproducible"
+    plan.close()
+
+
+def test_errors(dev):
+    s, tau, w, G, beta = synth.workload("sox_n8_naux32_ntau12", seed=0)
+    X = torch.from_numpy(s.X).to(dev); V = torch.from_numpy(s.V).to(dev)
+    with pytest.raises(thcsox.ThcsoxError) as e:
+        thcsox.thcsox_plan(8, 32, 12, beta, tau, w, s.X.ctypes.data, V.data_ptr(), 0)
+    assert e.value.code == -5
+    bad = tau.copy(); bad[3] += 0.1
+    with pytest.raises(thcsox.ThcsoxError) as e:
+        thcsox.thcsox_plan(8, 32, 12, beta, bad, w, X.data_ptr(), V.data_ptr(), 0)
+    assert e.value.code == -1
+    with pytest.raises(thcsox.ThcsoxError) as e:
+        thcsox.thcsox_plan(8, 32, 12, beta, tau, w, X.data_ptr(), V.data_ptr(), 7)
+    assert e.value.code == -1
+    with pytest.raises(thcsox.ThcsoxError) as e:
+        thcsox.thcsox_plan(8, 32, 12, beta, tau, w, X.data_ptr(), V.data_ptr(), 0,
+                           workspace_limit=1024)
+    assert e.value.code == -2
+    plan = thcsox.Plan(X, V, tau, w, beta)
+    Gd = torch.from_numpy(G).to(dev)
+    with pytest.raises(thcsox.ThcsoxError) as e:
+        plan.sigma(Gd, 5, 5)
+    assert e.value.code == -1
+    with pytest.raises(thcsox.ThcsoxError) as e:
+        thcsox.thcsox_sigma_sox(plan.handle, Gd.data_ptr(), Gd.data_ptr(), None, 0, 12)
+    assert e.value.code == -1
+    plan.close()
