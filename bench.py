@@ -1,0 +1,187 @@
+#!/usr/bin/env python3
+"""Throughput of the THC-SOX self-energy on one MI355X.
+
+One step = one full Sigma^SOX(tau) evaluation over every tau point of the
+workload plus its Galitskii-Migdal energy, inputs resident in HBM (the plan,
+i.e. the one-time U precontraction, is built before timing and reported
+separately).  The headline runs the mixed-precision path; the FP64 path is
+timed beside it and the energy of both is compared with the stored FP64 oracle
+value of the same seeded inputs.
+
+    python bench.py [--steps K] [--warmup W] [--precision fp16x2] [--gpus 1]
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "SOX Σ(τ) τ-points/s + MFMA util at N=300; mixed vs FP64 at ≤1e-6 Ha"
+# MI355X published dense peaks (TFLOP/s) of the matrix-core type each mode issues.
+PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "fp16x2": 2500.0}
+PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 6, "fp16x2": 3}
+HBM_PEAK_GBS = 8000.0
+
+
+def timed_steps(plan, Gd, S, steps, torch):
+    """Run `steps` steps between two events on the plan's stream; returns
+    (ms per step, last energy, stage times)."""
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    plan.profile(True)
+    e0.record(plan.stream)
+    E = None
+    for _ in range(steps):
+        plan.sigma(Gd, out=S)
+        E = plan.energy(Gd, S)
+    e1.record(plan.stream)
+    torch.cuda.synchronize()
+    st = plan.stage_times()
+    plan.profile(False)
+    return e0.elapsed_time(e1) / steps, E, st
+
+
+def cpu_baseline(s, G, taus):
+    """The FP64 oracle (the paper's sequence) on a few tau points, host cores."""
+    import numpy as np
+    from oracle import sox as osox
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([t.get("num_threads", 1) for t in threadpool_info()
+                       if t.get("user_api") == "blas"] or [1])
+    except Exception:
+        threads = os.cpu_count()
+    t0 = time.time()
+    U = osox.precontract_u(s.X, s.V)
+    t_u = time.time() - t0
+    m = G.shape[0]
+    t0 = time.time()
+    for k in taus:
+        osox.sigma_thc_paper(s.X, s.V, G[k], G[m - 1 - k], U=U)
+    dt = time.time() - t0
+    return {"value": len(taus) / dt, "unit": "tau-points/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{len(taus)} of {m} tau points (k={list(taus)}) of the same workload, "
+                      f"FP64 NumPy, {dt:.1f} s; U precontraction excluded ({t_u:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="fp16x2", choices=list(PEAK))
+    ap.add_argument("--workload", default="sox_n300_naux1800_ntau100")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--fp64-steps", type=int, default=1)
+    ap.add_argument("--cpu-taus", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU's share only: the SOX self-energy shards over tau "
+              "points with no communication, so run it with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2404_17744_amd import synth, thcsox
+
+    dev = torch.device("cuda:0")
+    s, tau, w, G, beta = synth.workload(args.workload, seed=args.seed)
+    m = len(tau)
+    X = torch.from_numpy(s.X).to(dev)
+    V = torch.from_numpy(s.V).to(dev)
+    Gd = torch.from_numpy(G).to(dev)
+    S = torch.zeros_like(Gd)
+
+    t0 = time.time()
+    plan = thcsox.Plan(X, V, tau, w, beta, precision=args.precision)
+    plan_s = time.time() - t0
+    info = plan.info()
+    for _ in range(args.warmup):
+        plan.sigma(Gd, out=S)
+        plan.energy(Gd, S)
+    ms, E_mixed, st = timed_steps(plan, Gd, S, args.steps, torch)
+    S_mixed = S.clone()
+    plan.close()
+
+    fused_ms, fused_n = st["fused"]
+    fused_avg = fused_ms / max(1, fused_n)
+    fused_flop = 2.0 * info["fused_mac_per_tau"]
+    achieved = fused_flop / (fused_avg * 1e-3) / 1e12
+    peak = PEAK[args.precision]
+
+    # FP64 path beside it
+    fp64 = None
+    if args.fp64_steps > 0:
+        p64 = thcsox.Plan(X, V, tau, w, beta, precision="fp64")
+        S64 = torch.zeros_like(Gd)
+        p64.sigma(Gd, 0, 2, out=S64)
+        ms64, E64, st64 = timed_steps(p64, Gd, S64, args.fp64_steps, torch)
+        f64_avg = st64["fused"][0] / max(1, st64["fused"][1])
+        fp64 = {"tau_points_per_s": m / (ms64 * 1e-3), "ms_per_step": ms64, "E_sox": E64,
+                "fused_tflops": fused_flop / (f64_avg * 1e-3) / 1e12,
+                "fused_frac_of_fp64_peak": fused_flop / (f64_avg * 1e-3) / 1e12 / PEAK["fp64"]}
+        d = (S_mixed - S64).abs().max().item() / S64.abs().max().item()
+        fp64["mixed_sigma_rel_err_vs_gpu_fp64"] = d
+        fp64["mixed_energy_err_vs_gpu_fp64"] = E_mixed - E64
+        p64.close()
+
+    accuracy = {"E_sox": E_mixed}
+    gold = os.path.join(ROOT, "tests", "golden", f"oracle_{args.workload}_seed{args.seed}.json")
+    if os.path.exists(gold):
+        with open(gold) as f:
+            g = json.load(f)
+        if g.get("input_digest") == s.digest():
+            accuracy["E_oracle"] = g["E_sox"]
+            accuracy["energy_err_vs_fp64_oracle_Ha"] = E_mixed - g["E_sox"]
+            if fp64:
+                accuracy["fp64_path_energy_err_vs_oracle_Ha"] = fp64["E_sox"] - g["E_sox"]
+            Sm = S_mixed.cpu().numpy()
+            errs = [abs(Sm[k, t, r] - v) for k, t, r, v in g["samples"]]
+            accuracy["sigma_sampled_rel_err_vs_oracle"] = max(errs) / g["sigma_absmax"]
+
+    out = {
+        "metric": METRIC,
+        "value": m / (ms * 1e-3),
+        "unit": "tau-points/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": s.n, "naux": s.naux, "ntau": m,
+                   "beta": beta, "seed": args.seed, "precision": args.precision,
+                   "parallelism": "none (one GPU; tau points are independent)"},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": f"fused_kernel<{args.precision}>",
+                     "avg_launch_ms": fused_avg, "launches": fused_n,
+                     "algorithmic_flop_per_launch": fused_flop,
+                     "plane_products": PRODUCTS[args.precision],
+                     "mfma_busy_frac": achieved * PRODUCTS[args.precision] / peak},
+        "tflops_whole_step": 2.0 * info["mac_per_tau"] * m / (ms * 1e-3) / 1e12,
+        "stage_ms_per_step": {k: v[0] / args.steps for k, v in st.items()},
+        "plan_s": plan_s,
+        "fp64_path": fp64,
+        "speedup_vs_fp64_path": (m / (ms * 1e-3)) / fp64["tau_points_per_s"] if fp64 else None,
+        "accuracy": accuracy,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(s, G, list(range(args.cpu_taus)))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

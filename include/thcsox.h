@@ -130,6 +130,26 @@ typedef struct {
 } thcsox_plan_info_t;
 int thcsox_plan_info(thcsox_plan_t p, thcsox_plan_info_t* info);
 
+/* Optional stage timing with HIP events recorded on the plan's stream around
+ * each stage of every tau point (negligible overhead).  Stages:
+ *   THCSOX_STAGE_PROJECT : projections G_Rq, G_wP, G(-tau) and their scaling/splits
+ *   THCSOX_STAGE_A       : A_Pqv = sum_s U_Pqs G_sv(-tau) (and its split)
+ *   THCSOX_STAGE_FUSED   : the fused B/C/D kernel
+ *   THCSOX_STAGE_BACK    : reduction of D, Sig_RP and the back-projection
+ * thcsox_profile(p, 1) starts recording (and clears what was recorded);
+ * thcsox_stage_times synchronises the stream and returns, per stage, the total
+ * milliseconds and the number of timed launches since the last read, then clears. */
+enum {
+  THCSOX_STAGE_PROJECT = 0,
+  THCSOX_STAGE_A = 1,
+  THCSOX_STAGE_FUSED = 2,
+  THCSOX_STAGE_BACK = 3,
+  THCSOX_NSTAGES = 4
+};
+int thcsox_profile(thcsox_plan_t p, int enable);
+int thcsox_stage_times(thcsox_plan_t p, double* ms /*[THCSOX_NSTAGES]*/,
+                       int* launches /*[THCSOX_NSTAGES]*/);
+
 #ifdef __cplusplus
 }
 #endif

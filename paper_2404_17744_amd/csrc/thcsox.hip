@@ -82,6 +82,12 @@ struct thcsox_plan_s {
   double* Sthc = nullptr;   // [naux][naux]
   double* T1 = nullptr;     // [n][naux]
   unsigned long long* amax = nullptr;   // [5 + m]: U, Gt, GX, (unused), A, G[k]
+  // optional per-stage timing with events on the plan's stream
+  bool profiling = false;
+  struct Timer {
+    std::vector<hipEvent_t> start, stop;
+    size_t used = 0;
+  } timers[THCSOX_NSTAGES];
   double* tr = nullptr;     // [m]
   double* E = nullptr;      // [1]
 
@@ -107,7 +113,25 @@ struct thcsox_plan_s {
     return 0;
   }
   ~thcsox_plan_s() {
+    for (auto& t : timers) {
+      for (hipEvent_t e : t.start) (void)hipEventDestroy(e);
+      for (hipEvent_t e : t.stop) (void)hipEventDestroy(e);
+    }
     for (void* q : allocs) (void)hipFree(q);
+  }
+  hipError_t mark(int stage, bool begin) {
+    if (!profiling) return hipSuccess;
+    Timer& t = timers[stage];
+    if (begin && t.used == t.start.size()) {
+      hipEvent_t a, b;
+      hipError_t e = hipEventCreate(&a);
+      if (e != hipSuccess) return e;
+      if ((e = hipEventCreate(&b)) != hipSuccess) return e;
+      t.start.push_back(a);
+      t.stop.push_back(b);
+    }
+    if (begin) return hipEventRecord(t.start[t.used], stream);
+    return hipEventRecord(t.stop[t.used++], stream);
   }
 };
 
@@ -181,6 +205,7 @@ int sigma_one(thcsox_plan_s* p, const double* G, double* Sigma, double* Sthc_out
   const double* Gk = G + (int64_t)k * nn;
   const double* Gbar = G + (int64_t)(m - 1 - k) * nn;
   unsigned long long* am = p->amax;
+  HIP_TRY(p->mark(THCSOX_STAGE_PROJECT, true));
   HIP_TRY(fill_u64(am + 1, 4, 0ull, s));
 
   // projections: Gt[R][q] = sum_u X[u][R] G[u][q];  GX[P][w] = sum_p G[w][p] X[p][P]
@@ -208,8 +233,10 @@ int sigma_one(thcsox_plan_s* p, const double* G, double* Sigma, double* Sthc_out
   sa.rows1 = n; sa.src = Gbar; sa.s1 = 1; sa.sc = n;
   sa.dst = p->Gb; sa.d_plane = p->gb_plane; sa.amax = am + 5 + (m - 1 - k);
   HIP_TRY(split_planes(mode, sa, s));
+  HIP_TRY(p->mark(THCSOX_STAGE_PROJECT, false));
 
   // A[v][P][q] = sum_s U[P][q][s] G(-tau)[s][v]
+  HIP_TRY(p->mark(THCSOX_STAGE_A, true));
   GemmKArgs ga{};
   ga.M = n; ga.N = naux * n; ga.kpad = ldk; ga.alpha = 1.0;
   ga.A = p->Gb; ga.lda = ldk; ga.a_plane = p->gb_plane;
@@ -232,13 +259,18 @@ int sigma_one(thcsox_plan_s* p, const double* G, double* Sigma, double* Sthc_out
     HIP_TRY(split_planes(mode, s2, s));
   }
 
+  HIP_TRY(p->mark(THCSOX_STAGE_A, false));
+
   FusedArgs f{};
   f.n = n; f.naux = naux; f.ldk = ldk; f.vsplit = p->vsplit; f.vchunk = p->vchunk;
   f.Gt = p->Gt; f.GXt = p->GX; f.g_plane = p->g_plane;
   f.U = p->U; f.u_plane = p->u_plane;
   f.A = p->A; f.a_plane = p->a_plane;
   f.Dpart = p->Dpart;
+  HIP_TRY(p->mark(THCSOX_STAGE_FUSED, true));
   HIP_TRY(sox_fused(mode, f, s));
+  HIP_TRY(p->mark(THCSOX_STAGE_FUSED, false));
+  HIP_TRY(p->mark(THCSOX_STAGE_BACK, true));
 
   double* St = Sthc_out ? Sthc_out + (int64_t)k * naux * naux : p->Sthc;
   DReduceArgs d{};
@@ -260,6 +292,7 @@ int sigma_one(thcsox_plan_s* p, const double* G, double* Sigma, double* Sthc_out
   b.B = p->X; b.b_k = 1; b.b_j = naux;
   b.C = Sigma + (int64_t)k * nn; b.c_i = n; b.c_j = 1; b.cj_in = n; b.cj_out = 0;
   HIP_TRY(gemm64(b, s));
+  HIP_TRY(p->mark(THCSOX_STAGE_BACK, false));
   return 0;
 }
 
@@ -423,6 +456,35 @@ int thcsox_plan_info(thcsox_plan_t p, thcsox_plan_info_t* info) {
   info->fused_mac_per_tau = 2 * na * na * n * n;
   info->fused_bytes_per_tau =
       (double)p->np * p->esize * (2 * na * n * n + 2 * na * n);
+  return 0;
+}
+
+int thcsox_profile(thcsox_plan_t p, int enable) {
+  g_last_error.clear();
+  if (p == nullptr) return fail(THCSOX_EINVAL, "plan is NULL");
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  p->profiling = enable != 0;
+  for (auto& t : p->timers) t.used = 0;
+  return 0;
+}
+
+int thcsox_stage_times(thcsox_plan_t p, double* ms, int* launches) {
+  g_last_error.clear();
+  if (p == nullptr || ms == nullptr || launches == nullptr)
+    return fail(THCSOX_EINVAL, "NULL argument");
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  for (int st = 0; st < THCSOX_NSTAGES; ++st) {
+    auto& t = p->timers[st];
+    double tot = 0.0;
+    for (size_t i = 0; i < t.used; ++i) {
+      float e = 0.f;
+      HIP_TRY(hipEventElapsedTime(&e, t.start[i], t.stop[i]));
+      tot += e;
+    }
+    ms[st] = tot;
+    launches[st] = (int)t.used;
+    t.used = 0;
+  }
   return 0;
 }
 

@@ -22,7 +22,8 @@ ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENONFINITE", -5: "ENOT
 
 # every symbol declared in include/thcsox.h
 EXPORTS = ("thcsox_plan", "thcsox_sigma_sox", "thcsox_energy", "thcsox_destroy",
-           "thcsox_last_error", "thcsox_plan_info")
+           "thcsox_last_error", "thcsox_plan_info", "thcsox_profile", "thcsox_stage_times")
+STAGES = ("project", "a_stage", "fused", "back")
 
 
 class ThcsoxError(RuntimeError):
@@ -63,6 +64,10 @@ def lib() -> ctypes.CDLL:
         L.thcsox_last_error.restype = ctypes.c_char_p
         L.thcsox_plan_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
         L.thcsox_plan_info.restype = i
+        L.thcsox_profile.argtypes = [vp, i]
+        L.thcsox_profile.restype = i
+        L.thcsox_stage_times.argtypes = [vp, ctypes.POINTER(d), ctypes.POINTER(i)]
+        L.thcsox_stage_times.restype = i
         _lib = L
     return _lib
 
@@ -110,6 +115,17 @@ def thcsox_plan_info(plan) -> dict:
     return {f: getattr(info, f) for f, _ in PlanInfo._fields_}
 
 
+def thcsox_profile(plan, enable: bool) -> None:
+    _check(lib().thcsox_profile(plan, 1 if enable else 0))
+
+
+def thcsox_stage_times(plan) -> dict:
+    ms = (ctypes.c_double * len(STAGES))()
+    cnt = (ctypes.c_int * len(STAGES))()
+    _check(lib().thcsox_stage_times(plan, ms, cnt))
+    return {st: (ms[i], cnt[i]) for i, st in enumerate(STAGES)}
+
+
 class Plan:
     """Owns one libthcsox plan; tensors are torch CUDA (HIP) float64 tensors."""
 
@@ -147,6 +163,13 @@ class Plan:
 
     def info(self) -> dict:
         return thcsox_plan_info(self.handle)
+
+    def profile(self, enable: bool = True) -> None:
+        thcsox_profile(self.handle, enable)
+
+    def stage_times(self) -> dict:
+        """{stage: (total ms, launches)} since the last read."""
+        return thcsox_stage_times(self.handle)
 
     def close(self) -> None:
         if getattr(self, "handle", None):
