@@ -1,0 +1,301 @@
+// The fused B/C/D stage of the THC-SOX sequence (one tau point):
+//
+//   D_PR = sum_v C_RvP B_PRv,   B_PRv = sum_q G_Rq A_Pqv,   C_RvP = sum_w U_Rvw G_wP
+//
+// A workgroup owns a TR (R) x TP (P) tile of D and a range of v.  For every v
+// it forms both length-n contractions on matrix cores,
+//   accB[R][P] = sum_q Gt[R][q] A[v][P][q]      accC[R][P] = sum_w U[R][v][w] GXt[P][w]
+// which land in the same MFMA output layout, so B o C is a register-to-register
+// product.  In FP64 mode it is accumulated in FP64 registers; in the other modes
+// in FP32 registers for at most FLUSH_V consecutive v, then added into the
+// workgroup's FP64 tile of D in global memory (which only that workgroup
+// touches), so the sum over v is FP64 across chunks.  Neither B (naux^2 n) nor
+// C ever reaches memory.  Operands are staged through LDS one (v, 32-wide k chunk) stage at a
+// time; the next stage's global loads are issued before the current stage's
+// MFMAs (register prefetch), so loads overlap the matrix work.
+#include <type_traits>
+
+#include "kernels.hpp"
+#include "mfma.hpp"
+#include "panel.hpp"
+
+namespace thcsox {
+namespace {
+
+constexpr int FLUSH_V = 8;   // v per FP32 partial sum of D before it is added in FP64
+constexpr int NXCD = 8;      // accelerator complex dies of an MI355X
+constexpr int BAND = 4;      // R blocks per band of the tile walk
+
+// MFMA tiles per wave (rows x cols); the workgroup is 2 x 2 waves.  Sized so
+// that two stages of operand panels fit the 160 KiB of LDS.
+template <int M> struct FusedCfg;
+template <> struct FusedCfg<MODE_F64> { static constexpr int WTI = 2, WTJ = 2; };
+template <> struct FusedCfg<MODE_F32> { static constexpr int WTI = 4, WTJ = 3; };
+#ifndef THCSOX_BF_ROWS
+#define THCSOX_BF_ROWS 3
+#endif
+#ifndef THCSOX_BF_COLS
+#define THCSOX_BF_COLS 3
+#endif
+template <> struct FusedCfg<MODE_BF16X3> {
+  static constexpr int WTI = THCSOX_BF_ROWS, WTJ = THCSOX_BF_COLS;
+};
+#ifndef THCSOX_WT_ROWS
+#define THCSOX_WT_ROWS 4
+#endif
+#ifndef THCSOX_WT_COLS
+#define THCSOX_WT_COLS 3
+#endif
+template <> struct FusedCfg<MODE_F16X2> {
+  static constexpr int WTI = THCSOX_WT_ROWS, WTJ = THCSOX_WT_COLS;
+};
+
+template <int M, bool AF32>
+__global__ __launch_bounds__(NT) void fused_kernel(FusedArgs f) {
+  using MT = ModeT<M>;
+  using T = typename MT::T;
+  constexpr int NP = MT::NP, KS = MT::KS, LD = lds_ld<T>();
+  constexpr int WTI = FusedCfg<M>::WTI, WTJ = FusedCfg<M>::WTJ;
+  constexpr int TR = 32 * WTI, TP = 32 * WTJ;
+  constexpr int ES = (int)sizeof(T);
+  using PR = Products<NP>;
+  // two stages of panels: one is read by the matrix cores while the next is written
+  __shared__ __attribute__((aligned(16))) T sG[2][NP][TR * LD];
+  __shared__ __attribute__((aligned(16))) T sU[2][NP][TR * LD];
+  __shared__ __attribute__((aligned(16))) T sA[2][NP][TP * LD];
+  __shared__ __attribute__((aligned(16))) T sX[2][NP][TP * LD];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  // XCD-aware placement.  Workgroups are dealt round-robin to the XCDs, so
+  // workgroup b runs on XCD b % NXCD.  Each XCD takes the v ranges z = xcd,
+  // xcd + NXCD, ... for every tile, and walks the tiles in bands of BAND R
+  // blocks, P block by P block: the workgroups resident on one XCD at a time
+  // form a compact BAND x (CUs per XCD / BAND) block of tiles at the same v,
+  // which share the U_v and A_v panels through that XCD's L2.
+  const int nrb = (f.naux + TR - 1) / TR, npb = (f.naux + TP - 1) / TP;
+  const int tiles = nrb * npb;
+  const int b = blockIdx.x;
+  const int xcd = b % NXCD, local = b / NXCD;
+  const int z = xcd + NXCD * (local / tiles);
+  const int to = local % tiles;
+  const int band = to / (BAND * npb);
+  const int rb0 = band * BAND, bh = min(BAND, nrb - rb0);
+  const int within = to - rb0 * npb;
+  const int P0 = (within / bh) * TP, R0 = (rb0 + within % bh) * TR;
+  const int v_lo = z * f.vchunk;
+  const int v_hi = min(f.n, v_lo + f.vchunk);
+  const int kst = f.ldk / BK;
+  const int nstage = (v_hi > v_lo) ? (v_hi - v_lo) * kst : 0;
+  const int64_t ldk = f.ldk;
+  const int64_t u_row = (int64_t)f.n * ldk;        // elements between R rows of U
+  const int64_t a_v = (int64_t)f.naux * ldk;       // elements between v slabs of A
+  const float a_scale = AF32 ? (float)pow2_scale_f(f.amax_a) : 1.f;
+  const int rows_r = min(TR, f.naux - R0), rows_p = min(TP, f.naux - P0);
+
+  const T* Gt = static_cast<const T*>(f.Gt) + R0 * ldk;
+  const T* GX = static_cast<const T*>(f.GXt) + P0 * ldk;
+  const T* U = static_cast<const T*>(f.U) + R0 * u_row;
+  __amdgpu_buffer_rsrc_t rG[NP], rX[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    rG[p] = make_rsrc(Gt + p * f.g_plane, TR * ldk * ES);
+    rX[p] = make_rsrc(GX + p * f.g_plane, TP * ldk * ES);
+  }
+
+  Panel<T, TR> pG[NP], pU[NP];
+  Panel<T, TP> pX[NP];
+  Panel<T, TP> pA[AF32 ? 1 : NP];
+  PanelF32<M == MODE_F64 || M == MODE_F32 ? MODE_F16X2 : M, TP> pA32;
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    pG[p].init(ldk, rows_r, tid);
+    pU[p].init(u_row, rows_r, tid);
+    pX[p].init(ldk, rows_p, tid);
+    if constexpr (!AF32) pA[p].init(ldk, rows_p, tid);
+  }
+  if constexpr (AF32) pA32.init(ldk, rows_p, tid);
+
+  auto load_stage = [&](int v, int k0) {
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      pG[p].load(rG[p], k0);
+      pX[p].load(rX[p], k0);
+      pU[p].load(make_rsrc(U + p * f.u_plane + v * ldk, TR * u_row * ES), k0);
+    }
+    if constexpr (AF32) {
+      pA32.load(make_rsrc(static_cast<const float*>(f.A) + v * a_v + P0 * ldk, TP * ldk * 4), k0);
+    } else {
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+        pA[p].load(make_rsrc(static_cast<const T*>(f.A) + p * f.a_plane + v * a_v + P0 * ldk,
+                             TP * ldk * ES),
+                   k0);
+    }
+  };
+
+  using DAcc = typename std::conditional<M == MODE_F64, double, float>::type;
+  typename MT::Acc accB[WTI][WTJ], accC[WTI][WTJ];
+  DAcc accD[WTI][WTJ][4];
+#pragma unroll
+  for (int ti = 0; ti < WTI; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < WTJ; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        accB[ti][tj][r] = 0;
+        accC[ti][tj][r] = 0;
+        accD[ti][tj][r] = 0;
+      }
+  double* D = f.Dpart + (int64_t)z * f.naux * f.naux;
+  // add (or, the first time, store) the register partial sums into the FP64 tile
+  auto flush = [&](bool first) {
+#pragma unroll
+    for (int ti = 0; ti < WTI; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < WTJ; ++tj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int R = R0 + wr * 16 * WTI + 16 * ti + out_row<M>(lane, r);
+          const int P = P0 + wc * 16 * WTJ + 16 * tj + (lane & 15);
+          if (R < f.naux && P < f.naux) {
+            double* d = D + (int64_t)R * f.naux + P;
+            *d = (first ? 0.0 : *d) + (double)accD[ti][tj][r];
+          }
+          accD[ti][tj][r] = 0;
+        }
+  };
+  int nv = 0;
+
+  // stage sequence: (v, ks) for v in [v_lo, v_hi), ks in [0, kst); (lv, lk) is the
+  // next stage to fetch from global memory
+  int lv = v_lo, lk = 0;
+  auto fetch_next = [&]() {
+    load_stage(lv, lk * BK);
+    if (++lk == kst) { lk = 0; ++lv; }
+  };
+  auto put = [&](int buf) {
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      pG[p].store(sG[buf][p], tid);
+      pU[p].store(sU[buf][p], tid);
+      pX[p].store(sX[buf][p], tid);
+    }
+    if constexpr (AF32) {
+      T* planes[NP];
+#pragma unroll
+      for (int p = 0; p < NP; ++p) planes[p] = sA[buf][p];
+      pA32.store(planes, a_scale, tid);
+    } else {
+#pragma unroll
+      for (int p = 0; p < NP; ++p) pA[p].store(sA[buf][p], tid);
+    }
+  };
+  // acc[ti][tj] += sum_k rows(sr) x rows(sc) over this stage's 32-wide k range
+  auto gemm = [&](typename MT::Acc (&acc)[WTI][WTJ], T (*sr)[TR * LD], T (*sc)[TP * LD]) {
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += KS) {
+      typename MT::Frag fr[WTI][NP], fc[WTJ][NP];
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+#pragma unroll
+        for (int ti = 0; ti < WTI; ++ti)
+          fr[ti][p] = lds_frag<M>(sr[p], LD, wr * 16 * WTI + 16 * ti, kk, lane);
+#pragma unroll
+        for (int tj = 0; tj < WTJ; ++tj)
+          fc[tj][p] = lds_frag<M>(sc[p], LD, wc * 16 * WTJ + 16 * tj, kk, lane);
+      }
+#pragma unroll
+      for (int q = 0; q < PR::N; ++q)
+#pragma unroll
+        for (int ti = 0; ti < WTI; ++ti)
+#pragma unroll
+          for (int tj = 0; tj < WTJ; ++tj)
+            acc[ti][tj] = mfma1(fr[ti][PR::a(q)], fc[tj][PR::b(q)], acc[ti][tj]);
+    }
+  };
+
+  if (nstage > 0) {
+    fetch_next();
+    put(0);
+  }
+  if (nstage > 1) fetch_next();
+  __syncthreads();
+  int t = 0;
+  for (int v = v_lo; v < v_hi; ++v) {
+#pragma unroll
+    for (int ti = 0; ti < WTI; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < WTJ; ++tj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          accB[ti][tj][r] = 0;
+          accC[ti][tj][r] = 0;
+        }
+    for (int ks = 0; ks < kst; ++ks, ++t) {
+      const int cur = t & 1;
+      gemm(accB, sG[cur], sA[cur]);
+      // while those run: stage t+1 (already in registers) into the other buffer,
+      // and start fetching stage t+2
+      if (t + 1 < nstage) put(cur ^ 1);
+      if (t + 2 < nstage) fetch_next();
+      gemm(accC, sU[cur], sX[cur]);
+      __syncthreads();
+    }
+    // all k of this v done: D += B o C
+#pragma unroll
+    for (int ti = 0; ti < WTI; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < WTJ; ++tj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          accD[ti][tj][r] = fma((DAcc)accB[ti][tj][r], (DAcc)accC[ti][tj][r], accD[ti][tj][r]);
+    ++nv;
+    if (M != MODE_F64 && (nv % FLUSH_V == 0) && v + 1 < v_hi) flush(nv == FLUSH_V);
+  }
+  // final flush (also writes zeros for an empty v range)
+  flush(M == MODE_F64 || nv <= FLUSH_V);
+}
+
+inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+}  // namespace
+
+template <int M> void tile_of(int* rows, int* cols) {
+  *rows = 32 * FusedCfg<M>::WTI;
+  *cols = 32 * FusedCfg<M>::WTJ;
+}
+
+void fused_tile(int mode, int* rows, int* cols) {
+  switch (mode) {
+    case MODE_F64: tile_of<MODE_F64>(rows, cols); break;
+    case MODE_F32: tile_of<MODE_F32>(rows, cols); break;
+    case MODE_BF16X3: tile_of<MODE_BF16X3>(rows, cols); break;
+    default: tile_of<MODE_F16X2>(rows, cols); break;
+  }
+}
+
+int fused_xcds() { return NXCD; }
+
+hipError_t sox_fused(int mode, const FusedArgs& f, hipStream_t s) {
+  int TR, TP;
+  fused_tile(mode, &TR, &TP);
+  if (f.vsplit % NXCD != 0 || (int64_t)f.vsplit * f.vchunk < f.n) return hipErrorInvalidValue;
+  dim3 grid(cdiv(f.naux, TP) * cdiv(f.naux, TR) * f.vsplit);
+  switch (mode) {
+    case MODE_F64: fused_kernel<MODE_F64, false><<<grid, NT, 0, s>>>(f); break;
+    case MODE_F32: fused_kernel<MODE_F32, false><<<grid, NT, 0, s>>>(f); break;
+    case MODE_BF16X3:
+      if (f.a_f32) fused_kernel<MODE_BF16X3, true><<<grid, NT, 0, s>>>(f);
+      else fused_kernel<MODE_BF16X3, false><<<grid, NT, 0, s>>>(f);
+      break;
+    case MODE_F16X2:
+      if (f.a_f32) fused_kernel<MODE_F16X2, true><<<grid, NT, 0, s>>>(f);
+      else fused_kernel<MODE_F16X2, false><<<grid, NT, 0, s>>>(f);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace thcsox

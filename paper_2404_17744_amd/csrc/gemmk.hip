@@ -1,0 +1,149 @@
+// GEMM over K-major operand planes on matrix cores, used for the A stage
+//     A_Pqv = sum_s U_Pqs G_sv(-tau)
+// as C(i, j) = alpha * sum_k Aop[i][k] Bop[j][k] with the rows of U as Aop
+// (i = (P, q), naux * n rows, streamed once) and the rows of G(-tau)^T as Bop
+// (j = v, n rows, re-read from L2 by every workgroup).  A workgroup owns a
+// (32 WTI) x (32 WTJ) tile; the next 32-wide k panel is prefetched into
+// registers while the current one runs on the matrix cores.
+#include "kernels.hpp"
+#include "mfma.hpp"
+#include "panel.hpp"
+
+namespace thcsox {
+namespace {
+
+__device__ __forceinline__ double wave_max_d(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+template <int M, int WTI, int WTJ, typename OutT>
+__global__ __launch_bounds__(NT) void gemmk_kernel(GemmKArgs g) {
+  using MT = ModeT<M>;
+  using T = typename MT::T;
+  constexpr int NP = MT::NP, KS = MT::KS, LD = lds_ld<T>(), ES = (int)sizeof(T);
+  constexpr int TM = 32 * WTI, TN = 32 * WTJ;
+  using PR = Products<NP>;
+  __shared__ __attribute__((aligned(16))) T sA[NP][TM * LD];
+  __shared__ __attribute__((aligned(16))) T sB[NP][TN * LD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int nib = (g.M + TM - 1) / TM;
+  const int i0 = (blockIdx.x % nib) * TM, j0 = (blockIdx.x / nib) * TN;
+
+  const T* A = static_cast<const T*>(g.A) + (int64_t)i0 * g.lda;
+  const T* B = static_cast<const T*>(g.B) + (int64_t)j0 * g.ldb;
+  __amdgpu_buffer_rsrc_t rA[NP], rB[NP];
+  Panel<T, TM> pA[NP];
+  Panel<T, TN> pB[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    rA[p] = make_rsrc(A + p * g.a_plane, (int64_t)TM * g.lda * ES);
+    rB[p] = make_rsrc(B + p * g.b_plane, (int64_t)TN * g.ldb * ES);
+    pA[p].init(g.lda, min(TM, g.M - i0), tid);
+    pB[p].init(g.ldb, min(TN, g.N - j0), tid);
+  }
+  typename MT::Acc acc[WTI][WTJ];
+#pragma unroll
+  for (int ti = 0; ti < WTI; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < WTJ; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[ti][tj][r] = 0;
+
+  const int nst = g.kpad / BK;
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    pA[p].load(rA[p], 0);
+    pB[p].load(rB[p], 0);
+  }
+  for (int ks = 0; ks < nst; ++ks) {
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      pA[p].store(sA[p], tid);
+      pB[p].store(sB[p], tid);
+    }
+    __syncthreads();
+    if (ks + 1 < nst) {
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        pA[p].load(rA[p], (ks + 1) * BK);
+        pB[p].load(rB[p], (ks + 1) * BK);
+      }
+    }
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += KS) {
+      typename MT::Frag fa[WTI][NP], fb[WTJ][NP];
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+#pragma unroll
+        for (int ti = 0; ti < WTI; ++ti)
+          fa[ti][p] = lds_frag<M>(sA[p], LD, wr * 16 * WTI + 16 * ti, kk, lane);
+#pragma unroll
+        for (int tj = 0; tj < WTJ; ++tj)
+          fb[tj][p] = lds_frag<M>(sB[p], LD, wc * 16 * WTJ + 16 * tj, kk, lane);
+      }
+#pragma unroll
+      for (int q = 0; q < PR::N; ++q)
+#pragma unroll
+        for (int ti = 0; ti < WTI; ++ti)
+#pragma unroll
+          for (int tj = 0; tj < WTJ; ++tj)
+            acc[ti][tj] = mfma1(fa[ti][PR::a(q)], fb[tj][PR::b(q)], acc[ti][tj]);
+    }
+  }
+
+  double lmax = 0.0;
+  OutT* C = static_cast<OutT*>(g.C);
+#pragma unroll
+  for (int ti = 0; ti < WTI; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < WTJ; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + wr * 16 * WTI + 16 * ti + out_row<M>(lane, r);
+        const int j = j0 + wc * 16 * WTJ + 16 * tj + (lane & 15);
+        if (i < g.M && j < g.N) {
+          const OutT v = (OutT)(g.alpha * (double)acc[ti][tj][r]);
+          C[((int64_t)i / g.ci_in) * g.ci_out + ((int64_t)i % g.ci_in) + (int64_t)j * g.c_j] = v;
+          lmax = fmax(lmax, fabs((double)v));
+        }
+      }
+  if (g.amax != nullptr) {
+    lmax = wave_max_d(lmax);
+    if (lane == 0) atomicMax(g.amax, (unsigned long long)__double_as_longlong(lmax));
+  }
+}
+
+inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+template <int M, int WTI, int WTJ>
+hipError_t launch(bool out_f64, const GemmKArgs& g, hipStream_t s) {
+  const unsigned grid = cdiv(g.M, 32 * WTI) * cdiv(g.N, 32 * WTJ);
+  if (out_f64) gemmk_kernel<M, WTI, WTJ, double><<<grid, NT, 0, s>>>(g);
+  else gemmk_kernel<M, WTI, WTJ, float><<<grid, NT, 0, s>>>(g);
+  return hipGetLastError();
+}
+
+template <int M>
+hipError_t launch_mode(bool out_f64, const GemmKArgs& g, hipStream_t s) {
+  // all of the B rows in one workgroup when they fit 320, else 160 per workgroup
+  if (g.N <= 320) return launch<M, 2, 10>(out_f64, g, s);
+  return launch<M, 2, 5>(out_f64, g, s);
+}
+
+}  // namespace
+
+hipError_t gemm_kmajor(int mode, bool out_f64, const GemmKArgs& g, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0) return hipSuccess;
+  switch (mode) {
+    case MODE_F64: return launch<MODE_F64, 2, 5>(out_f64, g, s);
+    case MODE_F32: return launch_mode<MODE_F32>(out_f64, g, s);
+    case MODE_BF16X3: return launch_mode<MODE_BF16X3>(out_f64, g, s);
+    case MODE_F16X2: return launch_mode<MODE_F16X2>(out_f64, g, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace thcsox

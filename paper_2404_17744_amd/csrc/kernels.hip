@@ -9,12 +9,6 @@ namespace {
 
 constexpr int NT = 256;   // threads per workgroup (4 wavefronts of 64)
 
-template <typename T> struct LdsPad;
-template <> struct LdsPad<double> { static constexpr int v = 2; };
-template <> struct LdsPad<float> { static constexpr int v = 4; };
-template <> struct LdsPad<__bf16> { static constexpr int v = 8; };
-template <> struct LdsPad<_Float16> { static constexpr int v = 8; };
-
 __device__ __forceinline__ double pow2_scale(const unsigned long long* amax) {
   if (amax == nullptr) return 1.0;
   unsigned long long b = *amax;
@@ -27,25 +21,6 @@ __device__ __forceinline__ double pow2_scale(const unsigned long long* amax) {
 __device__ __forceinline__ double wave_max(double v) {
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
   return v;
-}
-
-// Copy a ROWS x BK tile of a K-major array (rows of length >= k0 + BK,
-// 16-byte aligned) into LDS rows of stride LD.  Rows >= nrows are zero.
-template <typename T, int ROWS, int BK, int LD>
-__device__ __forceinline__ void load_tile(T* __restrict__ s, const T* __restrict__ g,
-                                          int64_t row_stride, int row0, int nrows,
-                                          int k0, int tid) {
-  constexpr int EPU = 16 / (int)sizeof(T);
-  constexpr int UPR = BK / EPU;
-  constexpr int NU = ROWS * UPR;
-#pragma unroll
-  for (int u = tid; u < NU; u += NT) {
-    const int r = u / UPR, c = (u % UPR) * EPU;
-    int4 val = {0, 0, 0, 0};
-    if (row0 + r < nrows)
-      val = *reinterpret_cast<const int4*>(g + (int64_t)(row0 + r) * row_stride + k0 + c);
-    *reinterpret_cast<int4*>(s + r * LD + c) = val;
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -113,182 +88,6 @@ __global__ __launch_bounds__(NT) void gemm64_kernel(Gemm64Args g) {
           if (g.beta != 0.0) v += g.beta * g.C[idx];
           g.C[idx] = v;
         }
-      }
-}
-
-// ---------------------------------------------------------------------------
-// K-major plane GEMM (the A = U G(-tau) stage)
-// ---------------------------------------------------------------------------
-template <int M, typename OutT>
-__global__ __launch_bounds__(NT) void gemmk_kernel(GemmKArgs g) {
-  using MT = ModeT<M>;
-  using T = typename MT::T;
-  constexpr int NP = MT::NP, KS = MT::KS, BK = 32, LD = BK + LdsPad<T>::v;
-  using PR = Products<NP>;
-  __shared__ __attribute__((aligned(16))) T sA[NP][64 * LD];
-  __shared__ __attribute__((aligned(16))) T sB[NP][64 * LD];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
-  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
-  const T* A = static_cast<const T*>(g.A);
-  const T* B = static_cast<const T*>(g.B);
-  typename MT::Acc acc[2][2];
-#pragma unroll
-  for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-    for (int tj = 0; tj < 2; ++tj)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) acc[ti][tj][r] = 0;
-
-  for (int k0 = 0; k0 < g.kpad; k0 += BK) {
-    __syncthreads();
-#pragma unroll
-    for (int p = 0; p < NP; ++p) {
-      load_tile<T, 64, BK, LD>(sA[p], A + p * g.a_plane, g.lda, i0, g.M, k0, tid);
-      load_tile<T, 64, BK, LD>(sB[p], B + p * g.b_plane, g.ldb, j0, g.N, k0, tid);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += KS) {
-      typename MT::Frag fa[2][NP], fb[2][NP];
-#pragma unroll
-      for (int t = 0; t < 2; ++t)
-#pragma unroll
-        for (int p = 0; p < NP; ++p) {
-          fa[t][p] = lds_frag<M>(sA[p], LD, 32 * wr + 16 * t, kk, lane);
-          fb[t][p] = lds_frag<M>(sB[p], LD, 32 * wc + 16 * t, kk, lane);
-        }
-#pragma unroll
-      for (int q = 0; q < PR::N; ++q)
-#pragma unroll
-        for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-          for (int tj = 0; tj < 2; ++tj)
-            acc[ti][tj] = mfma1(fa[ti][PR::a(q)], fb[tj][PR::b(q)], acc[ti][tj]);
-    }
-  }
-  double lmax = 0.0;
-  OutT* C = static_cast<OutT*>(g.C);
-#pragma unroll
-  for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-    for (int tj = 0; tj < 2; ++tj)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = i0 + 32 * wr + 16 * ti + out_row<M>(lane, r);
-        const int j = j0 + 32 * wc + 16 * tj + (lane & 15);
-        if (i < g.M && j < g.N) {
-          const OutT v = (OutT)(g.alpha * (double)acc[ti][tj][r]);
-          C[(int64_t)i * g.c_i + ((int64_t)j / g.cj_in) * g.cj_out + ((int64_t)j % g.cj_in)] = v;
-          lmax = fmax(lmax, fabs((double)v));
-        }
-      }
-  if (g.amax != nullptr) {
-    lmax = wave_max(lmax);
-    if (lane == 0) atomicMax(g.amax, (unsigned long long)__double_as_longlong(lmax));
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Fused B/C/D stage: for a 64 (R) x 64 (P) tile and a range of v,
-//   accB[R][P] = sum_q Gt[R][q] A[v][P][q]       (= B_PRv)
-//   accC[R][P] = sum_w U[R][v][w] GXt[P][w]      (= C_RvP)
-//   accD[R][P] += accB * accC                    (FP64, = D_PR)
-// Both products land in the same MFMA output layout, so the Hadamard product
-// is register-to-register.
-// ---------------------------------------------------------------------------
-template <int M>
-__global__ __launch_bounds__(NT) void fused_kernel(FusedArgs f) {
-  using MT = ModeT<M>;
-  using T = typename MT::T;
-  constexpr int NP = MT::NP, KS = MT::KS, BK = 32, LD = BK + LdsPad<T>::v;
-  using PR = Products<NP>;
-  __shared__ __attribute__((aligned(16))) T sG[NP][64 * LD];
-  __shared__ __attribute__((aligned(16))) T sX[NP][64 * LD];
-  __shared__ __attribute__((aligned(16))) T sU[NP][64 * LD];
-  __shared__ __attribute__((aligned(16))) T sA[NP][64 * LD];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
-  const int P0 = blockIdx.x * 64, R0 = blockIdx.y * 64, z = blockIdx.z;
-  const int v_lo = z * f.vchunk;
-  const int v_hi = min(f.n, v_lo + f.vchunk);
-  const T* Gt = static_cast<const T*>(f.Gt);
-  const T* GX = static_cast<const T*>(f.GXt);
-  const T* U = static_cast<const T*>(f.U);
-  const T* A = static_cast<const T*>(f.A);
-  const int64_t u_row = (int64_t)f.n * f.ldk;      // stride between R rows of U
-  const int64_t a_v = (int64_t)f.naux * f.ldk;     // stride between v slabs of A
-
-  double accD[2][2][4];
-#pragma unroll
-  for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-    for (int tj = 0; tj < 2; ++tj)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) accD[ti][tj][r] = 0.0;
-
-  for (int v = v_lo; v < v_hi; ++v) {
-    typename MT::Acc accB[2][2], accC[2][2];
-#pragma unroll
-    for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-      for (int tj = 0; tj < 2; ++tj)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) { accB[ti][tj][r] = 0; accC[ti][tj][r] = 0; }
-
-    for (int k0 = 0; k0 < f.ldk; k0 += BK) {
-      __syncthreads();
-#pragma unroll
-      for (int p = 0; p < NP; ++p) {
-        load_tile<T, 64, BK, LD>(sG[p], Gt + p * f.g_plane, f.ldk, R0, f.naux, k0, tid);
-        load_tile<T, 64, BK, LD>(sX[p], GX + p * f.g_plane, f.ldk, P0, f.naux, k0, tid);
-        load_tile<T, 64, BK, LD>(sU[p], U + p * f.u_plane + (int64_t)v * f.ldk, u_row, R0,
-                                 f.naux, k0, tid);
-        load_tile<T, 64, BK, LD>(sA[p], A + p * f.a_plane + (int64_t)v * a_v, f.ldk, P0,
-                                 f.naux, k0, tid);
-      }
-      __syncthreads();
-#pragma unroll
-      for (int kk = 0; kk < BK; kk += KS) {
-        typename MT::Frag fg[2][NP], fu[2][NP], fa[2][NP], fx[2][NP];
-#pragma unroll
-        for (int t = 0; t < 2; ++t)
-#pragma unroll
-          for (int p = 0; p < NP; ++p) {
-            fg[t][p] = lds_frag<M>(sG[p], LD, 32 * wr + 16 * t, kk, lane);
-            fu[t][p] = lds_frag<M>(sU[p], LD, 32 * wr + 16 * t, kk, lane);
-            fa[t][p] = lds_frag<M>(sA[p], LD, 32 * wc + 16 * t, kk, lane);
-            fx[t][p] = lds_frag<M>(sX[p], LD, 32 * wc + 16 * t, kk, lane);
-          }
-#pragma unroll
-        for (int q = 0; q < PR::N; ++q)
-#pragma unroll
-          for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-            for (int tj = 0; tj < 2; ++tj) {
-              accB[ti][tj] = mfma1(fg[ti][PR::a(q)], fa[tj][PR::b(q)], accB[ti][tj]);
-              accC[ti][tj] = mfma1(fu[ti][PR::a(q)], fx[tj][PR::b(q)], accC[ti][tj]);
-            }
-      }
-    }
-#pragma unroll
-    for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-      for (int tj = 0; tj < 2; ++tj)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          accD[ti][tj][r] = fma((double)accB[ti][tj][r], (double)accC[ti][tj][r], accD[ti][tj][r]);
-  }
-  double* D = f.Dpart + (int64_t)z * f.naux * f.naux;
-#pragma unroll
-  for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-    for (int tj = 0; tj < 2; ++tj)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int R = R0 + 32 * wr + 16 * ti + out_row<M>(lane, r);
-        const int P = P0 + 32 * wc + 16 * tj + (lane & 15);
-        if (R < f.naux && P < f.naux) D[(int64_t)R * f.naux + P] = accD[ti][tj][r];
       }
 }
 
@@ -394,43 +193,6 @@ hipError_t gemm64(const Gemm64Args& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
   dim3 grid(cdiv(g.N, 64), cdiv(g.M, 64), g.batch);
   gemm64_kernel<<<grid, NT, 0, s>>>(g);
-  return hipGetLastError();
-}
-
-hipError_t gemm_kmajor(int mode, bool out_f64, const GemmKArgs& g, hipStream_t s) {
-  if (g.M <= 0 || g.N <= 0) return hipSuccess;
-  dim3 grid(cdiv(g.N, 64), cdiv(g.M, 64), 1);
-  switch (mode) {
-    case MODE_F64:
-      if (out_f64) gemmk_kernel<MODE_F64, double><<<grid, NT, 0, s>>>(g);
-      else gemmk_kernel<MODE_F64, float><<<grid, NT, 0, s>>>(g);
-      break;
-    case MODE_F32:
-      if (out_f64) gemmk_kernel<MODE_F32, double><<<grid, NT, 0, s>>>(g);
-      else gemmk_kernel<MODE_F32, float><<<grid, NT, 0, s>>>(g);
-      break;
-    case MODE_BF16X3:
-      if (out_f64) gemmk_kernel<MODE_BF16X3, double><<<grid, NT, 0, s>>>(g);
-      else gemmk_kernel<MODE_BF16X3, float><<<grid, NT, 0, s>>>(g);
-      break;
-    case MODE_F16X2:
-      if (out_f64) gemmk_kernel<MODE_F16X2, double><<<grid, NT, 0, s>>>(g);
-      else gemmk_kernel<MODE_F16X2, float><<<grid, NT, 0, s>>>(g);
-      break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-hipError_t sox_fused(int mode, const FusedArgs& f, hipStream_t s) {
-  dim3 grid(cdiv(f.naux, 64), cdiv(f.naux, 64), f.vsplit);
-  switch (mode) {
-    case MODE_F64: fused_kernel<MODE_F64><<<grid, NT, 0, s>>>(f); break;
-    case MODE_F32: fused_kernel<MODE_F32><<<grid, NT, 0, s>>>(f); break;
-    case MODE_BF16X3: fused_kernel<MODE_BF16X3><<<grid, NT, 0, s>>>(f); break;
-    case MODE_F16X2: fused_kernel<MODE_F16X2><<<grid, NT, 0, s>>>(f); break;
-    default: return hipErrorInvalidValue;
-  }
   return hipGetLastError();
 }
 

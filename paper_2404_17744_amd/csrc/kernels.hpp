@@ -23,7 +23,7 @@ hipError_t gemm64(const Gemm64Args& g, hipStream_t s);
 //   C(i,j) = alpha * sum_{k < kpad} A[i][k] B[j][k]   (operand pad must be zero)
 //   A rows:  A + p*a_plane + i*lda          (i < M)
 //   B rows:  B + p*b_plane + j*ldb          (j < N)
-//   C(i,j) = C[i*c_i + (j / cj_in) * cj_out + (j % cj_in)]  (OutT = double or float)
+//   C(i,j) = C[(i / ci_in) * ci_out + (i % ci_in) + j * c_j]  (OutT = double or float)
 // If amax != nullptr, the largest |C(i,j)| is max-reduced into *amax (as the
 // bits of a non-negative double).
 struct GemmKArgs {
@@ -31,21 +31,27 @@ struct GemmKArgs {
   double alpha;
   const void* A; int64_t lda, a_plane;
   const void* B; int64_t ldb, b_plane;
-  void* C; int64_t c_i, cj_in, cj_out;
+  void* C; int64_t ci_in, ci_out, c_j;
   unsigned long long* amax;
 };
 hipError_t gemm_kmajor(int mode, bool out_f64, const GemmKArgs& g, hipStream_t s);
 
 // The fused B/C/D stage for one tau point (v split over grid.z):
 //   Dpart[z][R][P] = sum_{v in split z} (sum_q Gt[R][q] A[v][P][q]) (sum_w U[R][v][w] GXt[P][w])
+// With a_f32, A is an FP32 array [n][naux][ldk] split into the mode's planes on
+// the fly after scaling by the power of two taken from *amax_a.
 struct FusedArgs {
   int n, naux, ldk, vsplit, vchunk;
   const void* Gt; const void* GXt; int64_t g_plane;   // [naux][ldk] planes
   const void* U; int64_t u_plane;                      // [naux][n][ldk] planes
-  const void* A; int64_t a_plane;                      // [n][naux][ldk] planes
+  const void* A; int64_t a_plane;                      // [n][naux][ldk] planes (or FP32)
+  bool a_f32;
+  const unsigned long long* amax_a;
   double* Dpart;                                       // [vsplit][naux][naux]
 };
 hipError_t sox_fused(int mode, const FusedArgs& f, hipStream_t s);
+void fused_tile(int mode, int* rows, int* cols);   // D tile one workgroup owns (R x P)
+int fused_xcds();   // vsplit must be a multiple of this (one v range per XCD in turn)
 
 // Split rows of an FP64 source into the planes of a mode, scaled by the power of
 // two 2^-floor(log2(*amax)) (scale 1 if amax is null or zero):

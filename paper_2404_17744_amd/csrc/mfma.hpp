@@ -86,8 +86,17 @@ template <int M> __device__ __forceinline__ int out_row(int lane, int r) {
   else return 4 * (lane >> 4) + r;
 }
 
+// Physical 16-byte chunk of logical chunk c (0..3) in row r of a 16-bit LDS
+// tile with 64-byte rows.  Fragment reads touch 16 consecutive rows at one
+// logical chunk; with this map any 8 (or 16) consecutive rows land on distinct
+// bank groups for 128-byte (or 256-byte) wide LDS banking, and the four chunks
+// of one row stay distinct (so whole-row writes are conflict-free too).
+__device__ __forceinline__ int lds_chunk(int r, int c) { return c ^ (((r >> 1) ^ (r >> 3)) & 3); }
+
 // Load one operand fragment from an LDS tile stored row-major as
 // s[row][ldk_s] (k contiguous): rows i0..i0+15, k range starting at kk.
+// 16-bit tiles hold one 32-wide k range per row (kk = 0) as four 16-byte
+// chunks placed by lds_chunk.
 template <int M>
 __device__ __forceinline__ typename ModeT<M>::Frag
 lds_frag(const typename ModeT<M>::T* s, int ldk_s, int i0, int kk, int lane) {
@@ -95,8 +104,10 @@ lds_frag(const typename ModeT<M>::T* s, int ldk_s, int i0, int kk, int lane) {
   if constexpr (MT::KS == 4) {
     return s[(i0 + (lane & 15)) * ldk_s + kk + (lane >> 4)];
   } else {
-    const typename MT::Frag* p = reinterpret_cast<const typename MT::Frag*>(
-        s + (i0 + (lane & 15)) * ldk_s + kk + 8 * (lane >> 4));
+    const int r = i0 + (lane & 15);
+    const int c = lds_chunk(r, lane >> 4);
+    const typename MT::Frag* p =
+        reinterpret_cast<const typename MT::Frag*>(s + r * ldk_s + kk + 8 * c);
     return *p;
   }
 }

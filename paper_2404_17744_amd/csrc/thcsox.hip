@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <string>
@@ -235,13 +236,13 @@ int sigma_one(thcsox_plan_s* p, const double* G, double* Sigma, double* Sthc_out
   HIP_TRY(split_planes(mode, sa, s));
   HIP_TRY(p->mark(THCSOX_STAGE_PROJECT, false));
 
-  // A[v][P][q] = sum_s U[P][q][s] G(-tau)[s][v]
+  // A[v][P][q] = sum_s U[P][q][s] G(-tau)[s][v]: rows (P,q) of U against rows v of G(-tau)^T
   HIP_TRY(p->mark(THCSOX_STAGE_A, true));
   GemmKArgs ga{};
-  ga.M = n; ga.N = naux * n; ga.kpad = ldk; ga.alpha = 1.0;
-  ga.A = p->Gb; ga.lda = ldk; ga.a_plane = p->gb_plane;
-  ga.B = p->U; ga.ldb = ldk; ga.b_plane = p->u_plane;
-  ga.c_i = (int64_t)naux * ldk; ga.cj_in = n; ga.cj_out = ldk;
+  ga.M = naux * n; ga.N = n; ga.kpad = ldk; ga.alpha = 1.0;
+  ga.A = p->U; ga.lda = ldk; ga.a_plane = p->u_plane;
+  ga.B = p->Gb; ga.ldb = ldk; ga.b_plane = p->gb_plane;
+  ga.ci_in = n; ga.ci_out = ldk; ga.c_j = (int64_t)naux * ldk;
   const bool split_a = (mode == MODE_BF16X3 || mode == MODE_F16X2);
   if (mode == MODE_F64) {
     ga.C = p->A; ga.amax = nullptr;
@@ -250,22 +251,18 @@ int sigma_one(thcsox_plan_s* p, const double* G, double* Sigma, double* Sthc_out
     ga.C = p->A; ga.amax = nullptr;
     HIP_TRY(gemm_kmajor(mode, false, ga, s));
   } else {
+    // FP32 A; the fused kernel splits it into planes with the scale from max|A|
     ga.C = p->A32; ga.amax = am + 4;
     HIP_TRY(gemm_kmajor(mode, false, ga, s));
-    SplitArgs s2{};
-    s2.rows1 = n * naux; s2.rows2 = 1; s2.cols = n; s2.ldk = ldk;
-    s2.src = p->A32; s2.src_f32 = true; s2.s1 = ldk; s2.s2 = 0; s2.sc = 1;
-    s2.dst = p->A; s2.d1 = ldk; s2.d2 = 0; s2.d_plane = p->a_plane; s2.amax = am + 4;
-    HIP_TRY(split_planes(mode, s2, s));
   }
-
   HIP_TRY(p->mark(THCSOX_STAGE_A, false));
 
   FusedArgs f{};
   f.n = n; f.naux = naux; f.ldk = ldk; f.vsplit = p->vsplit; f.vchunk = p->vchunk;
   f.Gt = p->Gt; f.GXt = p->GX; f.g_plane = p->g_plane;
   f.U = p->U; f.u_plane = p->u_plane;
-  f.A = p->A; f.a_plane = p->a_plane;
+  f.A = split_a ? static_cast<const void*>(p->A32) : p->A; f.a_plane = p->a_plane;
+  f.a_f32 = split_a; f.amax_a = split_a ? am + 4 : nullptr;
   f.Dpart = p->Dpart;
   HIP_TRY(p->mark(THCSOX_STAGE_FUSED, true));
   HIP_TRY(sox_fused(mode, f, s));
@@ -347,10 +344,29 @@ int thcsox_plan(thcsox_plan_t* out, int n, int naux, int ntau, double beta,
   p->limit = workspace_limit;
   const int64_t ldk = p->ldk;
 
-  int tiles = ((naux + 63) / 64) * ((naux + 63) / 64);
-  int vs = std::max(1, std::min(n, (2048 + tiles - 1) / tiles));
-  p->vchunk = (n + vs - 1) / vs;
-  p->vsplit = (n + p->vchunk - 1) / p->vchunk;
+  {
+    // v split: a multiple of the XCD count (each XCD owns whole v ranges),
+    // chosen so the last round of workgroups on each XCD is nearly full.
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess)
+      (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int nx = fused_xcds();
+    const int per_xcd = std::max(1, cus / nx);
+    int TR = 64, TP = 64;
+    fused_tile(precision, &TR, &TP);
+    const long tiles = (long)((naux + TR - 1) / TR) * ((naux + TP - 1) / TP);
+    int best = nx;
+    double best_eff = -1.0;
+    for (int vs = nx; vs <= std::max(nx, std::min(8 * nx, n)); vs += nx) {
+      const long wg = tiles * (vs / nx);                 // workgroups per XCD
+      const long rounds = (wg + per_xcd - 1) / per_xcd;
+      double eff = (double)wg / (double)(rounds * per_xcd);
+      eff *= 1.0 - 0.002 * vs;                           // mild preference for long v ranges
+      if (eff > best_eff) { best_eff = eff; best = vs; }
+    }
+    p->vsplit = best;
+    p->vchunk = (n + best - 1) / best;   // trailing ranges may be empty (they write zeros)
+  }
 
   int rc = 0;
   const size_t es = p->esize, np = p->np;
@@ -366,10 +382,12 @@ int thcsox_plan(thcsox_plan_t* out, int n, int naux, int ntau, double beta,
   if ((rc = p->alloc(&p->E, 1))) return bail(rc);
   if ((rc = p->alloc(&tmp, np * es * (size_t)p->u_plane))) return bail(rc);
   p->U = tmp;
-  if ((rc = p->alloc(&tmp, np * es * (size_t)p->a_plane))) return bail(rc);
-  p->A = tmp;
-  if (precision == THCSOX_BF16X3 || precision == THCSOX_FP16X2)
+  if (precision == THCSOX_BF16X3 || precision == THCSOX_FP16X2) {
     if ((rc = p->alloc(&p->A32, (size_t)p->a_plane))) return bail(rc);
+  } else {
+    if ((rc = p->alloc(&tmp, np * es * (size_t)p->a_plane))) return bail(rc);
+    p->A = tmp;
+  }
   if ((rc = p->alloc(&tmp, np * es * (size_t)p->g_plane))) return bail(rc);
   p->Gt = tmp;
   if ((rc = p->alloc(&tmp, np * es * (size_t)p->g_plane))) return bail(rc);
@@ -394,7 +412,10 @@ int thcsox_plan(thcsox_plan_t* out, int n, int naux, int ntau, double beta,
     return hip_bail(e, "copy weights");
   // zero the operand pads once (stages only ever write the first n of ldk columns)
   if ((e = hipMemsetAsync(p->U, 0, np * es * (size_t)p->u_plane, s))) return hip_bail(e, "zero U");
-  if ((e = hipMemsetAsync(p->A, 0, np * es * (size_t)p->a_plane, s))) return hip_bail(e, "zero A");
+  if (p->A && (e = hipMemsetAsync(p->A, 0, np * es * (size_t)p->a_plane, s)))
+    return hip_bail(e, "zero A");
+  if (p->A32 && (e = hipMemsetAsync(p->A32, 0, sizeof(float) * (size_t)p->a_plane, s)))
+    return hip_bail(e, "zero A32");
   if ((rc = build_u(p, V_dev))) return bail(rc);
   if ((e = hipStreamSynchronize(s))) return hip_bail(e, "plan synchronise");
   *out = p;

@@ -67,6 +67,22 @@ def test_ragged_tiles(dev, precision):
         assert err <= MIXED_TOL[precision]
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3", "fp16x2"])
+def test_many_tiles_every_pair_covered(dev, precision):
+    """n=150, naux=600: many workgroup tiles in both directions and several v
+    ranges, so a tile or v range the launch failed to cover shows up."""
+    s = synth.make_system(150, 600, seed=6)
+    tau, w = synth.cheb_tau_grid(6, 100.0)
+    G = synth.g0_tau(s, tau, 100.0)
+    print(f"case n150 naux600 ntau6 seed 6 {precision}", flush=True)
+    U = osox.precontract_u(s.X, s.V)
+    ref = np.stack([osox.sigma_thc_paper(s.X, s.V, G[k], G[5 - k], U=U) for k in (0, 1)])
+    S, _ = _run(dev, s.X, s.V, tau, w, 100.0, G, precision, 0, 2)
+    err = _rel(S[:2], ref)
+    print(f"  sigma rel err {err:.3e}")
+    assert err <= (1e-10 if precision == "fp64" else MIXED_TOL[precision])
+
+
 def test_general_nonsymmetric_g(dev):
     """A dense non-symmetric G exercises both projections separately."""
     s = synth.make_system(40, 100, seed=4)
