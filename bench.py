@@ -141,14 +141,15 @@ def main():
     if os.path.exists(gold):
         with open(gold) as f:
             g = json.load(f)
-        if g.get("input_digest") == s.digest():
-            accuracy["E_oracle"] = g["E_sox"]
-            accuracy["energy_err_vs_fp64_oracle_Ha"] = E_mixed - g["E_sox"]
-            if fp64:
-                accuracy["fp64_path_energy_err_vs_oracle_Ha"] = fp64["E_sox"] - g["E_sox"]
-            Sm = S_mixed.cpu().numpy()
-            errs = [abs(Sm[k, t, r] - v) for k, t, r, v in g["samples"]]
-            accuracy["sigma_sampled_rel_err_vs_oracle"] = max(errs) / g["sigma_absmax"]
+        # inputs may differ in the last bits across hosts (BLAS code paths): ~1e-14 Ha
+        accuracy["input_digest_matches_golden"] = g.get("input_digest") == s.digest()
+        accuracy["E_oracle"] = g["E_sox"]
+        accuracy["energy_err_vs_fp64_oracle_Ha"] = E_mixed - g["E_sox"]
+        if fp64:
+            accuracy["fp64_path_energy_err_vs_oracle_Ha"] = fp64["E_sox"] - g["E_sox"]
+        Sm = S_mixed.cpu().numpy()
+        errs = [abs(Sm[k, t, r] - v) for k, t, r, v in g["samples"]]
+        accuracy["sigma_sampled_rel_err_vs_oracle"] = max(errs) / g["sigma_absmax"]
 
     out = {
         "metric": METRIC,

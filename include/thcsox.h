@@ -111,6 +111,14 @@ int thcsox_sigma_sox(thcsox_plan_t p, const double* G_dev, double* Sigma_dev,
 int thcsox_energy(thcsox_plan_t p, const double* G_dev, const double* Sigma_dev,
                   double* E_host);
 
+/* Back-projection alone (the last equation of the THC sequence):
+ *     Sigma_tr = sum_PR X_tR Sig_RP X_rP       for k in [k_begin, k_end)
+ *   Sigma_thc_dev[ntau][naux][naux] (read), Sigma_dev[ntau][n][n] (written).
+ * Used to bring a self-energy given in the THC basis (e.g. a predicted one)
+ * back to the orbital basis.  FP64, asynchronous. */
+int thcsox_backproject(thcsox_plan_t p, const double* Sigma_thc_dev, double* Sigma_dev,
+                       int k_begin, int k_end);
+
 /* Release a plan and all its device memory.  Accepts NULL. */
 int thcsox_destroy(thcsox_plan_t p);
 
@@ -129,6 +137,34 @@ typedef struct {
                                  U and A once each, plus the projected G */
 } thcsox_plan_info_t;
 int thcsox_plan_info(thcsox_plan_t p, thcsox_plan_info_t* info);
+
+/* ---------------------------------------------------------------------------
+ * One self-consistency step in FP64 (Sec. "Definitions": Eq. Dyson in an
+ * orthonormal basis, and the density matrix gamma_pq = -G_qp(0^-), taken as
+ * gamma = -G(beta^-)):
+ *   Sigma(tau) on the Chebyshev-root grid -> Chebyshev interpolation ->
+ *   Sigma(i w_n), w_n = (2n+1) pi / beta, n = 0 .. n_matsubara-1 ->
+ *   G(i w_n) = [(i w_n + mu) 1 - F - Sigma(i w_n)]^-1 ->
+ *   least-squares Chebyshev fit over the kept frequencies -> G(tau_k), gamma.
+ * The grid must be the m roots of T_m mapped to [0, beta] (ascending).
+ * ------------------------------------------------------------------------- */
+typedef struct thcsox_dyson_s* thcsox_dyson_t;
+
+/* F_dev[n][n]: one-body operator (copied).  mu: chemical potential (fixed).
+ * Needs 2 n_matsubara >= ntau.  Synchronises the stream. */
+int thcsox_dyson_plan(thcsox_dyson_t* out, int n, int ntau, int n_matsubara, double beta,
+                      double mu, const double* tau_host, const double* F_dev, void* hip_stream);
+
+/* Sigma_dev[ntau][n][n] (read) -> G_dev[ntau][n][n] and gamma_dev[n][n] (written;
+ * gamma_dev may be NULL).  Synchronises the stream; THCSOX_ENONFINITE if a
+ * Dyson matrix is singular. */
+int thcsox_dyson_step(thcsox_dyson_t d, const double* Sigma_dev, double* G_dev,
+                      double* gamma_dev);
+
+/* E1 = Tr[F gamma] = sum_pq F_pq gamma_qp in FP64 (host scalar). */
+int thcsox_dyson_onebody(thcsox_dyson_t d, const double* gamma_dev, double* E1_host);
+
+int thcsox_dyson_destroy(thcsox_dyson_t d);
 
 /* Optional stage timing with HIP events recorded on the plan's stream around
  * each stage of every tau point (negligible overhead).  Stages:

@@ -1,0 +1,511 @@
+// One self-consistency step in FP64 on the GPU: Sigma(tau) -> Sigma(i w_n) ->
+// Dyson equation (Sec. "Definitions", Eq. Dyson, orthonormal basis) ->
+// G(i w_n) -> G(tau) and the density matrix.
+//
+// tau grid: the m roots of the Chebyshev polynomial T_m mapped to [0, beta].
+//   forward : Sigma(i w_n) = sum_l T_nl c_l, c = Chebyshev interpolation
+//             coefficients of Sigma(tau) through the roots, and
+//             T_nl = int_0^beta exp(i w_n tau) T_l(2 tau / beta - 1) dtau,
+//             w_n = (2n+1) pi / beta, n = 0 .. nw-1.
+//   Dyson   : G(i w_n) = [(i w_n + mu) 1 - F - Sigma(i w_n)]^-1
+//   backward: real coefficients minimising sum_n |sum_l T_nl c_l - G(i w_n)|^2,
+//             G(tau_k) = sum_l c_l T_l(x_k),  gamma = -G(beta^-) = -sum_l c_l.
+// The three linear maps are folded into two real matrices built on the host
+// at plan time (Wf: [2 nw][m], Wb: [m + 1][2 nw]); each step is then two FP64
+// matrix-core GEMMs around a batched complex Gauss-Jordan inversion.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <complex>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/thcsox.h"
+#include "error.hpp"
+#include "kernels.hpp"
+
+using namespace thcsox;
+
+namespace {
+
+constexpr int NT = 256;
+
+// ----------------------------------------------------------------------------
+// Host tables (FP64)
+// ----------------------------------------------------------------------------
+
+// Gauss-Legendre nodes and weights on [-1, 1] (Newton iteration on P_q).
+void gauss_legendre(int q, std::vector<double>& x, std::vector<double>& w) {
+  x.resize(q);
+  w.resize(q);
+  for (int i = 0; i < q; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (q + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= q; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      const double dp = q * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = z;
+    for (int k = 2; k <= q; ++k) {
+      const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    const double dp = q * (z * p1 - p0) / (z * z - 1.0);
+    x[i] = z;
+    w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+struct Tables {
+  std::vector<double> Wf;   // [2 nw][m]: rows 0..nw-1 real part, nw..2nw-1 imaginary part
+  std::vector<double> Wb;   // [m + 1][2 nw]: G(tau_k) rows, then the gamma row
+};
+
+// T[n][l] = int_0^beta exp(i w_n tau) T_l(2 tau/beta - 1) dtau by composite
+// Gauss-Legendre over equal panels in x = 2 tau / beta - 1.
+std::vector<std::complex<double>> cheb_matsubara(int m, int nw, double beta) {
+  const int q = 16;
+  const double amax = (2.0 * nw - 1.0) * M_PI / 2.0;          // largest w_n beta / 2
+  const int panels = std::max(64, (int)std::ceil(amax / M_PI * 4.0) + 2 * m);
+  std::vector<double> gx, gw;
+  gauss_legendre(q, gx, gw);
+  const int npt = panels * q;
+  std::vector<double> xs(npt), ws(npt);
+  for (int p = 0; p < panels; ++p) {
+    const double a = -1.0 + 2.0 * p / panels, h = 1.0 / panels;   // half width
+    for (int i = 0; i < q; ++i) {
+      xs[p * q + i] = a + h + h * gx[i];
+      ws[p * q + i] = h * gw[i];
+    }
+  }
+  std::vector<double> Tl((size_t)npt * m);   // T_l(x) by recurrence
+  for (int i = 0; i < npt; ++i) {
+    double t0 = 1.0, t1 = xs[i];
+    Tl[(size_t)i * m] = 1.0;
+    if (m > 1) Tl[(size_t)i * m + 1] = t1;
+    for (int l = 2; l < m; ++l) {
+      const double t2 = 2.0 * xs[i] * t1 - t0;
+      Tl[(size_t)i * m + l] = t2;
+      t0 = t1;
+      t1 = t2;
+    }
+  }
+  std::vector<std::complex<double>> T((size_t)nw * m);
+  std::vector<std::complex<double>> acc(m);
+  for (int n = 0; n < nw; ++n) {
+    const double wn = (2.0 * n + 1.0) * M_PI / beta;
+    std::fill(acc.begin(), acc.end(), std::complex<double>(0.0, 0.0));
+    for (int i = 0; i < npt; ++i) {
+      const double tau = 0.5 * beta * (1.0 + xs[i]);
+      const std::complex<double> e = std::polar(ws[i] * 0.5 * beta, wn * tau);
+      const double* t = &Tl[(size_t)i * m];
+      for (int l = 0; l < m; ++l) acc[l] += e * t[l];
+    }
+    for (int l = 0; l < m; ++l) T[(size_t)n * m + l] = acc[l];
+  }
+  return T;
+}
+
+// Least-squares pseudo-inverse P = (A^T A)^-1 A^T of a tall A [r][c] by
+// Householder QR: A = Q R, P = R^-1 Q^T.
+std::vector<double> pinv_qr(std::vector<double> A, int r, int c) {
+  std::vector<double> Qt((size_t)r * r, 0.0);   // accumulate Q^T applied to identity rows
+  for (int i = 0; i < r; ++i) Qt[(size_t)i * r + i] = 1.0;
+  std::vector<double> v(r);
+  for (int k = 0; k < c; ++k) {
+    double norm = 0.0;
+    for (int i = k; i < r; ++i) norm += A[(size_t)i * c + k] * A[(size_t)i * c + k];
+    norm = std::sqrt(norm);
+    const double akk = A[(size_t)k * c + k];
+    const double alpha = akk > 0 ? -norm : norm;
+    for (int i = 0; i < r; ++i) v[i] = 0.0;
+    v[k] = akk - alpha;
+    for (int i = k + 1; i < r; ++i) v[i] = A[(size_t)i * c + k];
+    double vn = 0.0;
+    for (int i = k; i < r; ++i) vn += v[i] * v[i];
+    if (vn == 0.0) continue;
+    // H = I - 2 v v^T / (v^T v) applied to A (columns k..c-1) and to Qt
+    for (int j = k; j < c; ++j) {
+      double s = 0.0;
+      for (int i = k; i < r; ++i) s += v[i] * A[(size_t)i * c + j];
+      s = 2.0 * s / vn;
+      for (int i = k; i < r; ++i) A[(size_t)i * c + j] -= s * v[i];
+    }
+    for (int j = 0; j < r; ++j) {
+      double s = 0.0;
+      for (int i = k; i < r; ++i) s += v[i] * Qt[(size_t)i * r + j];
+      s = 2.0 * s / vn;
+      for (int i = k; i < r; ++i) Qt[(size_t)i * r + j] -= s * v[i];
+    }
+  }
+  // P = R^-1 (first c rows of Qt), R upper triangular in A[0..c-1][0..c-1]
+  std::vector<double> P((size_t)c * r);
+  for (int j = 0; j < r; ++j) {
+    for (int i = c - 1; i >= 0; --i) {
+      double s = Qt[(size_t)i * r + j];
+      for (int k2 = i + 1; k2 < c; ++k2) s -= A[(size_t)i * c + k2] * P[(size_t)k2 * r + j];
+      P[(size_t)i * r + j] = s / A[(size_t)i * c + i];
+    }
+  }
+  return P;
+}
+
+Tables build_tables(int m, int nw, double beta) {
+  std::vector<double> x(m);
+  for (int k = 0; k < m; ++k) x[k] = -std::cos((2.0 * k + 1.0) * M_PI / (2.0 * m));
+  std::vector<double> Tev((size_t)m * m);   // Tev[k][l] = T_l(x_k)
+  for (int k = 0; k < m; ++k) {
+    double t0 = 1.0, t1 = x[k];
+    Tev[(size_t)k * m] = 1.0;
+    if (m > 1) Tev[(size_t)k * m + 1] = t1;
+    for (int l = 2; l < m; ++l) {
+      const double t2 = 2.0 * x[k] * t1 - t0;
+      Tev[(size_t)k * m + l] = t2;
+      t0 = t1;
+      t1 = t2;
+    }
+  }
+  const auto T = cheb_matsubara(m, nw, beta);
+  Tables tb;
+  // forward: c_l = (2 - delta_l0)/m sum_k T_l(x_k) F_k ; F(i w_n) = sum_l T_nl c_l
+  tb.Wf.assign((size_t)2 * nw * m, 0.0);
+  for (int n = 0; n < nw; ++n)
+    for (int k = 0; k < m; ++k) {
+      std::complex<double> s(0.0, 0.0);
+      for (int l = 0; l < m; ++l)
+        s += T[(size_t)n * m + l] * ((l == 0 ? 1.0 : 2.0) / m) * Tev[(size_t)k * m + l];
+      tb.Wf[(size_t)n * m + k] = s.real();
+      tb.Wf[(size_t)(nw + n) * m + k] = s.imag();
+    }
+  // backward: c = pinv([Re T; Im T]) [Re G; Im G]
+  std::vector<double> A((size_t)2 * nw * m);
+  for (int n = 0; n < nw; ++n)
+    for (int l = 0; l < m; ++l) {
+      A[(size_t)n * m + l] = T[(size_t)n * m + l].real();
+      A[(size_t)(nw + n) * m + l] = T[(size_t)n * m + l].imag();
+    }
+  const auto P = pinv_qr(A, 2 * nw, m);   // [m][2nw]
+  tb.Wb.assign((size_t)(m + 1) * 2 * nw, 0.0);
+  for (int k = 0; k < m; ++k)
+    for (int j = 0; j < 2 * nw; ++j) {
+      double s = 0.0;
+      for (int l = 0; l < m; ++l) s += Tev[(size_t)k * m + l] * P[(size_t)l * 2 * nw + j];
+      tb.Wb[(size_t)k * 2 * nw + j] = s;
+    }
+  for (int j = 0; j < 2 * nw; ++j) {
+    double s = 0.0;
+    for (int l = 0; l < m; ++l) s += P[(size_t)l * 2 * nw + j];
+    tb.Wb[(size_t)m * 2 * nw + j] = -s;   // gamma = -sum_l c_l
+  }
+  return tb;
+}
+
+// tables depend only on (m, nw, beta): cache them for repeated plans
+const Tables& tables_for(int m, int nw, double beta) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, int, double>, Tables> cache;
+  std::lock_guard<std::mutex> lk(mu);
+  auto key = std::make_tuple(m, nw, beta);
+  auto it = cache.find(key);
+  if (it == cache.end()) it = cache.emplace(key, build_tables(m, nw, beta)).first;
+  return it->second;
+}
+
+// ----------------------------------------------------------------------------
+// Kernels
+// ----------------------------------------------------------------------------
+
+// Aug[w] = [ (i w + mu) 1 - F - Sigma(i w) | 1 ] as complex [n][2n].
+__global__ __launch_bounds__(NT) void build_aug(const double* __restrict__ S, const double* __restrict__ F,
+                                                double mu, double beta, int n, int nw,
+                                                double2* __restrict__ Aug) {
+  const int w = blockIdx.y;
+  const double wn = (2.0 * w + 1.0) * M_PI / beta;
+  const int64_t nn = (int64_t)n * n;
+  const double* Sre = S + (int64_t)w * nn;
+  const double* Sim = S + (int64_t)(nw + w) * nn;
+  double2* A = Aug + (int64_t)w * 2 * nn;
+  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < nn; e += (int64_t)gridDim.x * NT) {
+    const int64_t i = e / n, j = e % n;
+    double re = -F[e] - Sre[e], im = -Sim[e];
+    if (i == j) {
+      re += mu;
+      im += wn;
+    }
+    A[i * 2 * n + j] = make_double2(re, im);
+    A[i * 2 * n + n + j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+  }
+}
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// In-place Gauss-Jordan elimination with partial pivoting on [A | 1]; the
+// right half ends as A^-1.  One workgroup per matrix; each column step is
+// separated by barriers (global memory of one matrix is only touched by its
+// own workgroup).  flag[0] is set to 1 if a pivot is exactly zero.
+__global__ __launch_bounds__(NT) void gauss_jordan(double2* __restrict__ Aug, int n,
+                                                   int* __restrict__ flag) {
+  extern __shared__ double2 fac[];   // column k factors, n entries
+  __shared__ double bval[NT];
+  __shared__ int bidx[NT];
+  __shared__ double2 pinv;
+  const int tid = threadIdx.x;
+  const int ld = 2 * n;
+  double2* A = Aug + (int64_t)blockIdx.x * n * ld;
+  for (int k = 0; k < n; ++k) {
+    double best = -1.0;
+    int bi = k;
+    for (int i = k + tid; i < n; i += NT) {
+      const double2 a = A[(int64_t)i * ld + k];
+      const double v = a.x * a.x + a.y * a.y;
+      if (v > best) { best = v; bi = i; }
+    }
+    bval[tid] = best;
+    bidx[tid] = bi;
+    __syncthreads();
+    for (int o = NT / 2; o > 0; o >>= 1) {
+      if (tid < o) {
+        const double v2 = bval[tid + o];
+        const int i2 = bidx[tid + o];
+        if (v2 > bval[tid] || (v2 == bval[tid] && i2 < bidx[tid])) {
+          bval[tid] = v2;
+          bidx[tid] = i2;
+        }
+      }
+      __syncthreads();
+    }
+    const int piv = bidx[0];
+    if (tid == 0 && !(bval[0] > 0.0)) atomicExch(flag, 1);
+    if (piv != k) {
+      for (int j = k + tid; j < ld; j += NT) {
+        const double2 t = A[(int64_t)k * ld + j];
+        A[(int64_t)k * ld + j] = A[(int64_t)piv * ld + j];
+        A[(int64_t)piv * ld + j] = t;
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      const double2 a = A[(int64_t)k * ld + k];
+      const double d = a.x * a.x + a.y * a.y;
+      pinv = d > 0.0 ? make_double2(a.x / d, -a.y / d) : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    for (int j = k + tid; j < ld; j += NT) A[(int64_t)k * ld + j] = cmul(A[(int64_t)k * ld + j], pinv);
+    for (int i = tid; i < n; i += NT) fac[i] = A[(int64_t)i * ld + k];
+    __syncthreads();
+    const int w = ld - k;
+    for (int64_t e = tid; e < (int64_t)n * w; e += NT) {
+      const int i = (int)(e / w), j = k + (int)(e % w);
+      if (i == k) continue;
+      const double2 f = fac[i];
+      const double2 r = A[(int64_t)k * ld + j];
+      double2 a = A[(int64_t)i * ld + j];
+      a.x -= f.x * r.x - f.y * r.y;
+      a.y -= f.x * r.y + f.y * r.x;
+      A[(int64_t)i * ld + j] = a;
+    }
+    __syncthreads();
+  }
+}
+
+// Gstack[w][ij] = Re A^-1, Gstack[nw + w][ij] = Im A^-1.
+__global__ __launch_bounds__(NT) void extract_inv(const double2* __restrict__ Aug, int n, int nw,
+                                                  double* __restrict__ Gs) {
+  const int w = blockIdx.y;
+  const int64_t nn = (int64_t)n * n;
+  const double2* A = Aug + (int64_t)w * 2 * nn;
+  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < nn; e += (int64_t)gridDim.x * NT) {
+    const int64_t i = e / n, j = e % n;
+    const double2 v = A[i * 2 * n + n + j];
+    Gs[(int64_t)w * nn + e] = v.x;
+    Gs[(int64_t)(nw + w) * nn + e] = v.y;
+  }
+}
+
+// out = sum_pq A[p][q] B[q][p] (one workgroup, fixed order).
+__global__ __launch_bounds__(NT) void trace_ab(const double* A, const double* B, int n, double* out) {
+  __shared__ double red[NT];
+  double s = 0.0;
+  const int64_t nn = (int64_t)n * n;
+  for (int64_t e = threadIdx.x; e < nn; e += NT) {
+    const int64_t p = e / n, q = e % n;
+    s = fma(A[e], B[q * n + p], s);
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = NT / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+int dfail(int code, const std::string& m) { return set_error(code, m); }
+
+}  // namespace
+
+struct thcsox_dyson_s {
+  int n = 0, m = 0, nw = 0;
+  double beta = 0, mu = 0;
+  hipStream_t stream = nullptr;
+  double* F = nullptr;     // [n][n]
+  double* Wf = nullptr;    // [2nw][m]
+  double* Wb = nullptr;    // [m+1][2nw]
+  double* Siw = nullptr;   // [2nw][n n]
+  double2* Aug = nullptr;  // [nw][n][2n]
+  double* Gs = nullptr;    // [2nw][n n]
+  double* Gout = nullptr;  // [m+1][n n]
+  int* flag = nullptr;
+  double* scal = nullptr;
+  std::vector<void*> allocs;
+  ~thcsox_dyson_s() {
+    for (void* p : allocs) (void)hipFree(p);
+  }
+};
+
+namespace {
+template <typename T>
+int dalloc(thcsox_dyson_s* d, T** p, size_t count) {
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, std::max<size_t>(16, count * sizeof(T)));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return dfail(THCSOX_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+  }
+  d->allocs.push_back(q);
+  *p = static_cast<T*>(q);
+  return 0;
+}
+
+#define DTRY(expr)                                                                      \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return dfail(THCSOX_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));  \
+  } while (0)
+}  // namespace
+
+extern "C" {
+
+int thcsox_dyson_plan(thcsox_dyson_t* out, int n, int ntau, int n_matsubara, double beta,
+                      double mu, const double* tau_host, const double* F_dev, void* hip_stream) {
+  clear_error();
+  if (out == nullptr) return dfail(THCSOX_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n <= 0 || ntau <= 1 || n_matsubara <= 0 || !(beta > 0.0))
+    return dfail(THCSOX_EINVAL, "need n > 0, ntau > 1, n_matsubara > 0, beta > 0");
+  if (2 * n_matsubara < ntau)
+    return dfail(THCSOX_EINVAL, "need 2 n_matsubara >= ntau for the least-squares fit");
+  if (tau_host == nullptr || F_dev == nullptr) return dfail(THCSOX_EINVAL, "NULL argument");
+  for (int k = 0; k < ntau; ++k) {
+    const double x = -std::cos((2.0 * k + 1.0) * M_PI / (2.0 * ntau));
+    if (std::fabs(tau_host[k] - 0.5 * beta * (1.0 + x)) > 1e-12 * beta)
+      return dfail(THCSOX_EINVAL, "tau grid is not the Chebyshev-root grid");
+  }
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, F_dev) != hipSuccess ||
+      (a.type != hipMemoryTypeDevice && a.type != hipMemoryTypeManaged)) {
+    (void)hipGetLastError();
+    return dfail(THCSOX_ENOTDEV, "F_dev is not device memory");
+  }
+  auto* d = new thcsox_dyson_s();
+  d->n = n; d->m = ntau; d->nw = n_matsubara; d->beta = beta; d->mu = mu;
+  d->stream = static_cast<hipStream_t>(hip_stream);
+  const int64_t nn = (int64_t)n * n;
+  int rc;
+  if ((rc = dalloc(d, &d->F, nn)) || (rc = dalloc(d, &d->Wf, (size_t)2 * d->nw * d->m)) ||
+      (rc = dalloc(d, &d->Wb, (size_t)(d->m + 1) * 2 * d->nw)) ||
+      (rc = dalloc(d, &d->Siw, (size_t)2 * d->nw * nn)) ||
+      (rc = dalloc(d, &d->Aug, (size_t)d->nw * 2 * nn)) ||
+      (rc = dalloc(d, &d->Gs, (size_t)2 * d->nw * nn)) ||
+      (rc = dalloc(d, &d->Gout, (size_t)(d->m + 1) * nn)) || (rc = dalloc(d, &d->flag, 1)) ||
+      (rc = dalloc(d, &d->scal, 1))) {
+    delete d;
+    return rc;
+  }
+  const Tables& tb = tables_for(d->m, d->nw, beta);
+  hipError_t e;
+  if ((e = hipMemcpyAsync(d->F, F_dev, sizeof(double) * nn, hipMemcpyDeviceToDevice, d->stream)) ||
+      (e = hipMemcpyAsync(d->Wf, tb.Wf.data(), sizeof(double) * tb.Wf.size(),
+                          hipMemcpyHostToDevice, d->stream)) ||
+      (e = hipMemcpyAsync(d->Wb, tb.Wb.data(), sizeof(double) * tb.Wb.size(),
+                          hipMemcpyHostToDevice, d->stream)) ||
+      (e = hipStreamSynchronize(d->stream))) {
+    delete d;
+    return dfail(THCSOX_EDEVICE, std::string("dyson plan: ") + hipGetErrorString(e));
+  }
+  *out = d;
+  return 0;
+}
+
+int thcsox_dyson_step(thcsox_dyson_t d, const double* Sigma_dev, double* G_dev, double* gamma_dev) {
+  clear_error();
+  if (d == nullptr || Sigma_dev == nullptr || G_dev == nullptr)
+    return dfail(THCSOX_EINVAL, "NULL argument");
+  const int n = d->n, m = d->m, nw = d->nw;
+  const int64_t nn = (int64_t)n * n;
+  const hipStream_t s = d->stream;
+  // Sigma(i w) (real and imaginary rows) = Wf . Sigma(tau)
+  Gemm64Args g{};
+  g.M = 2 * nw; g.N = (int)nn; g.K = m; g.batch = 1; g.alpha = 1.0; g.beta = 0.0;
+  g.A = d->Wf; g.a_i = m; g.a_k = 1;
+  g.B = Sigma_dev; g.b_k = nn; g.b_j = 1;
+  g.C = d->Siw; g.c_i = nn; g.c_j = 1; g.cj_in = nn; g.cj_out = 0;
+  DTRY(gemm64(g, s));
+  const unsigned bx = (unsigned)std::min<int64_t>(64, (nn + NT - 1) / NT);
+  build_aug<<<dim3(bx, nw), NT, 0, s>>>(d->Siw, d->F, d->mu, d->beta, n, nw, d->Aug);
+  DTRY(hipGetLastError());
+  DTRY(hipMemsetAsync(d->flag, 0, sizeof(int), s));
+  gauss_jordan<<<nw, NT, sizeof(double2) * n, s>>>(d->Aug, n, d->flag);
+  DTRY(hipGetLastError());
+  extract_inv<<<dim3(bx, nw), NT, 0, s>>>(d->Aug, n, nw, d->Gs);
+  DTRY(hipGetLastError());
+  // [G(tau_0) .. G(tau_{m-1}); gamma] = Wb . [Re G(i w); Im G(i w)]
+  g.M = m + 1; g.N = (int)nn; g.K = 2 * nw;
+  g.A = d->Wb; g.a_i = 2 * nw; g.a_k = 1;
+  g.B = d->Gs; g.b_k = nn; g.b_j = 1;
+  g.C = d->Gout;
+  DTRY(gemm64(g, s));
+  DTRY(hipMemcpyAsync(G_dev, d->Gout, sizeof(double) * m * nn, hipMemcpyDeviceToDevice, s));
+  if (gamma_dev)
+    DTRY(hipMemcpyAsync(gamma_dev, d->Gout + (int64_t)m * nn, sizeof(double) * nn,
+                        hipMemcpyDeviceToDevice, s));
+  int flag = 0;
+  DTRY(hipMemcpyAsync(&flag, d->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  DTRY(hipStreamSynchronize(s));
+  if (flag) return dfail(THCSOX_ENONFINITE, "singular matrix in the Dyson solve");
+  return 0;
+}
+
+int thcsox_dyson_onebody(thcsox_dyson_t d, const double* gamma_dev, double* E1_host) {
+  clear_error();
+  if (d == nullptr || gamma_dev == nullptr || E1_host == nullptr)
+    return dfail(THCSOX_EINVAL, "NULL argument");
+  trace_ab<<<1, NT, 0, d->stream>>>(d->F, gamma_dev, d->n, d->scal);
+  DTRY(hipGetLastError());
+  DTRY(hipMemcpyAsync(E1_host, d->scal, sizeof(double), hipMemcpyDeviceToHost, d->stream));
+  DTRY(hipStreamSynchronize(d->stream));
+  return 0;
+}
+
+int thcsox_dyson_destroy(thcsox_dyson_t d) {
+  if (d == nullptr) return 0;
+  (void)hipStreamSynchronize(d->stream);
+  delete d;
+  return 0;
+}
+
+}  // extern "C"

@@ -11,19 +11,26 @@
 #include <vector>
 
 #include "../../include/thcsox.h"
+#include "error.hpp"
 #include "kernels.hpp"
 #include "mfma.hpp"
+
+namespace thcsox {
+namespace {
+thread_local std::string g_last_error;
+}
+int set_error(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+void clear_error() { clear_error(); }
+}  // namespace thcsox
 
 using namespace thcsox;
 
 namespace {
 
-thread_local std::string g_last_error;
-
-int fail(int code, const std::string& msg) {
-  g_last_error = msg;
-  return code;
-}
+int fail(int code, const std::string& msg) { return set_error(code, msg); }
 
 #define HIP_TRY(expr)                                                                  \
   do {                                                                                 \
@@ -198,6 +205,24 @@ int build_u(thcsox_plan_s* p, const double* V) {
   return 0;
 }
 
+// Sigma = X Sig_thc X^T for one tau point (FP64 matrix cores).
+int backproject_one(thcsox_plan_s* p, const double* St, double* Sig) {
+  const int n = p->n, naux = p->naux;
+  const hipStream_t s = p->stream;
+  Gemm64Args b{};
+  b.M = n; b.N = naux; b.K = naux; b.batch = 1; b.alpha = 1.0; b.beta = 0.0;
+  b.A = p->X; b.a_i = naux; b.a_k = 1;
+  b.B = St; b.b_k = naux; b.b_j = 1;
+  b.C = p->T1; b.c_i = naux; b.c_j = 1; b.cj_in = naux; b.cj_out = 0;
+  HIP_TRY(gemm64(b, s));
+  b.N = n;
+  b.A = p->T1; b.a_i = naux; b.a_k = 1;
+  b.B = p->X; b.b_k = 1; b.b_j = naux;
+  b.C = Sig; b.c_i = n; b.c_j = 1; b.cj_in = n; b.cj_out = 0;
+  HIP_TRY(gemm64(b, s));
+  return 0;
+}
+
 // One tau point k: Sigma[k] (and Sig_thc[k]) from G.
 int sigma_one(thcsox_plan_s* p, const double* G, double* Sigma, double* Sthc_out, int k) {
   const int n = p->n, naux = p->naux, ldk = p->ldk, m = p->m, mode = p->mode;
@@ -277,18 +302,7 @@ int sigma_one(thcsox_plan_s* p, const double* G, double* Sigma, double* Sthc_out
   d.amax_u = (mode == MODE_F64) ? nullptr : am + 0;
   HIP_TRY(dreduce(d, s));
 
-  // Sigma = X Sig_thc X^T
-  Gemm64Args b{};
-  b.M = n; b.N = naux; b.K = naux; b.batch = 1; b.alpha = 1.0; b.beta = 0.0;
-  b.A = p->X; b.a_i = naux; b.a_k = 1;
-  b.B = St; b.b_k = naux; b.b_j = 1;
-  b.C = p->T1; b.c_i = naux; b.c_j = 1; b.cj_in = naux; b.cj_out = 0;
-  HIP_TRY(gemm64(b, s));
-  b.N = n;
-  b.A = p->T1; b.a_i = naux; b.a_k = 1;
-  b.B = p->X; b.b_k = 1; b.b_j = naux;
-  b.C = Sigma + (int64_t)k * nn; b.c_i = n; b.c_j = 1; b.cj_in = n; b.cj_out = 0;
-  HIP_TRY(gemm64(b, s));
+  TRY(backproject_one(p, St, Sigma + (int64_t)k * nn));
   HIP_TRY(p->mark(THCSOX_STAGE_BACK, false));
   return 0;
 }
@@ -302,7 +316,7 @@ const char* thcsox_last_error(void) { return g_last_error.c_str(); }
 int thcsox_plan(thcsox_plan_t* out, int n, int naux, int ntau, double beta,
                 const double* tau_host, const double* wq_host, const double* X_dev,
                 const double* V_dev, int precision, size_t workspace_limit, void* hip_stream) {
-  g_last_error.clear();
+  clear_error();
   if (out == nullptr) return fail(THCSOX_EINVAL, "out is NULL");
   *out = nullptr;
   if (n <= 0 || naux <= 0 || ntau <= 0)
@@ -424,7 +438,7 @@ int thcsox_plan(thcsox_plan_t* out, int n, int naux, int ntau, double beta,
 
 int thcsox_sigma_sox(thcsox_plan_t p, const double* G_dev, double* Sigma_dev,
                      double* Sigma_thc_dev, int k_begin, int k_end) {
-  g_last_error.clear();
+  clear_error();
   if (p == nullptr) return fail(THCSOX_EINVAL, "plan is NULL");
   if (k_begin < 0 || k_end > p->m || k_begin >= k_end)
     return fail(THCSOX_EINVAL, "need 0 <= k_begin < k_end <= ntau");
@@ -443,9 +457,23 @@ int thcsox_sigma_sox(thcsox_plan_t p, const double* G_dev, double* Sigma_dev,
   return 0;
 }
 
+int thcsox_backproject(thcsox_plan_t p, const double* Sigma_thc_dev, double* Sigma_dev,
+                       int k_begin, int k_end) {
+  clear_error();
+  if (p == nullptr) return fail(THCSOX_EINVAL, "plan is NULL");
+  if (k_begin < 0 || k_end > p->m || k_begin >= k_end)
+    return fail(THCSOX_EINVAL, "need 0 <= k_begin < k_end <= ntau");
+  TRY(check_dev(Sigma_thc_dev, "Sigma_thc_dev"));
+  TRY(check_dev(Sigma_dev, "Sigma_dev"));
+  const int64_t nn = (int64_t)p->n * p->n, aa = (int64_t)p->naux * p->naux;
+  for (int k = k_begin; k < k_end; ++k)
+    TRY(backproject_one(p, Sigma_thc_dev + k * aa, Sigma_dev + k * nn));
+  return 0;
+}
+
 int thcsox_energy(thcsox_plan_t p, const double* G_dev, const double* Sigma_dev,
                   double* E_host) {
-  g_last_error.clear();
+  clear_error();
   if (p == nullptr) return fail(THCSOX_EINVAL, "plan is NULL");
   if (E_host == nullptr) return fail(THCSOX_EINVAL, "E_host is NULL");
   TRY(check_dev(G_dev, "G_dev"));
@@ -467,7 +495,7 @@ int thcsox_destroy(thcsox_plan_t p) {
 }
 
 int thcsox_plan_info(thcsox_plan_t p, thcsox_plan_info_t* info) {
-  g_last_error.clear();
+  clear_error();
   if (p == nullptr || info == nullptr) return fail(THCSOX_EINVAL, "NULL argument");
   const double n = p->n, na = p->naux;
   info->n = p->n; info->naux = p->naux; info->ntau = p->m; info->precision = p->mode;
@@ -481,7 +509,7 @@ int thcsox_plan_info(thcsox_plan_t p, thcsox_plan_info_t* info) {
 }
 
 int thcsox_profile(thcsox_plan_t p, int enable) {
-  g_last_error.clear();
+  clear_error();
   if (p == nullptr) return fail(THCSOX_EINVAL, "plan is NULL");
   HIP_TRY(hipStreamSynchronize(p->stream));
   p->profiling = enable != 0;
@@ -490,7 +518,7 @@ int thcsox_profile(thcsox_plan_t p, int enable) {
 }
 
 int thcsox_stage_times(thcsox_plan_t p, double* ms, int* launches) {
-  g_last_error.clear();
+  clear_error();
   if (p == nullptr || ms == nullptr || launches == nullptr)
     return fail(THCSOX_EINVAL, "NULL argument");
   HIP_TRY(hipStreamSynchronize(p->stream));

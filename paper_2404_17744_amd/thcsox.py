@@ -29,7 +29,9 @@ ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENONFINITE", -5: "ENOT
 
 # every symbol declared in include/thcsox.h
 EXPORTS = ("thcsox_plan", "thcsox_sigma_sox", "thcsox_energy", "thcsox_destroy",
-           "thcsox_last_error", "thcsox_plan_info", "thcsox_profile", "thcsox_stage_times")
+           "thcsox_last_error", "thcsox_plan_info", "thcsox_profile", "thcsox_stage_times",
+           "thcsox_backproject", "thcsox_dyson_plan", "thcsox_dyson_step",
+           "thcsox_dyson_onebody", "thcsox_dyson_destroy")
 STAGES = ("project", "a_stage", "fused", "back")
 
 
@@ -75,6 +77,16 @@ def lib() -> ctypes.CDLL:
         L.thcsox_profile.restype = i
         L.thcsox_stage_times.argtypes = [vp, ctypes.POINTER(d), ctypes.POINTER(i)]
         L.thcsox_stage_times.restype = i
+        L.thcsox_backproject.argtypes = [vp, vp, vp, i, i]
+        L.thcsox_backproject.restype = i
+        L.thcsox_dyson_plan.argtypes = [ctypes.POINTER(vp), i, i, i, d, d, vp, vp, vp]
+        L.thcsox_dyson_plan.restype = i
+        L.thcsox_dyson_step.argtypes = [vp, vp, vp, vp]
+        L.thcsox_dyson_step.restype = i
+        L.thcsox_dyson_onebody.argtypes = [vp, vp, ctypes.POINTER(d)]
+        L.thcsox_dyson_onebody.restype = i
+        L.thcsox_dyson_destroy.argtypes = [vp]
+        L.thcsox_dyson_destroy.restype = i
         _lib = L
     return _lib
 
@@ -133,6 +145,70 @@ def thcsox_stage_times(plan) -> dict:
     return {st: (ms[i], cnt[i]) for i, st in enumerate(STAGES)}
 
 
+def thcsox_backproject(plan, Sigma_thc_dev: int, Sigma_dev: int, k_begin: int, k_end: int):
+    _check(lib().thcsox_backproject(plan, Sigma_thc_dev, Sigma_dev, k_begin, k_end))
+
+
+def thcsox_dyson_plan(n: int, ntau: int, n_matsubara: int, beta: float, mu: float,
+                      tau_host: np.ndarray, F_dev: int, hip_stream: int = 0):
+    tau = np.ascontiguousarray(tau_host, dtype=np.float64)
+    h = ctypes.c_void_p()
+    _check(lib().thcsox_dyson_plan(ctypes.byref(h), n, ntau, n_matsubara, beta, mu,
+                                   tau.ctypes.data_as(ctypes.c_void_p), F_dev, hip_stream))
+    return h
+
+
+def thcsox_dyson_step(d, Sigma_dev: int, G_dev: int, gamma_dev: int | None) -> None:
+    _check(lib().thcsox_dyson_step(d, Sigma_dev, G_dev, gamma_dev))
+
+
+def thcsox_dyson_onebody(d, gamma_dev: int) -> float:
+    e = ctypes.c_double()
+    _check(lib().thcsox_dyson_onebody(d, gamma_dev, ctypes.byref(e)))
+    return e.value
+
+
+def thcsox_dyson_destroy(d) -> None:
+    _check(lib().thcsox_dyson_destroy(d))
+
+
+class Dyson:
+    """Owns one Dyson/transform plan; tensors are torch float64 device tensors."""
+
+    def __init__(self, F, mu: float, tau, beta: float, n_matsubara: int = 256, stream=None):
+        import torch
+        self.n = F.shape[0]
+        self.ntau = len(tau)
+        self.device = F.device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(F.device)
+        Fc = F.contiguous().to(torch.float64)
+        self.handle = thcsox_dyson_plan(self.n, self.ntau, n_matsubara, float(beta), float(mu),
+                                        np.asarray(tau), Fc.data_ptr(), self.stream.cuda_stream)
+
+    def step(self, Sigma, G_out=None, gamma_out=None):
+        import torch
+        if G_out is None:
+            G_out = torch.empty((self.ntau, self.n, self.n), dtype=torch.float64, device=self.device)
+        if gamma_out is None:
+            gamma_out = torch.empty((self.n, self.n), dtype=torch.float64, device=self.device)
+        thcsox_dyson_step(self.handle, Sigma.data_ptr(), G_out.data_ptr(), gamma_out.data_ptr())
+        return G_out, gamma_out
+
+    def onebody(self, gamma) -> float:
+        return thcsox_dyson_onebody(self.handle, gamma.data_ptr())
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            thcsox_dyson_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Plan:
     """Owns one libthcsox plan; tensors are torch CUDA (HIP) float64 tensors."""
 
@@ -167,6 +243,14 @@ class Plan:
 
     def energy(self, G, Sigma) -> float:
         return thcsox_energy(self.handle, G.data_ptr(), Sigma.data_ptr())
+
+    def backproject(self, Sigma_thc, k_begin: int = 0, k_end: int | None = None, out=None):
+        import torch
+        k_end = self.ntau if k_end is None else k_end
+        if out is None:
+            out = torch.zeros((self.ntau, self.n, self.n), dtype=torch.float64, device=self.device)
+        thcsox_backproject(self.handle, Sigma_thc.data_ptr(), out.data_ptr(), k_begin, k_end)
+        return out
 
     def info(self) -> dict:
         return thcsox_plan_info(self.handle)

@@ -1,0 +1,97 @@
+"""GPU parity of the FP64 self-consistency step (transforms + Dyson) against
+the oracle, and one full iteration of the n=100 / naux=500 / 64-tau workload.
+
+Tolerances: the Dyson step is FP64 end to end, so G(tau) and gamma agree with
+the oracle to 1e-10 relative; the Sigma = 0 round trip reproduces the closed
+form G0 to the accuracy of the 64-term Chebyshev fit (5e-9).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import energy as oenergy
+from oracle import sox as osox
+from oracle import transforms as otr
+from paper_2404_17744_amd import synth, thcsox
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def test_dyson_zero_sigma_roundtrip(dev):
+    s = synth.make_system(20, 40, seed=2)
+    tau, w = synth.cheb_tau_grid(64, 100.0)
+    print("case dyson n20 ntau64 Sigma=0", flush=True)
+    G0 = synth.g0_tau(s, tau, 100.0)
+    F = torch.from_numpy(s.F).to(dev)
+    d = thcsox.Dyson(F, s.mu, tau, 100.0, 256)
+    G, gam = d.step(torch.zeros((64, 20, 20), dtype=torch.float64, device=dev))
+    E1 = d.onebody(gam)
+    d.close()
+    G = G.cpu().numpy(); gam = gam.cpu().numpy()
+    assert np.abs(G - G0).max() < 5e-9
+    assert abs(np.trace(gam) - s.n_occ) < 1e-8
+    gam0 = (s.Q * (s.eps < s.mu)) @ s.Q.T
+    assert abs(E1 - float(np.sum(s.F * gam.T))) < 1e-12 * max(1.0, abs(E1))
+    assert np.abs(gam - gam0).max() < 1e-8
+
+
+def test_dyson_step_matches_oracle(dev):
+    """Sigma from the oracle at G0 (n=30, naux=120, 64 tau) -> one step."""
+    s = synth.make_system(30, 120, seed=8, lam=0.5)
+    tau, w = synth.cheb_tau_grid(64, 100.0)
+    print("case dyson n30 naux120 ntau64 lam 0.5", flush=True)
+    G0 = synth.g0_tau(s, tau, 100.0)
+    S = osox.sigma_all_tau(osox.sigma_thc_paper, G0, s.X, s.V)
+    Tm = otr.cheb_to_matsubara(64, 256, 100.0)
+    G_ref, gam_ref, _ = otr.loop_step(s.F, s.mu, 100.0, S, Tm)
+    d = thcsox.Dyson(torch.from_numpy(s.F).to(dev), s.mu, tau, 100.0, 256)
+    G, gam = d.step(torch.from_numpy(S).to(dev))
+    d.close()
+    assert _rel(G.cpu().numpy(), G_ref) < 1e-10
+    assert _rel(gam.cpu().numpy(), gam_ref) < 1e-10
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16x2"])
+def test_one_iteration_n100(dev, precision):
+    """SOX at G0, its energy, then one Dyson step, at n=100, naux=500, 64 tau,
+    256 Matsubara points (seed 0).  Energies against the stored oracle values;
+    the new G against the oracle's step from the GPU's own FP64 Sigma."""
+    name = "sox_n100_naux500_ntau64"
+    s, tau, w, G0, beta = synth.workload(name, seed=0)
+    with open(os.path.join(GOLDEN, f"oracle_{name}_seed0.json")) as f:
+        gold = json.load(f)
+    # The seeded inputs can differ in the last bits between hosts (QR and GEMMs
+    # take different BLAS code paths); that moves E by ~1e-14 Ha, far below
+    # every tolerance here, so the digest is reported, not required.
+    print("  input digest", s.digest(), "golden", gold["input_digest"])
+    print(f"case one iteration {name} seed 0 {precision}", flush=True)
+    X = torch.from_numpy(s.X).to(dev); V = torch.from_numpy(s.V).to(dev)
+    Gd = torch.from_numpy(G0).to(dev)
+    plan = thcsox.Plan(X, V, tau, w, beta, precision=precision)
+    S = plan.sigma(Gd)
+    E = plan.energy(Gd, S)
+    plan.close()
+    tol = 1e-8 if precision == "fp64" else 1e-6
+    print(f"  E_sox {E:.12f} oracle {gold['E_sox']:.12f} diff {E - gold['E_sox']:.2e}")
+    assert abs(E - gold["E_sox"]) < tol
+    Sn = S.cpu().numpy()
+    errs = [abs(Sn[k, t, r] - v) for k, t, r, v in gold["samples"]]
+    assert max(errs) / gold["sigma_absmax"] < (1e-10 if precision == "fp64" else 2e-6)
+    d = thcsox.Dyson(torch.from_numpy(s.F).to(dev), s.mu, tau, beta, 256)
+    G1, gam = d.step(S)
+    E1 = d.onebody(gam)
+    d.close()
+    if precision == "fp64":
+        Tm = otr.cheb_to_matsubara(64, 256, beta)
+        G_ref, gam_ref, _ = otr.loop_step(s.F, s.mu, beta, Sn, Tm)
+        assert _rel(G1.cpu().numpy(), G_ref) < 1e-10
+        assert _rel(gam.cpu().numpy(), gam_ref) < 1e-10
+        assert abs(E1 - float(np.sum(s.F * gam_ref.T))) < 1e-9
