@@ -166,6 +166,46 @@ int thcsox_dyson_onebody(thcsox_dyson_t d, const double* gamma_dev, double* E1_h
 
 int thcsox_dyson_destroy(thcsox_dyson_t d);
 
+/* ---------------------------------------------------------------------------
+ * Learned warm start (not part of the paper's method; it only proposes a
+ * starting self-energy that the plain SOX loop then corrects).  A residual MLP
+ * on the tau-profile of one THC pair (m inputs, m outputs, two hidden layers
+ * of width H, silu, FP32 weights and matrix cores):
+ *     y = x + W3 silu(W2 silu(W1 x + b1) + b2) + b3
+ * params: one packed FP32 array W1[H][m], b1[H], W2[H][H], b2[H], W3[m][H], b3[m].
+ * x, y, target: [batch][m] FP32 device arrays.  Loss: mean squared error.
+ * ------------------------------------------------------------------------- */
+typedef struct thcsox_mlp_s* thcsox_mlp_t;
+int thcsox_mlp_create(thcsox_mlp_t* out, int m, int hidden, int max_batch,
+                      const float* params_host, void* hip_stream);
+/* Inference for any batch size (processed max_batch rows at a time); asynchronous. */
+int thcsox_mlp_forward(thcsox_mlp_t q, const float* x_dev, float* y_dev, int batch);
+/* Loss and its gradient with respect to every parameter (packed like params);
+ * batch <= max_batch.  grads_host may be NULL.  Synchronises. */
+int thcsox_mlp_gradients(thcsox_mlp_t q, const float* x_dev, const float* target_dev, int batch,
+                         float* grads_host, double* loss_host);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on the
+ * gradient of one batch; loss_host (may be NULL) receives the batch loss
+ * before the step (then the call synchronises). */
+int thcsox_mlp_train_step(thcsox_mlp_t q, const float* x_dev, const float* target_dev, int batch,
+                          float lr, double* loss_host);
+int thcsox_mlp_params(thcsox_mlp_t q, float* params_host);
+int thcsox_mlp_destroy(thcsox_mlp_t q);
+
+/* Network inputs and outputs in the THC basis.  S is a THC-basis self-energy
+ * [m][naux][naux] (FP64, device); a "pair" is the flat index R*naux + P.
+ *   thcsox_pair_scale  : scale[k] = max_RP |S[k][R][P]| (1 if zero), FP64 [m].
+ *   thcsox_pair_gather : x[b][k] = S[k][pairs[b]] / scale[k] (pairs NULL: all
+ *                        naux^2 pairs in order), FP32 [npairs][m].
+ *   thcsox_pair_scatter: S[k][p] = y[p][k] * scale[k] for all naux^2 pairs.
+ * All asynchronous on hip_stream. */
+int thcsox_pair_scale(int m, int naux, const double* S_dev, double* scale_dev, void* hip_stream);
+int thcsox_pair_gather(int m, int naux, const double* S_dev, const double* scale_dev,
+                       const long long* pairs_dev, long long npairs, float* x_dev,
+                       void* hip_stream);
+int thcsox_pair_scatter(int m, int naux, const float* y_dev, const double* scale_dev,
+                        double* S_dev, void* hip_stream);
+
 /* Optional stage timing with HIP events recorded on the plan's stream around
  * each stage of every tau point (negligible overhead).  Stages:
  *   THCSOX_STAGE_PROJECT : projections G_Rq, G_wP, G(-tau) and their scaling/splits

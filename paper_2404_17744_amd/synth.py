@@ -159,3 +159,10 @@ def block_diag_system(parts: list[System]) -> System:
     mu = parts[0].mu
     return System(n=n, naux=naux, n_occ=sum(p.n_occ for p in parts), Q=Q, eps=eps,
                   mu=mu, X=X, V=V)
+
+
+def warmstart_system(seed: int, lam: float, n_range=(40, 160)):
+    """One system of the learned-warm-start set: n uniform in n_range (drawn from
+    its own stream), naux = 5 n, n_occ = n // 2, interaction scale lam."""
+    n = int(np.random.default_rng(seed + 10**6).integers(n_range[0], n_range[1] + 1))
+    return make_system(n, 5 * n, seed, lam=lam)

@@ -31,7 +31,10 @@ ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENONFINITE", -5: "ENOT
 EXPORTS = ("thcsox_plan", "thcsox_sigma_sox", "thcsox_energy", "thcsox_destroy",
            "thcsox_last_error", "thcsox_plan_info", "thcsox_profile", "thcsox_stage_times",
            "thcsox_backproject", "thcsox_dyson_plan", "thcsox_dyson_step",
-           "thcsox_dyson_onebody", "thcsox_dyson_destroy")
+           "thcsox_dyson_onebody", "thcsox_dyson_destroy", "thcsox_mlp_create",
+           "thcsox_mlp_forward", "thcsox_mlp_gradients", "thcsox_mlp_train_step",
+           "thcsox_mlp_params", "thcsox_mlp_destroy", "thcsox_pair_scale",
+           "thcsox_pair_gather", "thcsox_pair_scatter")
 STAGES = ("project", "a_stage", "fused", "back")
 
 
@@ -87,6 +90,26 @@ def lib() -> ctypes.CDLL:
         L.thcsox_dyson_onebody.restype = i
         L.thcsox_dyson_destroy.argtypes = [vp]
         L.thcsox_dyson_destroy.restype = i
+        fp = ctypes.c_float
+        L.thcsox_mlp_create.argtypes = [ctypes.POINTER(vp), i, i, i, vp, vp]
+        L.thcsox_mlp_create.restype = i
+        L.thcsox_mlp_forward.argtypes = [vp, vp, vp, i]
+        L.thcsox_mlp_forward.restype = i
+        L.thcsox_mlp_gradients.argtypes = [vp, vp, vp, i, vp, ctypes.POINTER(d)]
+        L.thcsox_mlp_gradients.restype = i
+        L.thcsox_mlp_train_step.argtypes = [vp, vp, vp, i, fp, ctypes.POINTER(d)]
+        L.thcsox_mlp_train_step.restype = i
+        L.thcsox_mlp_params.argtypes = [vp, vp]
+        L.thcsox_mlp_params.restype = i
+        L.thcsox_mlp_destroy.argtypes = [vp]
+        L.thcsox_mlp_destroy.restype = i
+        ll = ctypes.c_longlong
+        L.thcsox_pair_scale.argtypes = [i, i, vp, vp, vp]
+        L.thcsox_pair_scale.restype = i
+        L.thcsox_pair_gather.argtypes = [i, i, vp, vp, vp, ll, vp, vp]
+        L.thcsox_pair_gather.restype = i
+        L.thcsox_pair_scatter.argtypes = [i, i, vp, vp, vp, vp]
+        L.thcsox_pair_scatter.restype = i
         _lib = L
     return _lib
 
@@ -200,6 +223,84 @@ class Dyson:
     def close(self) -> None:
         if getattr(self, "handle", None):
             thcsox_dyson_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def thcsox_pair_scale(m, naux, S_dev, scale_dev, hip_stream=0):
+    _check(lib().thcsox_pair_scale(m, naux, S_dev, scale_dev, hip_stream))
+
+
+def thcsox_pair_gather(m, naux, S_dev, scale_dev, pairs_dev, npairs, x_dev, hip_stream=0):
+    _check(lib().thcsox_pair_gather(m, naux, S_dev, scale_dev, pairs_dev, npairs, x_dev,
+                                    hip_stream))
+
+
+def thcsox_pair_scatter(m, naux, y_dev, scale_dev, S_dev, hip_stream=0):
+    _check(lib().thcsox_pair_scatter(m, naux, y_dev, scale_dev, S_dev, hip_stream))
+
+
+class MLP:
+    """Residual warm-start MLP on the GPU (thcsox_mlp_*); params packed FP32."""
+
+    ORDER = ("W1", "b1", "W2", "b2", "W3", "b3")
+
+    def __init__(self, m: int, hidden: int, params: dict, max_batch: int = 65536, stream=None):
+        import torch
+        self.m, self.H, self.max_batch = m, hidden, max_batch
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        flat = np.concatenate([np.asarray(params[k], dtype=np.float32).ravel()
+                               for k in self.ORDER])
+        h = ctypes.c_void_p()
+        _check(lib().thcsox_mlp_create(ctypes.byref(h), m, hidden, max_batch,
+                                       flat.ctypes.data_as(ctypes.c_void_p),
+                                       self.stream.cuda_stream))
+        self.handle = h
+        self.nparam = flat.size
+
+    def _unpack(self, flat: np.ndarray) -> dict:
+        m, H = self.m, self.H
+        shapes = {"W1": (H, m), "b1": (H,), "W2": (H, H), "b2": (H,), "W3": (m, H), "b3": (m,)}
+        out, o = {}, 0
+        for k in self.ORDER:
+            size = int(np.prod(shapes[k]))
+            out[k] = flat[o:o + size].reshape(shapes[k])
+            o += size
+        return out
+
+    def forward(self, x, out=None):
+        import torch
+        if out is None:
+            out = torch.empty_like(x)
+        _check(lib().thcsox_mlp_forward(self.handle, x.data_ptr(), out.data_ptr(), x.shape[0]))
+        return out
+
+    def gradients(self, x, t):
+        g = np.empty(self.nparam, dtype=np.float32)
+        loss = ctypes.c_double()
+        _check(lib().thcsox_mlp_gradients(self.handle, x.data_ptr(), t.data_ptr(), x.shape[0],
+                                          g.ctypes.data_as(ctypes.c_void_p), ctypes.byref(loss)))
+        return loss.value, self._unpack(g)
+
+    def train_step(self, x, t, lr: float, want_loss: bool = True):
+        loss = ctypes.c_double()
+        _check(lib().thcsox_mlp_train_step(self.handle, x.data_ptr(), t.data_ptr(), x.shape[0],
+                                           lr, ctypes.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def params(self) -> dict:
+        p = np.empty(self.nparam, dtype=np.float32)
+        _check(lib().thcsox_mlp_params(self.handle, p.ctypes.data_as(ctypes.c_void_p)))
+        return self._unpack(p)
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            _check(lib().thcsox_mlp_destroy(self.handle))
             self.handle = None
 
     def __del__(self):
