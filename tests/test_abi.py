@@ -1,0 +1,88 @@
+"""The C-ABI library loads on a host without a GPU and exports every entry
+point that include/thcsox.h declares; argument checks that come before any
+device work return the documented error codes.  No compute call is made."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2404_17744_amd import build as pbuild
+from paper_2404_17744_amd import thcsox
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "thcsox.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    return sorted(set(re.findall(r"\b(thcsox_[a-z0-9_]+)\s*\(", src)))
+
+
+def _constants():
+    src = open(HEADER).read()
+    return {k: int(v) for k, v in re.findall(r"\b(THCSOX_[A-Z0-9_]+)\s*=\s*(-?\d+)", src)}
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(thcsox.LIB_PATH):
+        pbuild.build()
+    return thcsox.lib()
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    assert len(names) >= 20
+    for required in ("thcsox_plan", "thcsox_sigma_sox", "thcsox_energy", "thcsox_destroy",
+                     "thcsox_dyson_step", "thcsox_mlp_train_step", "thcsox_pair_gather"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(L):
+    missing = [s for s in _declared() if not hasattr(L, s)]
+    assert not missing, missing
+
+
+def test_binding_covers_the_header():
+    assert sorted(thcsox.EXPORTS) == _declared()
+
+
+def test_error_codes_match_binding():
+    c = _constants()
+    assert c["THCSOX_EINVAL"] == -1 and c["THCSOX_ENOMEM"] == -2
+    assert c["THCSOX_EDEVICE"] == -3 and c["THCSOX_ENONFINITE"] == -4
+    assert c["THCSOX_ENOTDEV"] == -5
+    for name, code in c.items():
+        if name in ("THCSOX_EINVAL", "THCSOX_ENOMEM", "THCSOX_EDEVICE", "THCSOX_ENONFINITE",
+                    "THCSOX_ENOTDEV"):
+            assert code in thcsox.ERRORS
+    assert c["THCSOX_FP64"] == thcsox.PRECISIONS["fp64"]
+    assert c["THCSOX_FP16X2"] == thcsox.PRECISIONS["fp16x2"]
+
+
+def test_plan_argument_checks_without_device(L):
+    """These checks run before the library touches the device."""
+    out = ctypes.c_void_p()
+    tau = (ctypes.c_double * 4)(10, 20, 80, 90)
+    w = (ctypes.c_double * 4)(1, 1, 1, 1)
+    rc = L.thcsox_plan(None, 8, 32, 4, 100.0, tau, w, None, None, 0, 0, None)
+    assert rc == -1 and b"out" in L.thcsox_last_error()
+    rc = L.thcsox_plan(ctypes.byref(out), 0, 32, 4, 100.0, tau, w, None, None, 0, 0, None)
+    assert rc == -1 and b"positive" in L.thcsox_last_error()
+    assert out.value is None
+    rc = L.thcsox_plan(ctypes.byref(out), 8, 32, 4, -1.0, tau, w, None, None, 0, 0, None)
+    assert rc == -1 and b"beta" in L.thcsox_last_error()
+    rc = L.thcsox_plan(ctypes.byref(out), 8, 32, 4, 100.0, tau, w, None, None, 9, 0, None)
+    assert rc == -1 and b"precision" in L.thcsox_last_error()
+    rc = L.thcsox_plan(ctypes.byref(out), 8, 32, 4, 100.0, None, w, None, None, 0, 0, None)
+    assert rc == -1 and b"tau_host" in L.thcsox_last_error()
+
+
+def test_null_handles_rejected(L):
+    assert L.thcsox_sigma_sox(None, None, None, None, 0, 1) == -1
+    assert L.thcsox_destroy(None) == 0          # destroying nothing is a no-op
+    assert L.thcsox_dyson_destroy(None) == 0
+    assert L.thcsox_mlp_destroy(None) == 0
