@@ -49,6 +49,33 @@ def timed_steps(plan, Gd, S, steps, torch):
     return e0.elapsed_time(e1) / steps, E, st
 
 
+def fused_source_hash():
+    """Hash of the sources that make up the fused kernel."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("fused.hip", "panel.hpp", "mfma.hpp", "kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_2404_17744_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(precision, workload):
+    """HBM bytes per fused launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary, or None when there is none or the kernel has changed since."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_fused_{precision}_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "source_sha256"):
+                k, v = line.split(":", 1)
+                kv[k] = v.strip()
+    if kv.get("source_sha256") != fused_source_hash() or "traffic_bytes_per_launch" not in kv:
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(s, G, taus):
     """The FP64 oracle (the paper's sequence) on a few tau points, host cores."""
     import numpy as np
@@ -166,7 +193,8 @@ def main():
                    "beta": beta, "seed": args.seed, "precision": args.precision,
                    "parallelism": "none (one GPU; tau points are independent)"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak,
+                     "traffic": measured_traffic(args.precision, args.workload),
                      "kernel": f"fused_kernel<{args.precision}>",
                      "avg_launch_ms": fused_avg, "launches": fused_n,
                      "algorithmic_flop_per_launch": fused_flop,

@@ -1,0 +1,76 @@
+"""Parity at the full n=300 / naux=1800 / 100-tau size (seed 0), in the same
+launch configuration the throughput measurement uses (one plan, all tau points
+in one call), against stored FP64 oracle values written by
+tests/golden/make_oracle_golden.py (the paper's order of contractions, FP64,
+every tau point).
+
+Bars: FP64 path 1e-10 relative on the sampled Sigma elements and 1e-8 Ha in
+energy; mixed paths 1e-6 Ha in energy and 1e-6 relative on the samples.
+Properties that hold at any size are checked too: Sigma(tau) is symmetric for
+symmetric inputs, and the mixed paths agree with the GPU FP64 path.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2404_17744_amd import synth, thcsox
+
+pytestmark = pytest.mark.gpu
+NAME = "sox_n300_naux1800_ntau100"
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", f"oracle_{NAME}_seed0.json")
+
+
+@pytest.fixture(scope="module")
+def case(dev):
+    s, tau, w, G, beta = synth.workload(NAME, seed=0)
+    with open(GOLDEN) as f:
+        gold = json.load(f)
+    print("  input digest", s.digest(), "golden", gold["input_digest"], flush=True)
+    X = torch.from_numpy(s.X).to(dev)
+    V = torch.from_numpy(s.V).to(dev)
+    Gd = torch.from_numpy(G).to(dev)
+    return dict(s=s, tau=tau, w=w, beta=beta, X=X, V=V, G=Gd, gold=gold, S64=None)
+
+
+def _evaluate(case, precision):
+    plan = thcsox.Plan(case["X"], case["V"], case["tau"], case["w"], case["beta"],
+                       precision=precision)
+    S = plan.sigma(case["G"])
+    E = plan.energy(case["G"], S)
+    plan.close()
+    return S, E
+
+
+def _sample_err(S, gold):
+    Sn = S.cpu().numpy()
+    return max(abs(Sn[k, t, r] - v) for k, t, r, v in gold["samples"]) / gold["sigma_absmax"]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp16x2", "bf16x3", "fp32"])
+def test_fullsize_vs_oracle(case, precision):
+    print(f"case {NAME} seed 0 {precision}", flush=True)
+    S, E = _evaluate(case, precision)
+    gold = case["gold"]
+    dE = E - gold["E_sox"]
+    err = _sample_err(S, gold)
+    print(f"  E {E:.12f} oracle {gold['E_sox']:.12f} dE {dE:.2e} sampled rel {err:.2e}")
+    # the energy integrand Tr[G(beta - tau_k) Sigma(tau_k)] at every tau point
+    tr = (case["G"].flip(0).transpose(1, 2) * S).sum((1, 2)).cpu().numpy()
+    assert np.abs(tr - np.array(gold["trace_per_tau"])).max() < \
+        (1e-9 if precision == "fp64" else 1e-5) * max(1.0, np.abs(gold["trace_per_tau"]).max())
+    if precision == "fp64":
+        assert abs(dE) <= 1e-8
+        assert err <= 1e-10
+        case["S64"] = S
+    else:
+        assert abs(dE) <= 1e-6
+        assert err <= 1e-6
+        asym = (S - S.transpose(1, 2)).abs().max().item() / S.abs().max().item()
+        assert asym <= 1e-6
+        if case["S64"] is not None:
+            d = (S - case["S64"]).abs().max().item() / case["S64"].abs().max().item()
+            print(f"  vs GPU FP64 path: max rel {d:.2e}")
+            assert d <= 1e-6
