@@ -30,6 +30,16 @@ PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 6, "fp16x2": 3}
 HBM_PEAK_GBS = 8000.0
 
 
+def fused_flop_per_launch(plan, info, m):
+    """Algorithmic flops of one fused launch: 2 products of length n for every
+    (R, P) pair formed -- all naux^2 pairs, or naux (naux + 1) / 2 where the
+    symmetric path applies -- averaged over the tau points of one step."""
+    n, na = info["n"], info["naux"]
+    flags = plan.symmetric_flags()
+    pairs = [na * (na + 1) / 2 if f else na * na for f in flags]
+    return 2.0 * 2.0 * n * n * sum(pairs) / m, int(sum(flags))
+
+
 def timed_steps(plan, Gd, S, steps, torch):
     """Run `steps` steps between two events on the plan's stream; returns
     (ms per step, last energy, stage times)."""
@@ -111,6 +121,7 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=1)
     ap.add_argument("--cpu-taus", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--symmetry", default="auto", choices=["auto", "off"])
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -132,6 +143,7 @@ def main():
 
     t0 = time.time()
     plan = thcsox.Plan(X, V, tau, w, beta, precision=args.precision)
+    plan.set_symmetry(args.symmetry)
     plan_s = time.time() - t0
     info = plan.info()
     for _ in range(args.warmup):
@@ -139,11 +151,11 @@ def main():
         plan.energy(Gd, S)
     ms, E_mixed, st = timed_steps(plan, Gd, S, args.steps, torch)
     S_mixed = S.clone()
+    fused_flop, n_sym = fused_flop_per_launch(plan, info, m)
     plan.close()
 
     fused_ms, fused_n = st["fused"]
     fused_avg = fused_ms / max(1, fused_n)
-    fused_flop = 2.0 * info["fused_mac_per_tau"]
     achieved = fused_flop / (fused_avg * 1e-3) / 1e12
     peak = PEAK[args.precision]
 
@@ -151,6 +163,7 @@ def main():
     fp64 = None
     if args.fp64_steps > 0:
         p64 = thcsox.Plan(X, V, tau, w, beta, precision="fp64")
+        p64.set_symmetry(args.symmetry)
         S64 = torch.zeros_like(Gd)
         p64.sigma(Gd, 0, 2, out=S64)
         ms64, E64, st64 = timed_steps(p64, Gd, S64, args.fp64_steps, torch)
@@ -191,6 +204,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n": s.n, "naux": s.naux, "ntau": m,
                    "beta": beta, "seed": args.seed, "precision": args.precision,
+                   "symmetry": args.symmetry,
                    "parallelism": "none (one GPU; tau points are independent)"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak,
@@ -198,6 +212,7 @@ def main():
                      "kernel": f"fused_kernel<{args.precision}>",
                      "avg_launch_ms": fused_avg, "launches": fused_n,
                      "algorithmic_flop_per_launch": fused_flop,
+                     "symmetric_tau_points": n_sym,
                      "plane_products": PRODUCTS[args.precision],
                      "mfma_busy_frac": achieved * PRODUCTS[args.precision] / peak},
         "tflops_whole_step": 2.0 * info["mac_per_tau"] * m / (ms * 1e-3) / 1e12,

@@ -98,9 +98,26 @@ int thcsox_plan(thcsox_plan_t* out, int n, int naux, int ntau, double beta,
  *   Sigma_thc_dev[ntau][naux][naux] : optional (NULL to skip); slots
  *                    k_begin..k_end-1 receive Sig_RP (as computed above; it is
  *                    not unique, X has rank <= n).
+ * Symmetric inputs: when G(tau_k) and G(beta - tau_k) are both symmetric to
+ * within 1e-12 of their largest element (checked on the device at every call,
+ * see thcsox_set_symmetry), D_PR = D_RP holds (U_Pqs = U_Psq by construction),
+ * so only tiles of D touching the upper triangle are formed and the rest is
+ * mirrored; Sigma changes by at most about that relative asymmetry.
  * 0 <= k_begin < k_end <= ntau.  Sigma must not alias G.  Asynchronous. */
 int thcsox_sigma_sox(thcsox_plan_t p, const double* G_dev, double* Sigma_dev,
                      double* Sigma_thc_dev, int k_begin, int k_end);
+
+/* Use of the symmetry of D described at thcsox_sigma_sox:
+ *   THCSOX_SYM_AUTO (default): per tau point, where the inputs are symmetric;
+ *   THCSOX_SYM_OFF: never (every tile of D is formed).
+ * Synchronises the plan's stream.  THCSOX_EINVAL for another mode. */
+enum { THCSOX_SYM_AUTO = 0, THCSOX_SYM_OFF = 1 };
+int thcsox_set_symmetry(thcsox_plan_t p, int mode);
+
+/* flags_host[ntau]: 1 for each tau point the last thcsox_sigma_sox call would
+ * (or did) take the symmetric path for, 0 otherwise (all 0 under
+ * THCSOX_SYM_OFF).  Synchronises the plan's stream. */
+int thcsox_symmetric_flags(thcsox_plan_t p, int* flags_host);
 
 /* Galitskii-Migdal dynamic energy of Eq. E2b, read as the spin-orbital form
  * with a factor 1/2 and evaluated on the tau grid:

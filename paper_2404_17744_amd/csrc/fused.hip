@@ -83,6 +83,8 @@ __global__ __launch_bounds__(NT) void fused_kernel(FusedArgs f) {
   const int rb0 = band * BAND, bh = min(BAND, nrb - rb0);
   const int within = to - rb0 * npb;
   const int P0 = (within / bh) * TP, R0 = (rb0 + within % bh) * TR;
+  // symmetric D: a tile wholly below the diagonal is the mirror of one above it
+  if (f.sym != nullptr && *f.sym != 0 && R0 >= P0 + TP) return;
   const int v_lo = z * f.vchunk;
   const int v_hi = min(f.n, v_lo + f.vchunk);
   const int kst = f.ldk / BK;

@@ -100,7 +100,7 @@ __global__ __launch_bounds__(NT) void split_kernel(SplitArgs a) {
   constexpr int NP = ModeT<M>::NP;
   const int64_t row = blockIdx.x;
   const int64_t r1 = row / a.rows2, r2 = row % a.rows2;
-  const double sc = pow2_scale(a.amax);
+  const double sc = pow2_scale(a.amax ? a.amax + r2 * a.amax_s2 : nullptr);
   T* dst = static_cast<T*>(a.dst);
   const int64_t so = r1 * a.s1 + r2 * a.s2;
   const int64_t dof = r1 * a.d1 + r2 * a.d2;
@@ -140,12 +140,41 @@ __global__ __launch_bounds__(NT) void dreduce_kernel(DReduceArgs a) {
                    pow2_scale(a.amax_a) * pow2_scale(a.amax_u) * pow2_scale(a.amax_u);
   const double inv = 1.0 / f;   // exact: a power of two
   const int64_t nn = (int64_t)a.naux * a.naux;
+  const bool sym = a.sym != nullptr && *a.sym != 0;
   for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < nn; e += (int64_t)gridDim.x * NT) {
-    double s = 0.0;
-    for (int z = 0; z < a.vsplit; ++z) s += a.Dpart[z * nn + e];
     const int64_t R = e / a.naux, P = e % a.naux;
+    const int64_t src = (sym && R > P) ? P * a.naux + R : e;
+    double s = 0.0;
+    for (int z = 0; z < a.vsplit; ++z) s += a.Dpart[z * nn + src];
     a.Sthc[R * a.s_ld + P] = -inv * s;
   }
+}
+
+// max |G[k][i][j] - G[k][j][i]| over j > i; a row of workgroups per k strides over G[k].
+__global__ __launch_bounds__(NT) void asym_kernel(const double* G, int n,
+                                                  unsigned long long* asym) {
+  const int k = blockIdx.y;
+  const double* g = G + (int64_t)k * n * n;
+  double m = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < (int64_t)n * n;
+       e += (int64_t)gridDim.x * NT) {
+    const int i = (int)(e / n), j = (int)(e % n);
+    if (j > i) m = fmax(m, fabs(g[(int64_t)i * n + j] - g[(int64_t)j * n + i]));
+  }
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0) atomicMax(asym + k, (unsigned long long)__double_as_longlong(m));
+}
+
+__global__ void sym_flags_kernel(const unsigned long long* asym, const unsigned long long* amax,
+                                 int m, double rtol, int* flag) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= m) return;
+  auto ok = [&](int j) {
+    const double a = __longlong_as_double((long long)asym[j]);
+    const double g = __longlong_as_double((long long)amax[j]);
+    return a <= rtol * g;
+  };
+  flag[k] = (ok(k) && ok(m - 1 - k)) ? 1 : 0;
 }
 
 __global__ __launch_bounds__(NT) void khatri_rao_kernel(const double* X, int n, int naux, int q0,
@@ -232,6 +261,22 @@ hipError_t dreduce(const DReduceArgs& a, hipStream_t s) {
   unsigned b = cdiv(nn, NT);
   if (b > 8192) b = 8192;
   dreduce_kernel<<<b, NT, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t asym64(const double* G, int n, int m, unsigned long long* asym, hipStream_t s) {
+  if (n <= 0 || m <= 0) return hipSuccess;
+  unsigned bx = cdiv((int64_t)n * n, NT);
+  if (bx > 256) bx = 256;
+  fill_u64_kernel<<<cdiv(m, NT), NT, 0, s>>>(asym, m, 0ull);
+  asym_kernel<<<dim3(bx, m), NT, 0, s>>>(G, n, asym);
+  return hipGetLastError();
+}
+
+hipError_t sym_flags(const unsigned long long* asym, const unsigned long long* amax, int m,
+                     double rtol, int* flag, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  sym_flags_kernel<<<cdiv(m, 64), 64, 0, s>>>(asym, amax, m, rtol, flag);
   return hipGetLastError();
 }
 

@@ -48,20 +48,24 @@ struct FusedArgs {
   bool a_f32;
   const unsigned long long* amax_a;
   double* Dpart;                                       // [vsplit][naux][naux]
+  // If sym != nullptr and *sym != 0, D is symmetric (G(tau) and G(beta - tau)
+  // symmetric): tiles lying wholly below the diagonal (every R > every P) are
+  // skipped and their Dpart entries are left untouched.
+  const int* sym;
 };
 hipError_t sox_fused(int mode, const FusedArgs& f, hipStream_t s);
 void fused_tile(int mode, int* rows, int* cols);   // D tile one workgroup owns (R x P)
 int fused_xcds();   // vsplit must be a multiple of this (one v range per XCD in turn)
 
 // Split rows of an FP64 source into the planes of a mode, scaled by the power of
-// two 2^-floor(log2(*amax)) (scale 1 if amax is null or zero):
+// two 2^-floor(log2(amax[r2 * amax_s2])) (scale 1 if amax is null or zero):
 //   src(r1,r2,c) = src[r1*s1 + r2*s2 + c*sc],  dst plane p:
 //   dst[p*d_plane + r1*d1 + r2*d2 + c] for c < cols, zero for cols <= c < ldk.
 struct SplitArgs {
   int rows1, rows2, cols, ldk;
   const void* src; bool src_f32; int64_t s1, s2, sc;
   void* dst; int64_t d1, d2, d_plane;
-  const unsigned long long* amax;
+  const unsigned long long* amax; int64_t amax_s2;
 };
 hipError_t split_planes(int mode, const SplitArgs& a, hipStream_t s);
 
@@ -72,6 +76,8 @@ hipError_t fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipS
 
 // Sthc[R][P] = -factor * sum_z Dpart[z][R][P], factor = product of the inverse
 // operand scales (see scale_factor in the kernel source).
+// With sym != nullptr and *sym != 0 (symmetric D, lower tiles skipped by the
+// fused stage), entries with R > P are taken from the mirrored position P, R.
 struct DReduceArgs {
   int naux, vsplit;
   const double* Dpart;
@@ -79,8 +85,16 @@ struct DReduceArgs {
   const unsigned long long* amax_gt; const unsigned long long* amax_gx;
   const unsigned long long* amax_gb; const unsigned long long* amax_a;
   const unsigned long long* amax_u;
+  const int* sym;
 };
 hipError_t dreduce(const DReduceArgs& a, hipStream_t s);
+
+// asym[k] = max |G[k] - G[k]^T| (as the bits of a non-negative double), k < m.
+hipError_t asym64(const double* G, int n, int m, unsigned long long* asym, hipStream_t s);
+// flag[k] = 1 if both G[k] and G[m-1-k] are symmetric to within rtol of their
+// largest element (asym[k] <= rtol * amax[k]), else 0.
+hipError_t sym_flags(const unsigned long long* asym, const unsigned long long* amax, int m,
+                     double rtol, int* flag, hipStream_t s);
 
 // KR[(q - q0)*n + s][Q] = X[q][Q] * X[s][Q] for q in [q0, q1).
 hipError_t khatri_rao(const double* X, int n, int naux, int q0, int q1, double* KR,

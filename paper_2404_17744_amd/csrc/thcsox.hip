@@ -23,7 +23,7 @@ int set_error(int code, const std::string& msg) {
   g_last_error = msg;
   return code;
 }
-void clear_error() { clear_error(); }
+void clear_error() { g_last_error.clear(); }
 }  // namespace thcsox
 
 using namespace thcsox;
@@ -31,6 +31,10 @@ using namespace thcsox;
 namespace {
 
 int fail(int code, const std::string& msg) { return set_error(code, msg); }
+
+// G(tau) counts as symmetric when max |G - G^T| <= SYM_RTOL max |G|; the
+// symmetric-D path then changes Sigma by at most about that relative amount.
+constexpr double SYM_RTOL = 1e-12;
 
 #define HIP_TRY(expr)                                                                  \
   do {                                                                                 \
@@ -78,18 +82,28 @@ struct thcsox_plan_s {
   void* A = nullptr;        // planes of [n][naux][ldk]
   int64_t a_plane = 0;
   float* A32 = nullptr;     // [n][naux][ldk], split modes only
-  void* Gt = nullptr;       // planes of [naux][ldk]
+  int tb = 1;               // tau points per projection / back-projection batch
+  void* Gt = nullptr;       // planes of [tb][naux][ldk]
   void* GX = nullptr;
   int64_t g_plane = 0;
-  void* Gb = nullptr;       // planes of [n][ldk]: G(-tau)^T
+  void* Gb = nullptr;       // planes of [tb][n][ldk]: G(beta - tau)^T
   int64_t gb_plane = 0;
-  double* Gt64 = nullptr;   // [naux][n]
-  double* GX64 = nullptr;   // [naux][n]
+  double* Gt64 = nullptr;   // [tb][naux][n]
+  double* GX64 = nullptr;   // [tb][naux][n]
   double* Dpart = nullptr;  // [vsplit][naux][naux]
   int vsplit = 1, vchunk = 1;
-  double* Sthc = nullptr;   // [naux][naux]
-  double* T1 = nullptr;     // [n][naux]
-  unsigned long long* amax = nullptr;   // [5 + m]: U, Gt, GX, (unused), A, G[k]
+  double* Sthc = nullptr;   // [tb][naux][naux]
+  double* T1 = nullptr;     // [tb][n][naux]
+  // max-abs values as the bits of non-negative doubles: [0] U, then five arrays
+  // of m per-tau entries: Gt, GX, A, G[k], asymmetry of G[k]
+  unsigned long long* amax = nullptr;
+  int* symflag = nullptr;   // [m]: 1 where the symmetric-D path applies
+  int sym_mode = THCSOX_SYM_AUTO;
+  unsigned long long* am_gt() { return amax + 1; }
+  unsigned long long* am_gx() { return amax + 1 + m; }
+  unsigned long long* am_a() { return amax + 1 + 2 * (int64_t)m; }
+  unsigned long long* am_g() { return amax + 1 + 3 * (int64_t)m; }
+  unsigned long long* am_asym() { return amax + 1 + 4 * (int64_t)m; }
   // optional per-stage timing with events on the plan's stream
   bool profiling = false;
   struct Timer {
@@ -162,7 +176,7 @@ int build_u(thcsox_plan_s* p, const double* V) {
   TRY(p->alloc(&KR, (size_t)qb * n * naux));
   double* Uc = nullptr;
   if (p->mode != MODE_F64) TRY(p->alloc(&Uc, (size_t)qb * n * naux));
-  HIP_TRY(fill_u64(p->amax, 5, 0ull, s));
+  HIP_TRY(fill_u64(p->amax, 1, 0ull, s));
   const int passes = p->mode == MODE_F64 ? 1 : 2;
   for (int pass = 0; pass < passes; ++pass) {
     for (int q0 = 0; q0 < n; q0 += qb) {
@@ -205,104 +219,121 @@ int build_u(thcsox_plan_s* p, const double* V) {
   return 0;
 }
 
-// Sigma = X Sig_thc X^T for one tau point (FP64 matrix cores).
-int backproject_one(thcsox_plan_s* p, const double* St, double* Sig) {
+// Sigma[b] = X Sig_thc[b] X^T for nb tau points at once (FP64 matrix cores);
+// Sig_thc[b] = St + b * st_stride, Sigma[b] = Sig + b * n * n.
+int backproject_batch(thcsox_plan_s* p, const double* St, int64_t st_stride, double* Sig,
+                      int nb) {
   const int n = p->n, naux = p->naux;
   const hipStream_t s = p->stream;
   Gemm64Args b{};
-  b.M = n; b.N = naux; b.K = naux; b.batch = 1; b.alpha = 1.0; b.beta = 0.0;
-  b.A = p->X; b.a_i = naux; b.a_k = 1;
-  b.B = St; b.b_k = naux; b.b_j = 1;
-  b.C = p->T1; b.c_i = naux; b.c_j = 1; b.cj_in = naux; b.cj_out = 0;
+  b.M = n; b.N = naux; b.K = naux; b.batch = nb; b.alpha = 1.0; b.beta = 0.0;
+  b.A = p->X; b.a_i = naux; b.a_k = 1; b.a_b = 0;
+  b.B = St; b.b_k = naux; b.b_j = 1; b.b_b = st_stride;
+  b.C = p->T1; b.c_i = naux; b.c_j = 1; b.cj_in = naux; b.cj_out = 0; b.c_b = (int64_t)n * naux;
   HIP_TRY(gemm64(b, s));
   b.N = n;
-  b.A = p->T1; b.a_i = naux; b.a_k = 1;
-  b.B = p->X; b.b_k = 1; b.b_j = naux;
-  b.C = Sig; b.c_i = n; b.c_j = 1; b.cj_in = n; b.cj_out = 0;
+  b.A = p->T1; b.a_i = naux; b.a_k = 1; b.a_b = (int64_t)n * naux;
+  b.B = p->X; b.b_k = 1; b.b_j = naux; b.b_b = 0;
+  b.C = Sig; b.c_i = n; b.c_j = 1; b.cj_in = n; b.cj_out = 0; b.c_b = (int64_t)n * n;
   HIP_TRY(gemm64(b, s));
   return 0;
 }
 
-// One tau point k: Sigma[k] (and Sig_thc[k]) from G.
-int sigma_one(thcsox_plan_s* p, const double* G, double* Sigma, double* Sthc_out, int k) {
+// Tau points k0 <= k < k1 (k1 - k0 <= tb): Sigma[k] (and Sig_thc[k]) from G.
+// Needs the per-tau max |G[k]| and the symmetry flags of every k (set by the caller).
+int sigma_batch(thcsox_plan_s* p, const double* G, double* Sigma, double* Sthc_out, int k0,
+                int k1) {
   const int n = p->n, naux = p->naux, ldk = p->ldk, m = p->m, mode = p->mode;
+  const int nb = k1 - k0;
   const hipStream_t s = p->stream;
-  const int64_t nn = (int64_t)n * n;
-  const double* Gk = G + (int64_t)k * nn;
-  const double* Gbar = G + (int64_t)(m - 1 - k) * nn;
-  unsigned long long* am = p->amax;
+  const int64_t nn = (int64_t)n * n, an = (int64_t)naux * n, aa = (int64_t)naux * naux;
+  const size_t es = p->esize;
   HIP_TRY(p->mark(THCSOX_STAGE_PROJECT, true));
-  HIP_TRY(fill_u64(am + 1, 4, 0ull, s));
+  HIP_TRY(fill_u64(p->am_gt() + k0, nb, 0ull, s));
+  HIP_TRY(fill_u64(p->am_gx() + k0, nb, 0ull, s));
+  HIP_TRY(fill_u64(p->am_a() + k0, nb, 0ull, s));
 
-  // projections: Gt[R][q] = sum_u X[u][R] G[u][q];  GX[P][w] = sum_p G[w][p] X[p][P]
+  // projections of the batch: Gt[b][R][q] = sum_u X[u][R] G[k0+b][u][q],
+  // GX[b][P][w] = sum_p G[k0+b][w][p] X[p][P]
   Gemm64Args g{};
-  g.M = naux; g.N = n; g.K = n; g.batch = 1; g.alpha = 1.0; g.beta = 0.0;
-  g.A = p->X; g.a_i = 1; g.a_k = naux;
-  g.B = Gk; g.b_k = n; g.b_j = 1;
-  g.C = p->Gt64; g.c_i = n; g.c_j = 1; g.cj_in = n; g.cj_out = 0;
+  g.M = naux; g.N = n; g.K = n; g.batch = nb; g.alpha = 1.0; g.beta = 0.0;
+  g.A = p->X; g.a_i = 1; g.a_k = naux; g.a_b = 0;
+  g.B = G + (int64_t)k0 * nn; g.b_k = n; g.b_j = 1; g.b_b = nn;
+  g.C = p->Gt64; g.c_i = n; g.c_j = 1; g.cj_in = n; g.cj_out = 0; g.c_b = an;
   HIP_TRY(gemm64(g, s));
-  g.B = Gk; g.b_k = 1; g.b_j = n;
+  g.b_k = 1; g.b_j = n;
   g.C = p->GX64;
   HIP_TRY(gemm64(g, s));
-  HIP_TRY(absmax64(p->Gt64, (int64_t)naux * n, 0, 1, am + 1, s));
-  HIP_TRY(absmax64(p->GX64, (int64_t)naux * n, 0, 1, am + 2, s));
+  HIP_TRY(absmax64(p->Gt64, an, an, nb, p->am_gt() + k0, s));
+  HIP_TRY(absmax64(p->GX64, an, an, nb, p->am_gx() + k0, s));
 
   SplitArgs sa{};
-  sa.rows1 = naux; sa.rows2 = 1; sa.cols = n; sa.ldk = ldk;
-  sa.src_f32 = false; sa.s1 = n; sa.s2 = 0; sa.sc = 1;
-  sa.d1 = ldk; sa.d2 = 0; sa.d_plane = p->g_plane;
-  sa.src = p->Gt64; sa.dst = p->Gt; sa.amax = am + 1;
+  sa.rows1 = naux; sa.rows2 = nb; sa.cols = n; sa.ldk = ldk;
+  sa.src_f32 = false; sa.s1 = n; sa.s2 = an; sa.sc = 1;
+  sa.d1 = ldk; sa.d2 = (int64_t)naux * ldk; sa.d_plane = p->g_plane;
+  sa.src = p->Gt64; sa.dst = p->Gt; sa.amax = p->am_gt() + k0; sa.amax_s2 = 1;
   HIP_TRY(split_planes(mode, sa, s));
-  sa.src = p->GX64; sa.dst = p->GX; sa.amax = am + 2;
+  sa.src = p->GX64; sa.dst = p->GX; sa.amax = p->am_gx() + k0;
   HIP_TRY(split_planes(mode, sa, s));
-  // G(-tau)^T: row v holds G(beta - tau)[s][v] over s
-  sa.rows1 = n; sa.src = Gbar; sa.s1 = 1; sa.sc = n;
-  sa.dst = p->Gb; sa.d_plane = p->gb_plane; sa.amax = am + 5 + (m - 1 - k);
+  // G(beta - tau)^T of each tau of the batch: row v holds G[m-1-k][s][v] over s
+  sa.rows1 = n; sa.src = G + (int64_t)(m - 1 - k0) * nn; sa.s1 = 1; sa.s2 = -nn; sa.sc = n;
+  sa.d2 = (int64_t)n * ldk; sa.dst = p->Gb; sa.d_plane = p->gb_plane;
+  sa.amax = p->am_g() + (m - 1 - k0); sa.amax_s2 = -1;
   HIP_TRY(split_planes(mode, sa, s));
   HIP_TRY(p->mark(THCSOX_STAGE_PROJECT, false));
 
-  // A[v][P][q] = sum_s U[P][q][s] G(-tau)[s][v]: rows (P,q) of U against rows v of G(-tau)^T
-  HIP_TRY(p->mark(THCSOX_STAGE_A, true));
-  GemmKArgs ga{};
-  ga.M = naux * n; ga.N = n; ga.kpad = ldk; ga.alpha = 1.0;
-  ga.A = p->U; ga.lda = ldk; ga.a_plane = p->u_plane;
-  ga.B = p->Gb; ga.ldb = ldk; ga.b_plane = p->gb_plane;
-  ga.ci_in = n; ga.ci_out = ldk; ga.c_j = (int64_t)naux * ldk;
   const bool split_a = (mode == MODE_BF16X3 || mode == MODE_F16X2);
-  if (mode == MODE_F64) {
-    ga.C = p->A; ga.amax = nullptr;
-    HIP_TRY(gemm_kmajor(mode, true, ga, s));
-  } else if (mode == MODE_F32) {
-    ga.C = p->A; ga.amax = nullptr;
-    HIP_TRY(gemm_kmajor(mode, false, ga, s));
-  } else {
-    // FP32 A; the fused kernel splits it into planes with the scale from max|A|
-    ga.C = p->A32; ga.amax = am + 4;
-    HIP_TRY(gemm_kmajor(mode, false, ga, s));
+  for (int b = 0; b < nb; ++b) {
+    const int k = k0 + b, kb = m - 1 - k;
+    const int* sym = p->sym_mode == THCSOX_SYM_AUTO ? p->symflag + k : nullptr;
+    // A[v][P][q] = sum_s U[P][q][s] G(beta - tau)[s][v]: rows (P,q) of U against rows v of Gb
+    HIP_TRY(p->mark(THCSOX_STAGE_A, true));
+    GemmKArgs ga{};
+    ga.M = naux * n; ga.N = n; ga.kpad = ldk; ga.alpha = 1.0;
+    ga.A = p->U; ga.lda = ldk; ga.a_plane = p->u_plane;
+    ga.B = static_cast<const char*>(p->Gb) + (size_t)b * n * ldk * es;
+    ga.ldb = ldk; ga.b_plane = p->gb_plane;
+    ga.ci_in = n; ga.ci_out = ldk; ga.c_j = (int64_t)naux * ldk;
+    if (mode == MODE_F64 || mode == MODE_F32) {
+      ga.C = p->A; ga.amax = nullptr;
+      HIP_TRY(gemm_kmajor(mode, mode == MODE_F64, ga, s));
+    } else {
+      // FP32 A; the fused kernel splits it into planes with the scale from max|A|
+      ga.C = p->A32; ga.amax = p->am_a() + k;
+      HIP_TRY(gemm_kmajor(mode, false, ga, s));
+    }
+    HIP_TRY(p->mark(THCSOX_STAGE_A, false));
+
+    FusedArgs f{};
+    f.n = n; f.naux = naux; f.ldk = ldk; f.vsplit = p->vsplit; f.vchunk = p->vchunk;
+    f.Gt = static_cast<const char*>(p->Gt) + (size_t)b * naux * ldk * es;
+    f.GXt = static_cast<const char*>(p->GX) + (size_t)b * naux * ldk * es;
+    f.g_plane = p->g_plane;
+    f.U = p->U; f.u_plane = p->u_plane;
+    f.A = split_a ? static_cast<const void*>(p->A32) : p->A; f.a_plane = p->a_plane;
+    f.a_f32 = split_a; f.amax_a = split_a ? p->am_a() + k : nullptr;
+    f.Dpart = p->Dpart;
+    f.sym = sym;
+    HIP_TRY(p->mark(THCSOX_STAGE_FUSED, true));
+    HIP_TRY(sox_fused(mode, f, s));
+    HIP_TRY(p->mark(THCSOX_STAGE_FUSED, false));
+
+    HIP_TRY(p->mark(THCSOX_STAGE_BACK, true));
+    DReduceArgs d{};
+    d.naux = naux; d.vsplit = p->vsplit; d.Dpart = p->Dpart;
+    d.Sthc = Sthc_out ? Sthc_out + (int64_t)k * aa : p->Sthc + (int64_t)b * aa;
+    d.s_ld = naux;
+    d.amax_gt = p->am_gt() + k; d.amax_gx = p->am_gx() + k; d.amax_gb = p->am_g() + kb;
+    d.amax_a = split_a ? p->am_a() + k : nullptr;
+    d.amax_u = (mode == MODE_F64) ? nullptr : p->amax;
+    d.sym = sym;
+    HIP_TRY(dreduce(d, s));
+    HIP_TRY(p->mark(THCSOX_STAGE_BACK, false));
   }
-  HIP_TRY(p->mark(THCSOX_STAGE_A, false));
 
-  FusedArgs f{};
-  f.n = n; f.naux = naux; f.ldk = ldk; f.vsplit = p->vsplit; f.vchunk = p->vchunk;
-  f.Gt = p->Gt; f.GXt = p->GX; f.g_plane = p->g_plane;
-  f.U = p->U; f.u_plane = p->u_plane;
-  f.A = split_a ? static_cast<const void*>(p->A32) : p->A; f.a_plane = p->a_plane;
-  f.a_f32 = split_a; f.amax_a = split_a ? am + 4 : nullptr;
-  f.Dpart = p->Dpart;
-  HIP_TRY(p->mark(THCSOX_STAGE_FUSED, true));
-  HIP_TRY(sox_fused(mode, f, s));
-  HIP_TRY(p->mark(THCSOX_STAGE_FUSED, false));
   HIP_TRY(p->mark(THCSOX_STAGE_BACK, true));
-
-  double* St = Sthc_out ? Sthc_out + (int64_t)k * naux * naux : p->Sthc;
-  DReduceArgs d{};
-  d.naux = naux; d.vsplit = p->vsplit; d.Dpart = p->Dpart; d.Sthc = St; d.s_ld = naux;
-  d.amax_gt = am + 1; d.amax_gx = am + 2; d.amax_gb = am + 5 + (m - 1 - k);
-  d.amax_a = split_a ? am + 4 : nullptr;
-  d.amax_u = (mode == MODE_F64) ? nullptr : am + 0;
-  HIP_TRY(dreduce(d, s));
-
-  TRY(backproject_one(p, St, Sigma + (int64_t)k * nn));
+  const double* St = Sthc_out ? Sthc_out + (int64_t)k0 * aa : p->Sthc;
+  TRY(backproject_batch(p, St, aa, Sigma + (int64_t)k0 * nn, nb));
   HIP_TRY(p->mark(THCSOX_STAGE_BACK, false));
   return 0;
 }
@@ -386,12 +417,28 @@ int thcsox_plan(thcsox_plan_t* out, int n, int naux, int ntau, double beta,
   const size_t es = p->esize, np = p->np;
   p->u_plane = (int64_t)naux * n * ldk;
   p->a_plane = (int64_t)n * naux * ldk;
-  p->g_plane = (int64_t)naux * ldk;
-  p->gb_plane = (int64_t)n * ldk;
+  {
+    // tau batch of the projections and back-projection: up to 16 points within ~2 GB
+    const double per_tau = 8.0 * (2.0 * naux * n + (double)naux * naux + (double)n * naux) +
+                           (double)p->np * p->esize * ((2.0 * naux + n) * ldk);
+    double cap = 2.0e9;
+    if (workspace_limit > 0) {
+      // what the plan keeps besides the batch buffers, plus 1 MiB of slack
+      const double fixed = 8.0 * ((double)n * naux + 7.0 * ntau + 2.0) +
+                           (double)p->np * p->esize * naux * n * ldk +
+                           (p->np > 1 ? 4.0 : (double)p->esize) * n * naux * ldk +
+                           8.0 * p->vsplit * (double)naux * naux + (1 << 20);
+      cap = std::min(cap, (double)workspace_limit - fixed);
+    }
+    p->tb = (int)std::max(1.0, std::min({16.0, (double)ntau, std::floor(cap / per_tau)}));
+  }
+  p->g_plane = (int64_t)p->tb * naux * ldk;
+  p->gb_plane = (int64_t)p->tb * n * ldk;
   char* tmp = nullptr;
   if ((rc = p->alloc(&p->X, (size_t)n * naux))) return bail(rc);
   if ((rc = p->alloc(&p->w, (size_t)ntau))) return bail(rc);
-  if ((rc = p->alloc(&p->amax, (size_t)5 + ntau))) return bail(rc);
+  if ((rc = p->alloc(&p->amax, (size_t)1 + 5 * (size_t)ntau))) return bail(rc);
+  if ((rc = p->alloc(&p->symflag, (size_t)ntau))) return bail(rc);
   if ((rc = p->alloc(&p->tr, (size_t)ntau))) return bail(rc);
   if ((rc = p->alloc(&p->E, 1))) return bail(rc);
   if ((rc = p->alloc(&tmp, np * es * (size_t)p->u_plane))) return bail(rc);
@@ -408,11 +455,11 @@ int thcsox_plan(thcsox_plan_t* out, int n, int naux, int ntau, double beta,
   p->GX = tmp;
   if ((rc = p->alloc(&tmp, np * es * (size_t)p->gb_plane))) return bail(rc);
   p->Gb = tmp;
-  if ((rc = p->alloc(&p->Gt64, (size_t)naux * n))) return bail(rc);
-  if ((rc = p->alloc(&p->GX64, (size_t)naux * n))) return bail(rc);
+  if ((rc = p->alloc(&p->Gt64, (size_t)p->tb * naux * n))) return bail(rc);
+  if ((rc = p->alloc(&p->GX64, (size_t)p->tb * naux * n))) return bail(rc);
   if ((rc = p->alloc(&p->Dpart, (size_t)p->vsplit * naux * naux))) return bail(rc);
-  if ((rc = p->alloc(&p->Sthc, (size_t)naux * naux))) return bail(rc);
-  if ((rc = p->alloc(&p->T1, (size_t)n * naux))) return bail(rc);
+  if ((rc = p->alloc(&p->Sthc, (size_t)p->tb * naux * naux))) return bail(rc);
+  if ((rc = p->alloc(&p->T1, (size_t)p->tb * n * naux))) return bail(rc);
 
   const hipStream_t s = p->stream;
   auto hip_bail = [&](hipError_t e, const char* what) {
@@ -428,6 +475,8 @@ int thcsox_plan(thcsox_plan_t* out, int n, int naux, int ntau, double beta,
   if ((e = hipMemsetAsync(p->U, 0, np * es * (size_t)p->u_plane, s))) return hip_bail(e, "zero U");
   if (p->A && (e = hipMemsetAsync(p->A, 0, np * es * (size_t)p->a_plane, s)))
     return hip_bail(e, "zero A");
+  if ((e = hipMemsetAsync(p->symflag, 0, sizeof(int) * (size_t)ntau, s)))
+    return hip_bail(e, "zero flags");
   if (p->A32 && (e = hipMemsetAsync(p->A32, 0, sizeof(float) * (size_t)p->a_plane, s)))
     return hip_bail(e, "zero A32");
   if ((rc = build_u(p, V_dev))) return bail(rc);
@@ -451,9 +500,14 @@ int thcsox_sigma_sox(thcsox_plan_t p, const double* G_dev, double* Sigma_dev,
   if (s0 < g0 + gbytes && g0 < s0 + gbytes) return fail(THCSOX_EINVAL, "Sigma aliases G");
   const hipStream_t s = p->stream;
   const int64_t nn = (int64_t)p->n * p->n;
-  HIP_TRY(fill_u64(p->amax + 5, p->m, 0ull, s));
-  HIP_TRY(absmax64(G_dev, nn, nn, p->m, p->amax + 5, s));
-  for (int k = k_begin; k < k_end; ++k) TRY(sigma_one(p, G_dev, Sigma_dev, Sigma_thc_dev, k));
+  HIP_TRY(fill_u64(p->am_g(), p->m, 0ull, s));
+  HIP_TRY(absmax64(G_dev, nn, nn, p->m, p->am_g(), s));
+  if (p->sym_mode == THCSOX_SYM_AUTO) {
+    HIP_TRY(asym64(G_dev, p->n, p->m, p->am_asym(), s));
+    HIP_TRY(sym_flags(p->am_asym(), p->am_g(), p->m, SYM_RTOL, p->symflag, s));
+  }
+  for (int k = k_begin; k < k_end; k += p->tb)
+    TRY(sigma_batch(p, G_dev, Sigma_dev, Sigma_thc_dev, k, std::min(k_end, k + p->tb)));
   return 0;
 }
 
@@ -466,8 +520,9 @@ int thcsox_backproject(thcsox_plan_t p, const double* Sigma_thc_dev, double* Sig
   TRY(check_dev(Sigma_thc_dev, "Sigma_thc_dev"));
   TRY(check_dev(Sigma_dev, "Sigma_dev"));
   const int64_t nn = (int64_t)p->n * p->n, aa = (int64_t)p->naux * p->naux;
-  for (int k = k_begin; k < k_end; ++k)
-    TRY(backproject_one(p, Sigma_thc_dev + k * aa, Sigma_dev + k * nn));
+  for (int k = k_begin; k < k_end; k += p->tb)
+    TRY(backproject_batch(p, Sigma_thc_dev + k * aa, aa, Sigma_dev + k * nn,
+                          std::min(k_end, k + p->tb) - k));
   return 0;
 }
 
@@ -499,12 +554,34 @@ int thcsox_plan_info(thcsox_plan_t p, thcsox_plan_info_t* info) {
   if (p == nullptr || info == nullptr) return fail(THCSOX_EINVAL, "NULL argument");
   const double n = p->n, na = p->naux;
   info->n = p->n; info->naux = p->naux; info->ntau = p->m; info->precision = p->mode;
-  info->tau_batch = 1;
+  info->tau_batch = p->tb;
   info->bytes = p->bytes;
   info->mac_per_tau = 2 * na * na * n * n + na * n * n * n + 2 * na * na * n + 3 * na * n * n;
   info->fused_mac_per_tau = 2 * na * na * n * n;
   info->fused_bytes_per_tau =
       (double)p->np * p->esize * (2 * na * n * n + 2 * na * n);
+  return 0;
+}
+
+int thcsox_set_symmetry(thcsox_plan_t p, int mode) {
+  clear_error();
+  if (p == nullptr) return fail(THCSOX_EINVAL, "plan is NULL");
+  if (mode != THCSOX_SYM_AUTO && mode != THCSOX_SYM_OFF)
+    return fail(THCSOX_EINVAL, "unknown symmetry mode " + std::to_string(mode));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  p->sym_mode = mode;
+  return 0;
+}
+
+int thcsox_symmetric_flags(thcsox_plan_t p, int* flags_host) {
+  clear_error();
+  if (p == nullptr || flags_host == nullptr) return fail(THCSOX_EINVAL, "NULL argument");
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  if (p->sym_mode != THCSOX_SYM_AUTO) {
+    for (int k = 0; k < p->m; ++k) flags_host[k] = 0;
+    return 0;
+  }
+  HIP_TRY(hipMemcpy(flags_host, p->symflag, sizeof(int) * p->m, hipMemcpyDeviceToHost));
   return 0;
 }
 

@@ -34,7 +34,9 @@ EXPORTS = ("thcsox_plan", "thcsox_sigma_sox", "thcsox_energy", "thcsox_destroy",
            "thcsox_dyson_onebody", "thcsox_dyson_destroy", "thcsox_mlp_create",
            "thcsox_mlp_forward", "thcsox_mlp_gradients", "thcsox_mlp_train_step",
            "thcsox_mlp_params", "thcsox_mlp_destroy", "thcsox_pair_scale",
-           "thcsox_pair_gather", "thcsox_pair_scatter")
+           "thcsox_pair_gather", "thcsox_pair_scatter", "thcsox_set_symmetry",
+           "thcsox_symmetric_flags")
+SYMMETRY = {"auto": 0, "off": 1}
 STAGES = ("project", "a_stage", "fused", "back")
 
 
@@ -82,6 +84,10 @@ def lib() -> ctypes.CDLL:
         L.thcsox_stage_times.restype = i
         L.thcsox_backproject.argtypes = [vp, vp, vp, i, i]
         L.thcsox_backproject.restype = i
+        L.thcsox_set_symmetry.argtypes = [vp, i]
+        L.thcsox_set_symmetry.restype = i
+        L.thcsox_symmetric_flags.argtypes = [vp, vp]
+        L.thcsox_symmetric_flags.restype = i
         L.thcsox_dyson_plan.argtypes = [ctypes.POINTER(vp), i, i, i, d, d, vp, vp, vp]
         L.thcsox_dyson_plan.restype = i
         L.thcsox_dyson_step.argtypes = [vp, vp, vp, vp]
@@ -170,6 +176,16 @@ def thcsox_stage_times(plan) -> dict:
 
 def thcsox_backproject(plan, Sigma_thc_dev: int, Sigma_dev: int, k_begin: int, k_end: int):
     _check(lib().thcsox_backproject(plan, Sigma_thc_dev, Sigma_dev, k_begin, k_end))
+
+
+def thcsox_set_symmetry(plan, mode: int) -> None:
+    _check(lib().thcsox_set_symmetry(plan, mode))
+
+
+def thcsox_symmetric_flags(plan, ntau: int) -> np.ndarray:
+    flags = np.zeros(ntau, dtype=np.int32)
+    _check(lib().thcsox_symmetric_flags(plan, flags.ctypes.data_as(ctypes.c_void_p)))
+    return flags
 
 
 def thcsox_dyson_plan(n: int, ntau: int, n_matsubara: int, beta: float, mu: float,
@@ -355,6 +371,14 @@ class Plan:
 
     def info(self) -> dict:
         return thcsox_plan_info(self.handle)
+
+    def set_symmetry(self, mode="auto") -> None:
+        """'auto': use D's symmetry where G is symmetric; 'off': never."""
+        thcsox_set_symmetry(self.handle, SYMMETRY[mode] if isinstance(mode, str) else mode)
+
+    def symmetric_flags(self) -> np.ndarray:
+        """Per tau point: 1 where the last sigma call took the symmetric path."""
+        return thcsox_symmetric_flags(self.handle, self.ntau)
 
     def profile(self, enable: bool = True) -> None:
         thcsox_profile(self.handle, enable)

@@ -1,0 +1,97 @@
+"""The symmetric-D path: when G(tau) and G(beta - tau) are symmetric, D_PR = D_RP
+(U_Pqs = U_Psq by construction), so only the tiles of D touching the upper
+triangle are formed and the rest is mirrored.  Checked against the oracle and
+against the same plan with the path switched off; tau points whose inputs are
+not symmetric must take the full path.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import energy as oenergy
+from oracle import sox as osox
+from paper_2404_17744_amd import synth, thcsox
+
+pytestmark = pytest.mark.gpu
+TOL = {"fp64": 1e-10, "fp32": 2e-6, "bf16x3": 2e-6, "fp16x2": 2e-6}
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def _sigma(dev, s, tau, w, beta, G, precision, mode):
+    plan = thcsox.Plan(torch.from_numpy(s.X).to(dev), torch.from_numpy(s.V).to(dev), tau, w,
+                       beta, precision=precision)
+    plan.set_symmetry(mode)
+    Gd = torch.from_numpy(G).to(dev)
+    S, St = plan.sigma(Gd, thc=True)
+    E = plan.energy(Gd, S)
+    flags = plan.symmetric_flags()
+    plan.close()
+    return S.cpu().numpy(), St.cpu().numpy(), E, flags
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3", "fp16x2"])
+def test_symmetric_path_matches_full_path(dev, precision):
+    """n=90, naux=400 (several tiles per side and ragged edges), 6 tau points."""
+    s = synth.make_system(90, 400, seed=11)
+    tau, w = synth.cheb_tau_grid(6, 100.0)
+    G = synth.g0_tau(s, tau, 100.0)
+    print(f"case n90 naux400 ntau6 seed 11 {precision} symmetric vs full", flush=True)
+    ref = osox.sigma_all_tau(osox.sigma_thc_paper, G, s.X, s.V)
+    S_sym, St_sym, E_sym, f_sym = _sigma(dev, s, tau, w, 100.0, G, precision, "auto")
+    S_full, St_full, E_full, f_full = _sigma(dev, s, tau, w, 100.0, G, precision, "off")
+    assert f_sym.tolist() == [1] * 6
+    assert f_full.tolist() == [0] * 6
+    assert _rel(S_sym, ref) <= TOL[precision]
+    assert _rel(S_full, ref) <= TOL[precision]
+    # the mirrored THC self-energy is exactly symmetric
+    assert np.array_equal(St_sym, np.transpose(St_sym, (0, 2, 1)))
+    assert _rel(St_sym, St_full) <= (1e-12 if precision == "fp64" else 1e-5)
+    E_ref = oenergy.energy_tau(G, ref, w)
+    assert abs(E_sym - E_ref) <= (1e-8 if precision == "fp64" else 1e-6)
+
+
+def test_mixed_symmetric_and_general_tau_points(dev):
+    """Only the pairs (k, m-1-k) with both inputs symmetric take the symmetric path."""
+    s = synth.make_system(40, 160, seed=12)
+    tau, w = synth.cheb_tau_grid(8, 100.0)
+    G = synth.g0_tau(s, tau, 100.0)
+    G[2] += 0.05 * synth.random_general_g(40, 1, seed=13)[0]   # breaks k = 2 and k = 5
+    print("case n40 naux160 ntau8 seed 12 fp64 partly symmetric", flush=True)
+    ref = osox.sigma_all_tau(osox.sigma_thc_paper, G, s.X, s.V)
+    S, _, _, flags = _sigma(dev, s, tau, w, 100.0, G, "fp64", "auto")
+    assert flags.tolist() == [1, 1, 0, 1, 1, 0, 1, 1]
+    assert _rel(S, ref) <= 1e-10
+
+
+def test_tiny_asymmetry_below_threshold(dev):
+    """An asymmetry of 1e-14 relative keeps the symmetric path and changes
+    Sigma by about that much; 1e-9 relative switches it off."""
+    s = synth.make_system(24, 96, seed=14)
+    tau, w = synth.cheb_tau_grid(4, 100.0)
+    G = synth.g0_tau(s, tau, 100.0)
+    noise = synth.random_general_g(24, 4, seed=15)
+    amax = np.abs(G).max(axis=(1, 2), keepdims=True)
+    print("case n24 naux96 ntau4 fp64 asymmetry thresholds", flush=True)
+    G1 = G + 1e-15 * amax * noise
+    ref1 = osox.sigma_all_tau(osox.sigma_thc_paper, G1, s.X, s.V)
+    S1, _, _, f1 = _sigma(dev, s, tau, w, 100.0, G1, "fp64", "auto")
+    assert f1.tolist() == [1, 1, 1, 1]
+    assert _rel(S1, ref1) <= 1e-10
+    G2 = G + 1e-9 * amax * noise
+    ref2 = osox.sigma_all_tau(osox.sigma_thc_paper, G2, s.X, s.V)
+    S2, _, _, f2 = _sigma(dev, s, tau, w, 100.0, G2, "fp64", "auto")
+    assert f2.tolist() == [0, 0, 0, 0]
+    assert _rel(S2, ref2) <= 1e-10
+
+
+def test_symmetry_mode_errors(dev):
+    s = synth.make_system(8, 32, seed=0)
+    tau, w = synth.cheb_tau_grid(4, 100.0)
+    plan = thcsox.Plan(torch.from_numpy(s.X).to(dev), torch.from_numpy(s.V).to(dev), tau, w,
+                       100.0)
+    with pytest.raises(thcsox.ThcsoxError):
+        plan.set_symmetry(7)
+    plan.close()
