@@ -13,6 +13,7 @@
 // C ever reaches memory.  Operands are staged through LDS one (v, 32-wide k chunk) stage at a
 // time; the next stage's global loads are issued before the current stage's
 // MFMAs (register prefetch), so loads overlap the matrix work.
+#include <algorithm>
 #include <type_traits>
 
 #include "kernels.hpp"
@@ -273,7 +274,13 @@ void fused_tile(int mode, int* rows, int* cols) {
     case MODE_F64: tile_of<MODE_F64>(rows, cols); break;
     case MODE_F32: tile_of<MODE_F32>(rows, cols); break;
     case MODE_BF16X3: tile_of<MODE_BF16X3>(rows, cols); break;
-    default: tile_of<MODE_F16X2>(rows, cols); break;
+    default:
+#ifdef THCSOX_F16_V1
+      tile_of<MODE_F16X2>(rows, cols);
+#else
+      fused_f16_tile(rows, cols);
+#endif
+      break;
   }
 }
 
@@ -283,6 +290,8 @@ hipError_t sox_fused(int mode, const FusedArgs& f, hipStream_t s) {
   int TR, TP;
   fused_tile(mode, &TR, &TP);
   if (f.vsplit % NXCD != 0 || (int64_t)f.vsplit * f.vchunk < f.n) return hipErrorInvalidValue;
+  // buffer offsets inside one tile's rows of U are 32-bit
+  if ((int64_t)std::max(TR, TP) * f.n * f.ldk * 8 > 0x7fffffffLL) return hipErrorInvalidValue;
   dim3 grid(cdiv(f.naux, TP) * cdiv(f.naux, TR) * f.vsplit);
   switch (mode) {
     case MODE_F64: fused_kernel<MODE_F64, false><<<grid, NT, 0, s>>>(f); break;
@@ -292,6 +301,9 @@ hipError_t sox_fused(int mode, const FusedArgs& f, hipStream_t s) {
       else fused_kernel<MODE_BF16X3, false><<<grid, NT, 0, s>>>(f);
       break;
     case MODE_F16X2:
+#ifndef THCSOX_F16_V1
+      if (f.a_f32) return sox_fused_f16(f, s);
+#endif
       if (f.a_f32) fused_kernel<MODE_F16X2, true><<<grid, NT, 0, s>>>(f);
       else fused_kernel<MODE_F16X2, false><<<grid, NT, 0, s>>>(f);
       break;

@@ -135,18 +135,48 @@ __global__ void fill_u64_kernel(unsigned long long* p, int64_t n, unsigned long 
     p[i] = v;
 }
 
+// One workgroup per 64 x 64 tile of Sthc: sum the partial D tiles over z and
+// scale.  With the symmetric path, tiles below the diagonal are the transposes
+// of tiles above it (read row-wise and transposed through LDS), and inside a
+// diagonal tile the entries with R > P come from the mirrored position.
+constexpr int DT = 64;
 __global__ __launch_bounds__(NT) void dreduce_kernel(DReduceArgs a) {
+  __shared__ double t[DT][DT + 1];
   const double f = pow2_scale(a.amax_gt) * pow2_scale(a.amax_gx) * pow2_scale(a.amax_gb) *
                    pow2_scale(a.amax_a) * pow2_scale(a.amax_u) * pow2_scale(a.amax_u);
   const double inv = 1.0 / f;   // exact: a power of two
   const int64_t nn = (int64_t)a.naux * a.naux;
   const bool sym = a.sym != nullptr && *a.sym != 0;
-  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < nn; e += (int64_t)gridDim.x * NT) {
-    const int64_t R = e / a.naux, P = e % a.naux;
-    const int64_t src = (sym && R > P) ? P * a.naux + R : e;
-    double s = 0.0;
-    for (int z = 0; z < a.vsplit; ++z) s += a.Dpart[z * nn + src];
-    a.Sthc[R * a.s_ld + P] = -inv * s;
+  const int nt = (a.naux + DT - 1) / DT;
+  const int rb = blockIdx.x / nt, pb = blockIdx.x % nt;
+  const bool mirror = sym && rb > pb;          // read the tile (pb, rb) and transpose
+  const int sr = mirror ? pb : rb, sc = mirror ? rb : pb;   // source tile rows, columns
+  const int col = threadIdx.x & (DT - 1), row0 = threadIdx.x / DT;   // 4 rows per pass
+  double acc[DT / 4];
+#pragma unroll
+  for (int i = 0; i < DT / 4; ++i) acc[i] = 0.0;
+  const int gc = sc * DT + col;
+  for (int z = 0; z < a.vsplit; ++z) {
+    const double* Dz = a.Dpart + z * nn;
+#pragma unroll
+    for (int i = 0; i < DT / 4; ++i) {
+      const int gr = sr * DT + row0 + 4 * i;
+      if (gr < a.naux && gc < a.naux) acc[i] += Dz[(int64_t)gr * a.naux + gc];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < DT / 4; ++i) t[row0 + 4 * i][col] = acc[i];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < DT / 4; ++i) {
+    const int lr = row0 + 4 * i, lc = col;      // output element (R, P) of tile (rb, pb)
+    const int R = rb * DT + lr, P = pb * DT + lc;
+    if (R >= a.naux || P >= a.naux) continue;
+    double v;
+    if (mirror) v = t[lc][lr];
+    else if (sym && rb == pb && R > P) v = t[lc][lr];
+    else v = t[lr][lc];
+    a.Sthc[(int64_t)R * a.s_ld + P] = -inv * v;
   }
 }
 
@@ -257,10 +287,9 @@ hipError_t fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipS
 }
 
 hipError_t dreduce(const DReduceArgs& a, hipStream_t s) {
-  const int64_t nn = (int64_t)a.naux * a.naux;
-  unsigned b = cdiv(nn, NT);
-  if (b > 8192) b = 8192;
-  dreduce_kernel<<<b, NT, 0, s>>>(a);
+  if (a.naux <= 0) return hipSuccess;
+  const unsigned nt = cdiv(a.naux, DT);
+  dreduce_kernel<<<nt * nt, NT, 0, s>>>(a);
   return hipGetLastError();
 }
 

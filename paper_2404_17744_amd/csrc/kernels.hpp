@@ -55,6 +55,9 @@ struct FusedArgs {
 };
 hipError_t sox_fused(int mode, const FusedArgs& f, hipStream_t s);
 void fused_tile(int mode, int* rows, int* cols);   // D tile one workgroup owns (R x P)
+// the fp16x2 kernel (FP32 A split on the fly), used by sox_fused for that mode
+hipError_t sox_fused_f16(const FusedArgs& f, hipStream_t s);
+void fused_f16_tile(int* rows, int* cols);
 int fused_xcds();   // vsplit must be a multiple of this (one v range per XCD in turn)
 
 // Split rows of an FP64 source into the planes of a mode, scaled by the power of
