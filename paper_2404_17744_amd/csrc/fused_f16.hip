@@ -26,7 +26,9 @@
 //            loads of stage t+2 -> LDS buffer cur and registers,
 //            matrix cores: last 32 MFMAs of C.
 // The loop body has no branches: past the last stage the loads repeat the last
-// stage and the extra panels written to LDS are never used.
+// stage and the extra panels written to LDS are never used.  The operand row
+// length (ldk) is a multiple of 64, so each v takes an even number of stages
+// and the loop runs two stages per trip with the buffers fixed at compile time.
 #include "kernels.hpp"
 #include "mfma.hpp"
 #include "panel.hpp"
@@ -46,9 +48,12 @@ constexpr int BAND16 = 4;
 
 typedef _Float16 h4 __attribute__((ext_vector_type(4)));
 
-// LDS: [buffer][panel G, U, A, X][plane][row * 32 + physical chunk * 8 + e]
-struct Smem {
-  _Float16 s[2][4][2][PANEL];
+// One LDS stage buffer: [panel G, U, A, X][plane][row * 32 + physical chunk * 8 + e].
+// The two buffers are separate objects and every access names one of them at
+// compile time, so the compiler can tell that reads of one buffer do not wait
+// for memory-to-LDS loads still landing in the other.
+struct Buf {
+  _Float16 s[4][2][PANEL];
 };
 
 __device__ __forceinline__ void vm_lds_barrier() {
@@ -59,7 +64,8 @@ __device__ __forceinline__ void vm_lds_barrier() {
 
 __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(NW / 4, NW / 4)))
 void fused_f16_kernel(FusedArgs f) {
-  __shared__ __attribute__((aligned(16))) Smem sm;
+  __shared__ __attribute__((aligned(16))) Buf sb0;
+  __shared__ __attribute__((aligned(16))) Buf sb1;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave / WP_, wc = wave % WP_;
 
@@ -114,7 +120,7 @@ void fused_f16_kernel(FusedArgs f) {
     du[j] = row < rows_r ? (uint32_t)((row * u_row + 8 * c) * 2) : OOB;
     dx[j] = row < rows_p ? (uint32_t)((row * ldk + 8 * c) * 2) : OOB;
   }
-  auto dma = [&](int buf, int v, int k0) {
+  auto dma = [&](Buf& b, int v, int k0) {
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
       const __amdgpu_buffer_rsrc_t rU =
@@ -122,9 +128,9 @@ void fused_f16_kernel(FusedArgs f) {
 #pragma unroll
       for (int j = 0; j < SL; ++j) {
         const int slab = (wave + NW * j) * 16 * KC;
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(rG[p], &sm.s[buf][0][p][slab], 16, dg[j], k0 * 2, 0, 0);
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(rU, &sm.s[buf][1][p][slab], 16, du[j], k0 * 2, 0, 0);
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(rX[p], &sm.s[buf][3][p][slab], 16, dx[j], k0 * 2, 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rG[p], &b.s[0][p][slab], 16, dg[j], k0 * 2, 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rU, &b.s[1][p][slab], 16, du[j], k0 * 2, 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rX[p], &b.s[3][p][slab], 16, dx[j], k0 * 2, 0, 0);
       }
     }
   };
@@ -146,7 +152,7 @@ void fused_f16_kernel(FusedArgs f) {
     for (int i = 0; i < AU; ++i)
       ra[i] = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(rA, offa[i], k0 * 4, 0));
   };
-  auto put_a = [&](int buf) {
+  auto put_a = [&](Buf& b) {
 #pragma unroll
     for (int i = 0; i < AU; ++i) {
       h4 hi, lo;
@@ -157,8 +163,8 @@ void fused_f16_kernel(FusedArgs f) {
         hi[e] = h;
         lo[e] = (_Float16)(x - (float)h);
       }
-      *reinterpret_cast<h4*>(&sm.s[buf][2][0][lda_[i]]) = hi;
-      *reinterpret_cast<h4*>(&sm.s[buf][2][1][lda_[i]]) = lo;
+      *reinterpret_cast<h4*>(&b.s[2][0][lda_[i]]) = hi;
+      *reinterpret_cast<h4*>(&b.s[2][1][lda_[i]]) = lo;
     }
   };
 
@@ -176,15 +182,15 @@ void fused_f16_kernel(FusedArgs f) {
   }
   struct Frags { f16x8 r[2][WBR], c[2][WBP]; };   // [plane][tile]
   Frags fB, fC;
-  auto read_frags = [&](Frags& fr, int buf, int pr, int pc) {
+  auto read_frags = [&](Frags& fr, const Buf& b, int pr, int pc) {
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
 #pragma unroll
       for (int t = 0; t < WBR; ++t)
-        fr.r[p][t] = *reinterpret_cast<const f16x8*>(&sm.s[buf][pr][p][fr_off[t]]);
+        fr.r[p][t] = *reinterpret_cast<const f16x8*>(&b.s[pr][p][fr_off[t]]);
 #pragma unroll
       for (int t = 0; t < WBP; ++t)
-        fr.c[p][t] = *reinterpret_cast<const f16x8*>(&sm.s[buf][pc][p][fc_off[t]]);
+        fr.c[p][t] = *reinterpret_cast<const f16x8*>(&b.s[pc][p][fc_off[t]]);
     }
   };
 
@@ -240,17 +246,35 @@ void fused_f16_kernel(FusedArgs f) {
   };
 
   if (nstage > 0) {
-    dma(0, lv, lk * KC);
+    dma(sb0, lv, lk * KC);
     fetch_a(lv, lk * KC);
     advance();
-    put_a(0);
-    dma(1, lv, lk * KC);
+    put_a(sb0);
+    dma(sb1, lv, lk * KC);
     fetch_a(lv, lk * KC);
     advance();
     vm_lds_barrier();
-    read_frags(fB, 0, 0, 2);
+    read_frags(fB, sb0, 0, 2);
   }
-  int t = 0, nv = 0;
+  // one stage; `cur` holds stage t, `nxt` receives stage t+1 (already loading)
+  auto stage = [&](Buf& cur, Buf& nxt) {
+    // phase 1: C fragments of stage t; B product
+    read_frags(fC, cur, 1, 3);
+    mfma_range(accB, fB, 0, 2 * NQ / 3);
+    // phase 2: A of stage t+1 into the other buffer; C product starts
+    mfma_range(accB, fB, 2 * NQ / 3, NQ);
+    put_a(nxt);
+    mfma_range(accC, fC, 0, NQ / 3);
+    // stage t+1 complete in LDS (its memory-to-LDS loads were issued one phase 3 ago)
+    vm_lds_barrier();
+    // phase 3: B fragments of stage t+1; stage t+2 loads into this buffer
+    read_frags(fB, nxt, 0, 2);
+    dma(cur, lv, lk * KC);
+    fetch_a(lv, lk * KC);
+    advance();
+    mfma_range(accC, fC, NQ / 3, NQ);
+  };
+  int nv = 0;
   for (int v = v_lo; v < v_hi; ++v) {
 #pragma unroll
     for (int i = 0; i < WBR; ++i)
@@ -259,23 +283,10 @@ void fused_f16_kernel(FusedArgs f) {
         accB[i][j] = f4{0.f, 0.f, 0.f, 0.f};
         accC[i][j] = f4{0.f, 0.f, 0.f, 0.f};
       }
-    for (int ks = 0; ks < kst; ++ks, ++t) {
-      const int cur = t & 1;
-      // phase 1: C fragments of stage t; B product
-      read_frags(fC, cur, 1, 3);
-      mfma_range(accB, fB, 0, 2 * NQ / 3);
-      // phase 2: A of stage t+1 into the other buffer; C product starts
-      mfma_range(accB, fB, 2 * NQ / 3, NQ);
-      put_a(cur ^ 1);
-      mfma_range(accC, fC, 0, NQ / 3);
-      // stage t+1 complete in LDS (its memory-to-LDS loads were issued one phase 3 ago)
-      vm_lds_barrier();
-      // phase 3: B fragments of stage t+1; stage t+2 loads into this buffer
-      read_frags(fB, cur ^ 1, 0, 2);
-      dma(cur, lv, lk * KC);
-      fetch_a(lv, lk * KC);
-      advance();
-      mfma_range(accC, fC, NQ / 3, NQ);
+    // kst is even, so every v starts on buffer 0
+    for (int ks = 0; ks < kst; ks += 2) {
+      stage(sb0, sb1);
+      stage(sb1, sb0);
     }
 #pragma unroll
     for (int i = 0; i < WBR; ++i)
@@ -300,7 +311,7 @@ void fused_f16_tile(int* rows, int* cols) {
 
 hipError_t sox_fused_f16(const FusedArgs& f, hipStream_t s) {
   if (!f.a_f32 || f.vsplit % NXCD16 != 0 || (int64_t)f.vsplit * f.vchunk < f.n ||
-      f.ldk % KC != 0)
+      f.ldk % (2 * KC) != 0)
     return hipErrorInvalidValue;
   // buffer offsets inside one tile's rows of U (fp16) and A (FP32) are 32-bit
   if ((int64_t)TT * f.n * f.ldk * 2 > 0x7fffffffLL || (int64_t)TT * f.ldk * 4 > 0x7fffffffLL)

@@ -382,7 +382,9 @@ int thcsox_plan(thcsox_plan_t* out, int n, int naux, int ntau, double beta,
   if (!p) return fail(THCSOX_ENOMEM, "host allocation failed");
   auto bail = [&](int rc) { delete p; return rc; };
   p->n = n; p->naux = naux; p->m = ntau; p->beta = beta; p->mode = precision;
-  p->ldk = (n + 31) / 32 * 32;
+  // operand row length: n rounded up to the k step of the matrix-core stages
+  // (64 for fp16x2, whose fused kernel takes two 32-wide stages per trip)
+  p->ldk = precision == THCSOX_FP16X2 ? (n + 63) / 64 * 64 : (n + 31) / 32 * 32;
   p->np = n_planes(precision);
   p->esize = elem_size(precision);
   p->stream = static_cast<hipStream_t>(hip_stream);
