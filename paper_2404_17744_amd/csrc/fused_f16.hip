@@ -297,6 +297,8 @@ void fused_f16_kernel(FusedArgs f) {
     ++nv;
     if ((nv % FLUSH16 == 0) && v + 1 < v_hi) flush(nv == FLUSH16);
   }
+  // the last (repeated) memory-to-LDS loads land before the workgroup may end
+  __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
   flush(nv <= FLUSH16);   // also writes zeros for an empty v range
 }
 

@@ -35,6 +35,9 @@ struct GemmKArgs {
   unsigned long long* amax;
 };
 hipError_t gemm_kmajor(int mode, bool out_f64, const GemmKArgs& g, hipStream_t s);
+// The same product for fp16x2 planes with FP32 output (the A stage of that
+// mode); kpad must be a multiple of 64.
+hipError_t astage_f16(const GemmKArgs& g, hipStream_t s);
 
 // The fused B/C/D stage for one tau point (v split over grid.z):
 //   Dpart[z][R][P] = sum_{v in split z} (sum_q Gt[R][q] A[v][P][q]) (sum_w U[R][v][w] GXt[P][w])

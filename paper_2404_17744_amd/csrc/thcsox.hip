@@ -300,7 +300,7 @@ int sigma_batch(thcsox_plan_s* p, const double* G, double* Sigma, double* Sthc_o
     } else {
       // FP32 A; the fused kernel splits it into planes with the scale from max|A|
       ga.C = p->A32; ga.amax = p->am_a() + k;
-      HIP_TRY(gemm_kmajor(mode, false, ga, s));
+      HIP_TRY(mode == MODE_F16X2 ? astage_f16(ga, s) : gemm_kmajor(mode, false, ga, s));
     }
     HIP_TRY(p->mark(THCSOX_STAGE_A, false));
 

@@ -86,3 +86,17 @@ def test_null_handles_rejected(L):
     assert L.thcsox_destroy(None) == 0          # destroying nothing is a no-op
     assert L.thcsox_dyson_destroy(None) == 0
     assert L.thcsox_mlp_destroy(None) == 0
+
+
+def test_no_undefined_library_symbols(L):
+    """Every symbol of the library's own namespace is defined (a kernel whose
+    host stub was not emitted shows up here, before any GPU run)."""
+    import shutil
+    import subprocess
+    nm = shutil.which("nm")
+    if nm is None:
+        pytest.skip("nm not available")
+    out = subprocess.run([nm, "-D", "--undefined-only", thcsox.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    bad = [l for l in out.splitlines() if "thcsox" in l]
+    assert not bad, bad
