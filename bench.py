@@ -63,13 +63,13 @@ def fused_source_hash():
     """Hash of the sources that make up the fused kernel."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("fused.hip", "panel.hpp", "mfma.hpp", "kernels.hpp"):
+    for f in ("fused.hip", "fused_f16.hip", "panel.hpp", "mfma.hpp", "kernels.hpp"):
         with open(os.path.join(ROOT, "paper_2404_17744_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(precision, workload):
+def measured_traffic(precision, workload, symmetry):
     """HBM bytes per fused launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
     summary, or None when there is none or the kernel has changed since."""
     path = os.path.join(ROOT, "profiles", f"hbm_traffic_fused_{precision}_{workload}.md")
@@ -78,10 +78,12 @@ def measured_traffic(precision, workload):
     kv = {}
     with open(path) as f:
         for line in f:
-            if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "source_sha256"):
-                k, v = line.split(":", 1)
-                kv[k] = v.strip()
+            key = line.split(":")[0]
+            if ":" in line and key in ("traffic_bytes_per_launch", "source_sha256", "symmetry"):
+                kv[key] = line.split(":", 1)[1].strip()
     if kv.get("source_sha256") != fused_source_hash() or "traffic_bytes_per_launch" not in kv:
+        return None
+    if kv.get("symmetry", "auto") != symmetry:
         return None
     return float(kv["traffic_bytes_per_launch"])
 
@@ -119,7 +121,7 @@ def main():
     ap.add_argument("--workload", default="sox_n300_naux1800_ntau100")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--fp64-steps", type=int, default=1)
-    ap.add_argument("--cpu-taus", type=int, default=1)
+    ap.add_argument("--cpu-taus", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--symmetry", default="auto", choices=["auto", "off"])
     args = ap.parse_args()
@@ -208,8 +210,9 @@ def main():
                    "parallelism": "none (one GPU; tau points are independent)"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak,
-                     "traffic": measured_traffic(args.precision, args.workload),
-                     "kernel": f"fused_kernel<{args.precision}>",
+                     "traffic": measured_traffic(args.precision, args.workload, args.symmetry),
+                     "kernel": ("fused_f16_kernel" if args.precision == "fp16x2"
+                                else f"fused_kernel<{args.precision}>"),
                      "avg_launch_ms": fused_avg, "launches": fused_n,
                      "algorithmic_flop_per_launch": fused_flop,
                      "symmetric_tau_points": n_sym,
