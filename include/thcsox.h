@@ -99,8 +99,9 @@ int thcsox_plan(thcsox_plan_t* out, int n, int naux, int ntau, double beta,
  *                    k_begin..k_end-1 receive Sig_RP (as computed above; it is
  *                    not unique, X has rank <= n).
  * Symmetric inputs: when G(tau_k) and G(beta - tau_k) are both symmetric to
- * within 1e-12 of their largest element (checked on the device at every call,
- * see thcsox_set_symmetry), D_PR = D_RP holds (U_Pqs = U_Psq by construction),
+ * within 1e-12 (FP64 plans) or 1e-10 (the other precisions, whose own rounding
+ * is about 1e-8) of the largest element of G on the grid (checked on the
+ * device at every call, see thcsox_set_symmetry), D_PR = D_RP holds (U_Pqs = U_Psq by construction),
  * so only tiles of D touching the upper triangle are formed and the rest is
  * mirrored; Sigma changes by at most about that relative asymmetry.
  * 0 <= k_begin < k_end <= ntau.  Sigma must not alias G.  Asynchronous. */

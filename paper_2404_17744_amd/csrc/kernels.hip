@@ -199,11 +199,11 @@ __global__ void sym_flags_kernel(const unsigned long long* asym, const unsigned 
                                  int m, double rtol, int* flag) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= m) return;
-  auto ok = [&](int j) {
-    const double a = __longlong_as_double((long long)asym[j]);
-    const double g = __longlong_as_double((long long)amax[j]);
-    return a <= rtol * g;
-  };
+  // the reference magnitude is the largest |G| on the whole grid: Sigma's error
+  // is measured against its largest element, which comes from the largest G
+  double gmax = 0.0;
+  for (int j = 0; j < m; ++j) gmax = fmax(gmax, __longlong_as_double((long long)amax[j]));
+  auto ok = [&](int j) { return __longlong_as_double((long long)asym[j]) <= rtol * gmax; };
   flag[k] = (ok(k) && ok(m - 1 - k)) ? 1 : 0;
 }
 

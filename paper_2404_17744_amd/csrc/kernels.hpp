@@ -97,8 +97,8 @@ hipError_t dreduce(const DReduceArgs& a, hipStream_t s);
 
 // asym[k] = max |G[k] - G[k]^T| (as the bits of a non-negative double), k < m.
 hipError_t asym64(const double* G, int n, int m, unsigned long long* asym, hipStream_t s);
-// flag[k] = 1 if both G[k] and G[m-1-k] are symmetric to within rtol of their
-// largest element (asym[k] <= rtol * amax[k]), else 0.
+// flag[k] = 1 if both G[k] and G[m-1-k] are symmetric to within rtol of the
+// largest element of G on the whole grid (asym[k] <= rtol * max_j amax[j]), else 0.
 hipError_t sym_flags(const unsigned long long* asym, const unsigned long long* amax, int m,
                      double rtol, int* flag, hipStream_t s);
 

@@ -32,9 +32,14 @@ namespace {
 
 int fail(int code, const std::string& msg) { return set_error(code, msg); }
 
-// G(tau) counts as symmetric when max |G - G^T| <= SYM_RTOL max |G|; the
-// symmetric-D path then changes Sigma by at most about that relative amount.
-constexpr double SYM_RTOL = 1e-12;
+// G(tau) counts as symmetric when max |G(tau) - G(tau)^T| <= rtol max |G| (the
+// largest element on the whole grid); the symmetric-D path then changes Sigma
+// by at most about that amount relative to its largest element:
+// 1e-12 for FP64 plans, 1e-10 for the reduced-precision ones (whose own
+// rounding error is about 1e-8).  A Green's function from a Dyson step carries
+// an asymmetry of that order from the rounding of the inversion.
+constexpr double SYM_RTOL_F64 = 1e-12;
+constexpr double SYM_RTOL_MIXED = 1e-10;
 
 #define HIP_TRY(expr)                                                                  \
   do {                                                                                 \
@@ -506,7 +511,8 @@ int thcsox_sigma_sox(thcsox_plan_t p, const double* G_dev, double* Sigma_dev,
   HIP_TRY(absmax64(G_dev, nn, nn, p->m, p->am_g(), s));
   if (p->sym_mode == THCSOX_SYM_AUTO) {
     HIP_TRY(asym64(G_dev, p->n, p->m, p->am_asym(), s));
-    HIP_TRY(sym_flags(p->am_asym(), p->am_g(), p->m, SYM_RTOL, p->symflag, s));
+    HIP_TRY(sym_flags(p->am_asym(), p->am_g(), p->m,
+                      p->mode == MODE_F64 ? SYM_RTOL_F64 : SYM_RTOL_MIXED, p->symflag, s));
   }
   for (int k = k_begin; k < k_end; k += p->tb)
     TRY(sigma_batch(p, G_dev, Sigma_dev, Sigma_thc_dev, k, std::min(k_end, k + p->tb)));
