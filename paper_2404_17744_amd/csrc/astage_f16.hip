@@ -8,13 +8,18 @@
 // The result is written in FP32, and max |C| is max-reduced for the scaling
 // that the fused stage applies when it splits A.
 //
-// A workgroup of eight waves (two per SIMD) owns 128 rows of U and TN = 64 WBN
-// columns (v), WBN <= 5; wave (wm, wn) holds 64 x 16 WBN of it.  Each 32-wide
+// A workgroup of eight waves (two per SIMD) works on 128 rows of U at a time and
+// TN = 64 WBN columns (v), WBN <= 5; wave (wm, wn) holds 64 x 16 WBN of it.  The
+// grid is persistent (about one workgroup per compute unit): a workgroup walks
+// its row tiles with one continuous stream of stages, so the loads of the next
+// tile overlap the last stages and the stores of the current one.  Each 32-wide
 // k stage of both operands (U: 16 KiB, G: TN x 128 B) is loaded from memory
 // straight into one of two LDS buffers, one stage ahead of the matrix cores;
 // the fragments of the next stage are read while the second half of the
 // current stage's MFMAs run.  The MFMA takes the G fragment as its row operand, so a lane's output
 // elements run along i = (P, q): stores of 16 lanes cover 64 contiguous bytes.
+#include <algorithm>
+
 #include "kernels.hpp"
 #include "mfma.hpp"
 #include "panel.hpp"
@@ -51,29 +56,27 @@ __device__ __forceinline__ void astage_body(const GemmKArgs& g, ABuf& b0, ABuf& 
   static_assert(TN <= AMAXN, "at most 320 columns per workgroup");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 2, wn = wave & 3;
+  // persistent: this workgroup owns column block jb_ and the row tiles
+  // tile0, tile0 + gridDim.y... (grid.x = column blocks, grid.y = row workers)
   const int nib = (g.M + AM - 1) / AM;
-  const int i0 = (blockIdx.x % nib) * AM, j0 = (blockIdx.x / nib) * TN;
-  const int rows_i = min(AM, g.M - i0), rows_j = min(TN, g.N - j0);
+  const int j0 = blockIdx.x * TN;
+  const int first = blockIdx.y, stride = gridDim.y;
+  const int ntile = first < nib ? (nib - 1 - first) / stride + 1 : 0;
+  if (ntile == 0) return;
+  const int rows_j = min(TN, g.N - j0);
   const int kst = g.kpad / AKC;
 
-  const _Float16* A = static_cast<const _Float16*>(g.A) + (int64_t)i0 * g.lda;
   const _Float16* B = static_cast<const _Float16*>(g.B) + (int64_t)j0 * g.ldb;
-  __amdgpu_buffer_rsrc_t rA[2], rB[2];
+  __amdgpu_buffer_rsrc_t rB[2];
 #pragma unroll
-  for (int p = 0; p < 2; ++p) {
-    rA[p] = make_rsrc(A + p * g.a_plane, (int64_t)AM * g.lda * 2);
-    rB[p] = make_rsrc(B + p * g.b_plane, (int64_t)TN * g.ldb * 2);
-  }
+  for (int p = 0; p < 2; ++p) rB[p] = make_rsrc(B + p * g.b_plane, (int64_t)TN * g.ldb * 2);
   // memory-to-LDS slabs of 16 rows: U has 8 per plane (wave w moves slab w of
   // both planes), G has TN / 16 per plane, 8 WBN in all (wave w moves the
   // slabs w + 8 j, j < WBN, counted across the two planes)
   constexpr int GSP = TN / 16;               // G slabs per plane
-  uint32_t du, dg[WBN];
-  {
-    const int row = wave * 16 + (lane >> 2);
-    const int c = lds_chunk(row, lane & 3);
-    du = row < rows_i ? (uint32_t)((row * g.lda + 8 * c) * 2) : OOB;
-  }
+  const int urow = wave * 16 + (lane >> 2);
+  const uint32_t du_in = (uint32_t)((urow * g.lda + 8 * lds_chunk(urow, lane & 3)) * 2);
+  uint32_t dg[WBN];
 #pragma unroll
   for (int j = 0; j < WBN; ++j) {
     const int slab = (wave + ANW * j) % GSP;
@@ -81,15 +84,21 @@ __device__ __forceinline__ void astage_body(const GemmKArgs& g, ABuf& b0, ABuf& 
     const int c = lds_chunk(row, lane & 3);
     dg[j] = row < rows_j ? (uint32_t)((row * g.ldb + 8 * c) * 2) : OOB;
   }
-  auto dma = [&](ABuf& bf, int k0) {
+  // stage (tile t of this workgroup, k chunk k) -> LDS buffer
+  auto dma = [&](ABuf& bf, int t, int k) {
+    const int i0 = (first + t * stride) * AM;
+    const _Float16* A = static_cast<const _Float16*>(g.A) + (int64_t)i0 * g.lda;
+    const uint32_t du = urow < g.M - i0 ? du_in : OOB;
 #pragma unroll
     for (int p = 0; p < 2; ++p)
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(rA[p], &bf.u[p][wave * 16 * AKC], 16, du, k0 * 2, 0, 0);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          make_rsrc(A + p * g.a_plane, (int64_t)AM * g.lda * 2), &bf.u[p][wave * 16 * AKC], 16, du,
+          k * AKC * 2, 0, 0);
 #pragma unroll
     for (int j = 0; j < WBN; ++j) {
       const int s = wave + ANW * j, p = s / GSP, slab = s % GSP;
       __builtin_amdgcn_raw_ptr_buffer_load_lds(p ? rB[1] : rB[0], &bf.g[p][slab * 16 * AKC], 16,
-                                               dg[j], k0 * 2, 0, 0);
+                                               dg[j], k * AKC * 2, 0, 0);
     }
   };
 
@@ -132,54 +141,65 @@ __device__ __forceinline__ void astage_body(const GemmKArgs& g, ABuf& b0, ABuf& 
     }
   };
 
-  Frags f0, f1;
-  // stage s lives in buffer s mod 2; kst is even
-  int lk = 0;
-  auto next_k = [&]() {
-    const int k = lk;
-    lk = min(lk + 1, kst - 1);
-    return k * AKC;
+  double lmax = 0.0;
+  float* C = static_cast<float*>(g.C);
+  const int jb = j0 + wn * 16 * WBN + 4 * (lane >> 4);
+  // write the finished tile t and clear the accumulators
+  auto store_tile = [&](int t) {
+    const int ib = (first + t * stride) * AM + wm * 64 + (lane & 15);
+#pragma unroll
+    for (int ti = 0; ti < 4; ++ti) {
+      const int i = ib + 16 * ti;
+      const bool ok = i < g.M;
+      const int64_t ibase = ((int64_t)i / g.ci_in) * g.ci_out + ((int64_t)i % g.ci_in);
+#pragma unroll
+      for (int tj = 0; tj < WBN; ++tj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int j = jb + 16 * tj + r;
+          if (ok && j < g.N) {
+            const float v = (float)(g.alpha * (double)acc[tj][ti][r]);
+            C[ibase + (int64_t)j * g.c_j] = v;
+            lmax = fmax(lmax, fabs((double)v));
+          }
+          acc[tj][ti][r] = 0.f;
+        }
+    }
   };
-  dma(b0, next_k());
-  dma(b1, next_k());
+
+  Frags f0, f1;
+  // one stream of stages over (tile, k), the stage in buffer (stage index) mod 2;
+  // kst is even, so every tile starts on buffer 0.  Past the end the loads repeat
+  // the last stage (never used).
+  int ft = 0, fk = 0;
+  auto fetch_next = [&](ABuf& bf) {
+    dma(bf, ft, fk);
+    const bool last = (ft == ntile - 1) && (fk == kst - 1);
+    const bool wrap = (fk == kst - 1);
+    fk = last ? fk : (wrap ? 0 : fk + 1);
+    ft = last ? ft : (wrap ? ft + 1 : ft);
+  };
+  fetch_next(b0);
+  fetch_next(b1);
   a_vm_lds_barrier();
   read_frags(f0, b0);
   auto stage = [&](ABuf& cur, ABuf& nxt, Frags& fc, Frags& fn) {
     mfma_range(fc, 0, NQ / 2);
     // the next stage has landed in nxt; every wave is done reading cur
     a_vm_lds_barrier();
-    dma(cur, next_k());
+    fetch_next(cur);
     read_frags(fn, nxt);
     mfma_range(fc, NQ / 2, NQ);
   };
-  for (int ks = 0; ks < kst; ks += 2) {
-    stage(b0, b1, f0, f1);
-    stage(b1, b0, f1, f0);
+  for (int t = 0; t < ntile; ++t) {
+    for (int ks = 0; ks < kst; ks += 2) {
+      stage(b0, b1, f0, f1);
+      stage(b1, b0, f1, f0);
+    }
+    store_tile(t);
   }
   // the last (repeated) memory-to-LDS loads land before the workgroup may end
   __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
-
-  double lmax = 0.0;
-  float* C = static_cast<float*>(g.C);
-  const int ib = i0 + wm * 64 + (lane & 15);
-  const int jb = j0 + wn * 16 * WBN + 4 * (lane >> 4);
-#pragma unroll
-  for (int ti = 0; ti < 4; ++ti) {
-    const int i = ib + 16 * ti;
-    if (i >= g.M) continue;
-    const int64_t ibase = ((int64_t)i / g.ci_in) * g.ci_out + ((int64_t)i % g.ci_in);
-#pragma unroll
-    for (int tj = 0; tj < WBN; ++tj)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int j = jb + 16 * tj + r;
-        if (j < g.N) {
-          const float v = (float)(g.alpha * (double)acc[tj][ti][r]);
-          C[ibase + (int64_t)j * g.c_j] = v;
-          lmax = fmax(lmax, fabs((double)v));
-        }
-      }
-  }
   if (g.amax != nullptr) {
     lmax = a_wave_max(lmax);
     if (lane == 0) atomicMax(g.amax, (unsigned long long)__double_as_longlong(lmax));
@@ -204,8 +224,13 @@ inline unsigned a_cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b
 
 template <int WBN>
 hipError_t a_launch(void (*kernel)(GemmKArgs), const GemmKArgs& g, hipStream_t s) {
-  const unsigned grid = a_cdiv(g.M, AM) * a_cdiv(g.N, 64 * WBN);
-  kernel<<<grid, ANT, 0, s>>>(g);
+  // persistent row workers: one per compute unit (the LDS holds one workgroup)
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess)
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const unsigned ncol = a_cdiv(g.N, 64 * WBN), nib = a_cdiv(g.M, AM);
+  const unsigned workers = std::max(1u, std::min(nib, (unsigned)std::max(1, cus) / ncol));
+  kernel<<<dim3(ncol, workers), ANT, 0, s>>>(g);
   return hipGetLastError();
 }
 
