@@ -169,13 +169,16 @@ int thcsox_plan_info(thcsox_plan_t p, thcsox_plan_info_t* info);
 typedef struct thcsox_dyson_s* thcsox_dyson_t;
 
 /* F_dev[n][n]: one-body operator (copied).  mu: chemical potential (fixed).
- * Needs 2 n_matsubara >= ntau.  Synchronises the stream. */
+ * Needs 2 n_matsubara >= ntau and n <= 9216 (the inversion keeps an n x b
+ * panel of each frequency's matrix in LDS, b = 8 for n <= 1152).  Device
+ * memory: about n_matsubara n^2 x 48 bytes.  Synchronises the stream. */
 int thcsox_dyson_plan(thcsox_dyson_t* out, int n, int ntau, int n_matsubara, double beta,
                       double mu, const double* tau_host, const double* F_dev, void* hip_stream);
 
 /* Sigma_dev[ntau][n][n] (read) -> G_dev[ntau][n][n] and gamma_dev[n][n] (written;
- * gamma_dev may be NULL).  Synchronises the stream; THCSOX_ENONFINITE if a
- * Dyson matrix is singular. */
+ * gamma_dev may be NULL).  The inversion is blocked in-place Gauss-Jordan
+ * elimination with partial pivoting.  Synchronises the stream;
+ * THCSOX_ENONFINITE if a pivot is zero or not finite (singular matrix). */
 int thcsox_dyson_step(thcsox_dyson_t d, const double* Sigma_dev, double* G_dev,
                       double* gamma_dev);
 

@@ -226,16 +226,16 @@ const Tables& tables_for(int m, int nw, double beta) {
 // Kernels
 // ----------------------------------------------------------------------------
 
-// Aug[w] = [ (i w + mu) 1 - F - Sigma(i w) | 1 ] as complex [n][2n].
-__global__ __launch_bounds__(NT) void build_aug(const double* __restrict__ S, const double* __restrict__ F,
-                                                double mu, double beta, int n, int nw,
-                                                double2* __restrict__ Aug) {
+// Am[w] = (i w + mu) 1 - F - Sigma(i w) as complex [n][n].
+__global__ __launch_bounds__(NT) void build_a(const double* __restrict__ S, const double* __restrict__ F,
+                                              double mu, double beta, int n, int nw,
+                                              double2* __restrict__ Am) {
   const int w = blockIdx.y;
   const double wn = (2.0 * w + 1.0) * M_PI / beta;
   const int64_t nn = (int64_t)n * n;
   const double* Sre = S + (int64_t)w * nn;
   const double* Sim = S + (int64_t)(nw + w) * nn;
-  double2* A = Aug + (int64_t)w * 2 * nn;
+  double2* A = Am + (int64_t)w * nn;
   for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < nn; e += (int64_t)gridDim.x * NT) {
     const int64_t i = e / n, j = e % n;
     double re = -F[e] - Sre[e], im = -Sim[e];
@@ -243,8 +243,7 @@ __global__ __launch_bounds__(NT) void build_aug(const double* __restrict__ S, co
       re += mu;
       im += wn;
     }
-    A[i * 2 * n + j] = make_double2(re, im);
-    A[i * 2 * n + n + j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+    A[e] = make_double2(re, im);
   }
 }
 
@@ -252,24 +251,46 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// In-place Gauss-Jordan elimination with partial pivoting on [A | 1]; the
-// right half ends as A^-1.  One workgroup per matrix; each column step is
-// separated by barriers (global memory of one matrix is only touched by its
-// own workgroup).  flag[0] is set to 1 if a pivot is exactly zero.
-__global__ __launch_bounds__(NT) void gauss_jordan(double2* __restrict__ Aug, int n,
-                                                   int* __restrict__ flag) {
-  extern __shared__ double2 fac[];   // column k factors, n entries
+// In-place Gauss-Jordan inversion with partial pivoting, blocked by panels of
+// GJ_B columns.  For the panel [k, k + bw):
+//   gje_panel: the n x bw panel sits in LDS; for each of its columns c the pivot
+//     is the largest |a_ic| over the rows i >= c not yet used as pivot rows, rows c
+//     and piv[c] are swapped in full (the panel in LDS, the other columns in
+//     memory), and the column is eliminated from the panel columns only: the
+//     pivot row is scaled by 1/p, every other row loses a_ic/p times it, and
+//     column c becomes the matching column of the inverse (1/p at the pivot,
+//     -a_ic/p elsewhere).  The panel ends as W, the panel's columns of the
+//     product of the panel's elimination matrices.
+//   gje_trail: every other column j gets the same eliminations at once,
+//     A[:, j] += (W - E) A[panel rows, j] with E the panel rows' unit columns.
+// After the last panel the matrix holds the inverse with its columns permuted by
+// the row interchanges; gje_perm and extract_inv undo them (last first).
+// One workgroup per frequency in gje_panel; flag[0] is set to 1 for a zero or
+// non-finite pivot.
+constexpr int GJ_B = 8;          // panel width
+constexpr int GJ_LDS = 9216;     // double2 panel elements in LDS (144 KiB): bw * n <= GJ_LDS
+constexpr int GJ_TCB = 64;       // columns per gje_trail workgroup
+constexpr int GJ_TRC = 32;       // rows per staged chunk of W
+
+__global__ __launch_bounds__(NT) void gje_panel(double2* __restrict__ Am, int n, int k, int bw,
+                                                int* __restrict__ piv, int* __restrict__ flag) {
+  __shared__ double2 P[GJ_LDS];  // column-major: P[t * n + i] = A[i][k + t]
   __shared__ double bval[NT];
   __shared__ int bidx[NT];
-  __shared__ double2 pinv;
-  const int tid = threadIdx.x;
-  const int ld = 2 * n;
-  double2* A = Aug + (int64_t)blockIdx.x * n * ld;
-  for (int k = 0; k < n; ++k) {
+  __shared__ double2 prow[GJ_B];
+  const int tid = threadIdx.x, w = blockIdx.x;
+  double2* A = Am + (int64_t)w * n * n;
+  for (int e = tid; e < n * bw; e += NT) {
+    const int i = e / bw, t = e % bw;
+    P[t * n + i] = A[(int64_t)i * n + k + t];
+  }
+  __syncthreads();
+  for (int t = 0; t < bw; ++t) {
+    const int c = k + t;
     double best = -1.0;
-    int bi = k;
-    for (int i = k + tid; i < n; i += NT) {
-      const double2 a = A[(int64_t)i * ld + k];
+    int bi = c;
+    for (int i = c + tid; i < n; i += NT) {
+      const double2 a = P[t * n + i];
       const double v = a.x * a.x + a.y * a.y;
       if (v > best) { best = v; bi = i; }
     }
@@ -287,49 +308,124 @@ __global__ __launch_bounds__(NT) void gauss_jordan(double2* __restrict__ Aug, in
       }
       __syncthreads();
     }
-    const int piv = bidx[0];
-    if (tid == 0 && !(bval[0] > 0.0)) atomicExch(flag, 1);
-    if (piv != k) {
-      for (int j = k + tid; j < ld; j += NT) {
-        const double2 t = A[(int64_t)k * ld + j];
-        A[(int64_t)k * ld + j] = A[(int64_t)piv * ld + j];
-        A[(int64_t)piv * ld + j] = t;
+    const int r = bidx[0];
+    if (tid == 0) {
+      piv[(int64_t)w * n + c] = r;
+      if (!(bval[0] > 0.0) || !isfinite(bval[0])) atomicExch(flag, 1);
+    }
+    if (r != c) {
+      for (int tt = tid; tt < bw; tt += NT) {
+        const double2 x = P[tt * n + c];
+        P[tt * n + c] = P[tt * n + r];
+        P[tt * n + r] = x;
+      }
+      for (int j = tid; j < n; j += NT) {
+        if (j >= k && j < k + bw) continue;
+        const double2 x = A[(int64_t)c * n + j];
+        A[(int64_t)c * n + j] = A[(int64_t)r * n + j];
+        A[(int64_t)r * n + j] = x;
       }
     }
     __syncthreads();
-    if (tid == 0) {
-      const double2 a = A[(int64_t)k * ld + k];
-      const double d = a.x * a.x + a.y * a.y;
-      pinv = d > 0.0 ? make_double2(a.x / d, -a.y / d) : make_double2(0.0, 0.0);
+    if (tid < bw) {
+      const double2 p = P[t * n + c];
+      const double d = p.x * p.x + p.y * p.y;
+      const double2 pinv = d > 0.0 ? make_double2(p.x / d, -p.y / d) : make_double2(0.0, 0.0);
+      prow[tid] = tid == t ? pinv : cmul(P[tid * n + c], pinv);
     }
     __syncthreads();
-    for (int j = k + tid; j < ld; j += NT) A[(int64_t)k * ld + j] = cmul(A[(int64_t)k * ld + j], pinv);
-    for (int i = tid; i < n; i += NT) fac[i] = A[(int64_t)i * ld + k];
-    __syncthreads();
-    const int w = ld - k;
-    for (int64_t e = tid; e < (int64_t)n * w; e += NT) {
-      const int i = (int)(e / w), j = k + (int)(e % w);
-      if (i == k) continue;
-      const double2 f = fac[i];
-      const double2 r = A[(int64_t)k * ld + j];
-      double2 a = A[(int64_t)i * ld + j];
-      a.x -= f.x * r.x - f.y * r.y;
-      a.y -= f.x * r.y + f.y * r.x;
-      A[(int64_t)i * ld + j] = a;
+    const double2 pinv = prow[t];
+    for (int i = tid; i < n; i += NT) {
+      if (i == c) {
+        for (int tt = 0; tt < bw; ++tt) P[tt * n + c] = prow[tt];
+      } else {
+        const double2 f = P[t * n + i];
+        for (int tt = 0; tt < bw; ++tt) {
+          if (tt == t) continue;
+          const double2 q = cmul(f, prow[tt]);
+          P[tt * n + i].x -= q.x;
+          P[tt * n + i].y -= q.y;
+        }
+        const double2 q = cmul(f, pinv);
+        P[t * n + i] = make_double2(-q.x, -q.y);
+      }
     }
     __syncthreads();
   }
+  for (int e = tid; e < n * bw; e += NT) {
+    const int i = e / bw, t = e % bw;
+    A[(int64_t)i * n + k + t] = P[t * n + i];
+  }
 }
 
-// Gstack[w][ij] = Re A^-1, Gstack[nw + w][ij] = Im A^-1.
-__global__ __launch_bounds__(NT) void extract_inv(const double2* __restrict__ Aug, int n, int nw,
+// A[:, j] += (W - E) A[k .. k+bw-1, j] for the columns j outside the panel; the
+// workgroup owns GJ_TCB columns (all rows) of one frequency, so the panel rows it
+// reads first are not yet overwritten.
+__global__ __launch_bounds__(NT) void gje_trail(double2* __restrict__ Am, int n, int k, int bw) {
+  __shared__ double2 X[GJ_B][GJ_TCB];
+  __shared__ double2 Wl[GJ_TRC][GJ_B];
+  const int tid = threadIdx.x, w = blockIdx.y;
+  double2* A = Am + (int64_t)w * n * n;
+  const int jj = tid % GJ_TCB, q = tid / GJ_TCB;
+  const int j0 = blockIdx.x * GJ_TCB, j = j0 + jj;
+  const bool active = j < n && (j < k || j >= k + bw);
+  for (int e = tid; e < bw * GJ_TCB; e += NT) {
+    const int t = e / GJ_TCB, c2 = e % GJ_TCB;
+    X[t][c2] = j0 + c2 < n ? A[(int64_t)(k + t) * n + j0 + c2] : make_double2(0.0, 0.0);
+  }
+  for (int i0 = 0; i0 < n; i0 += GJ_TRC) {
+    __syncthreads();
+    for (int e = tid; e < GJ_TRC * bw; e += NT) {
+      const int ii = e / bw, t = e % bw, i = i0 + ii;
+      double2 v = i < n ? A[(int64_t)i * n + k + t] : make_double2(0.0, 0.0);
+      if (i == k + t) v.x -= 1.0;
+      Wl[ii][t] = v;
+    }
+    __syncthreads();
+    if (active) {
+      for (int ii = q; ii < GJ_TRC && i0 + ii < n; ii += NT / GJ_TCB) {
+        double2 a = A[(int64_t)(i0 + ii) * n + j];
+        for (int t = 0; t < bw; ++t) {
+          const double2 wv = Wl[ii][t], x = X[t][jj];
+          a.x = fma(wv.x, x.x, fma(-wv.y, x.y, a.x));
+          a.y = fma(wv.x, x.y, fma(wv.y, x.x, a.y));
+        }
+        A[(int64_t)(i0 + ii) * n + j] = a;
+      }
+    }
+  }
+}
+
+// perm[w][j]: the column of the eliminated matrix that is column j of the
+// inverse (the row interchanges applied as column interchanges, last first).
+__global__ __launch_bounds__(NT) void gje_perm(const int* __restrict__ piv, int n, int nw,
+                                               int* __restrict__ perm) {
+  const int w = blockIdx.x * NT + threadIdx.x;
+  if (w >= nw) return;
+  int* pm = perm + (int64_t)w * n;
+  const int* pv = piv + (int64_t)w * n;
+  for (int j = 0; j < n; ++j) pm[j] = j;
+  for (int c = n - 1; c >= 0; --c) {
+    const int r = pv[c];
+    if (r != c) {
+      const int x = pm[c];
+      pm[c] = pm[r];
+      pm[r] = x;
+    }
+  }
+}
+
+// Gstack[w][ij] = Re G(i w)_ij, Gstack[nw + w][ij] = Im G(i w)_ij.
+__global__ __launch_bounds__(NT) void extract_inv(const double2* __restrict__ Am,
+                                                  const int* __restrict__ perm, int n, int nw,
                                                   double* __restrict__ Gs) {
   const int w = blockIdx.y;
   const int64_t nn = (int64_t)n * n;
-  const double2* A = Aug + (int64_t)w * 2 * nn;
+  const double2* A = Am + (int64_t)w * nn;
+  const int* pm = perm + (int64_t)w * n;
   for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < nn; e += (int64_t)gridDim.x * NT) {
     const int64_t i = e / n, j = e % n;
-    const double2 v = A[i * 2 * n + n + j];
+    const double2 v = A[i * n + pm[j]];
     Gs[(int64_t)w * nn + e] = v.x;
     Gs[(int64_t)(nw + w) * nn + e] = v.y;
   }
@@ -358,14 +454,16 @@ int dfail(int code, const std::string& m) { return set_error(code, m); }
 }  // namespace
 
 struct thcsox_dyson_s {
-  int n = 0, m = 0, nw = 0;
+  int n = 0, m = 0, nw = 0, panel = GJ_B;
   double beta = 0, mu = 0;
   hipStream_t stream = nullptr;
   double* F = nullptr;     // [n][n]
   double* Wf = nullptr;    // [2nw][m]
   double* Wb = nullptr;    // [m+1][2nw]
   double* Siw = nullptr;   // [2nw][n n]
-  double2* Aug = nullptr;  // [nw][n][2n]
+  double2* Am = nullptr;   // [nw][n][n]
+  int* piv = nullptr;      // [nw][n]
+  int* perm = nullptr;     // [nw][n]
   double* Gs = nullptr;    // [2nw][n n]
   double* Gout = nullptr;  // [m+1][n n]
   int* flag = nullptr;
@@ -407,6 +505,8 @@ int thcsox_dyson_plan(thcsox_dyson_t* out, int n, int ntau, int n_matsubara, dou
   *out = nullptr;
   if (n <= 0 || ntau <= 1 || n_matsubara <= 0 || !(beta > 0.0))
     return dfail(THCSOX_EINVAL, "need n > 0, ntau > 1, n_matsubara > 0, beta > 0");
+  if ((int64_t)n > GJ_LDS)
+    return dfail(THCSOX_EINVAL, "n too large for the in-LDS panel of the Dyson inversion (n <= 9216)");
   if (2 * n_matsubara < ntau)
     return dfail(THCSOX_EINVAL, "need 2 n_matsubara >= ntau for the least-squares fit");
   if (tau_host == nullptr || F_dev == nullptr) return dfail(THCSOX_EINVAL, "NULL argument");
@@ -423,13 +523,16 @@ int thcsox_dyson_plan(thcsox_dyson_t* out, int n, int ntau, int n_matsubara, dou
   }
   auto* d = new thcsox_dyson_s();
   d->n = n; d->m = ntau; d->nw = n_matsubara; d->beta = beta; d->mu = mu;
+  while (d->panel > 1 && (int64_t)d->panel * n > GJ_LDS) d->panel /= 2;
   d->stream = static_cast<hipStream_t>(hip_stream);
   const int64_t nn = (int64_t)n * n;
   int rc;
   if ((rc = dalloc(d, &d->F, nn)) || (rc = dalloc(d, &d->Wf, (size_t)2 * d->nw * d->m)) ||
       (rc = dalloc(d, &d->Wb, (size_t)(d->m + 1) * 2 * d->nw)) ||
       (rc = dalloc(d, &d->Siw, (size_t)2 * d->nw * nn)) ||
-      (rc = dalloc(d, &d->Aug, (size_t)d->nw * 2 * nn)) ||
+      (rc = dalloc(d, &d->Am, (size_t)d->nw * nn)) ||
+      (rc = dalloc(d, &d->piv, (size_t)d->nw * n)) ||
+      (rc = dalloc(d, &d->perm, (size_t)d->nw * n)) ||
       (rc = dalloc(d, &d->Gs, (size_t)2 * d->nw * nn)) ||
       (rc = dalloc(d, &d->Gout, (size_t)(d->m + 1) * nn)) || (rc = dalloc(d, &d->flag, 1)) ||
       (rc = dalloc(d, &d->scal, 1))) {
@@ -466,12 +569,20 @@ int thcsox_dyson_step(thcsox_dyson_t d, const double* Sigma_dev, double* G_dev, 
   g.C = d->Siw; g.c_i = nn; g.c_j = 1; g.cj_in = nn; g.cj_out = 0;
   DTRY(gemm64(g, s));
   const unsigned bx = (unsigned)std::min<int64_t>(64, (nn + NT - 1) / NT);
-  build_aug<<<dim3(bx, nw), NT, 0, s>>>(d->Siw, d->F, d->mu, d->beta, n, nw, d->Aug);
+  build_a<<<dim3(bx, nw), NT, 0, s>>>(d->Siw, d->F, d->mu, d->beta, n, nw, d->Am);
   DTRY(hipGetLastError());
   DTRY(hipMemsetAsync(d->flag, 0, sizeof(int), s));
-  gauss_jordan<<<nw, NT, sizeof(double2) * n, s>>>(d->Aug, n, d->flag);
+  const int bw = d->panel;
+  for (int k = 0; k < n; k += bw) {
+    const int w = std::min(bw, n - k);
+    gje_panel<<<nw, NT, 0, s>>>(d->Am, n, k, w, d->piv, d->flag);
+    DTRY(hipGetLastError());
+    gje_trail<<<dim3((unsigned)((n + GJ_TCB - 1) / GJ_TCB), nw), NT, 0, s>>>(d->Am, n, k, w);
+    DTRY(hipGetLastError());
+  }
+  gje_perm<<<(unsigned)((nw + NT - 1) / NT), NT, 0, s>>>(d->piv, n, nw, d->perm);
   DTRY(hipGetLastError());
-  extract_inv<<<dim3(bx, nw), NT, 0, s>>>(d->Aug, n, nw, d->Gs);
+  extract_inv<<<dim3(bx, nw), NT, 0, s>>>(d->Am, d->perm, n, nw, d->Gs);
   DTRY(hipGetLastError());
   // [G(tau_0) .. G(tau_{m-1}); gamma] = Wb . [Re G(i w); Im G(i w)]
   g.M = m + 1; g.N = (int)nn; g.K = 2 * nw;

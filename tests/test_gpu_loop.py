@@ -59,6 +59,36 @@ def test_dyson_step_matches_oracle(dev):
     assert _rel(gam.cpu().numpy(), gam_ref) < 1e-10
 
 
+def test_dyson_step_pivoting_ragged_panels(dev):
+    """A large non-physical Sigma (random, 40 x the spread of F) makes every
+    frequency's Dyson matrix far from diagonally dominant, so the inversion has
+    to interchange rows; n=150 is 18 panels of 8 columns and one of 6."""
+    s = synth.make_system(150, 300, seed=21)
+    tau, w = synth.cheb_tau_grid(32, 100.0)
+    rng = np.random.default_rng(22)
+    S = 40.0 * np.abs(s.F).max() * rng.standard_normal((32, 150, 150))
+    print("case dyson n150 ntau32 nw64 random Sigma", flush=True)
+    Tm = otr.cheb_to_matsubara(32, 64, 100.0)
+    G_ref, gam_ref, _ = otr.loop_step(s.F, s.mu, 100.0, S, Tm)
+    d = thcsox.Dyson(torch.from_numpy(s.F).to(dev), s.mu, tau, 100.0, 64)
+    G, gam = d.step(torch.from_numpy(S).to(dev))
+    d.close()
+    assert _rel(G.cpu().numpy(), G_ref) < 1e-10
+    assert _rel(gam.cpu().numpy(), gam_ref) < 1e-10
+
+
+def test_dyson_nonfinite_sigma_is_an_error(dev):
+    s = synth.make_system(12, 40, seed=3)
+    tau, w = synth.cheb_tau_grid(8, 100.0)
+    S = np.zeros((8, 12, 12))
+    S[3, 5, 5] = np.nan
+    print("case dyson n12 non-finite Sigma", flush=True)
+    d = thcsox.Dyson(torch.from_numpy(s.F).to(dev), s.mu, tau, 100.0, 16)
+    with pytest.raises(thcsox.ThcsoxError):
+        d.step(torch.from_numpy(S).to(dev))
+    d.close()
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16x2"])
 def test_one_iteration_n100(dev, precision):
     """SOX at G0, its energy, then one Dyson step, at n=100, naux=500, 64 tau,
