@@ -135,11 +135,14 @@ __global__ void fill_u64_kernel(unsigned long long* p, int64_t n, unsigned long 
     p[i] = v;
 }
 
-// One workgroup per 64 x 64 tile of Sthc: sum the partial D tiles over z and
-// scale.  With the symmetric path, tiles below the diagonal are the transposes
-// of tiles above it (read row-wise and transposed through LDS), and inside a
-// diagonal tile the entries with R > P come from the mirrored position.
-constexpr int DT = 64;
+// One workgroup per 32 x 32 tile of Sthc: sum the partial D tiles over z and
+// scale.  With the symmetric path only the tiles on and above the diagonal are
+// read: each writes itself and (through LDS) its transpose below the diagonal,
+// and inside a diagonal tile the entries with R > P come from the mirrored
+// position.
+constexpr int DT = 32;          // reduction tile edge
+constexpr int DRP = NT / DT;    // rows per pass
+constexpr int DEL = DT / DRP;   // elements per thread
 __global__ __launch_bounds__(NT) void dreduce_kernel(DReduceArgs a) {
   __shared__ double t[DT][DT + 1];
   const double f = pow2_scale(a.amax_gt) * pow2_scale(a.amax_gx) * pow2_scale(a.amax_gb) *
@@ -149,34 +152,41 @@ __global__ __launch_bounds__(NT) void dreduce_kernel(DReduceArgs a) {
   const bool sym = a.sym != nullptr && *a.sym != 0;
   const int nt = (a.naux + DT - 1) / DT;
   const int rb = blockIdx.x / nt, pb = blockIdx.x % nt;
-  const bool mirror = sym && rb > pb;          // read the tile (pb, rb) and transpose
-  const int sr = mirror ? pb : rb, sc = mirror ? rb : pb;   // source tile rows, columns
-  const int col = threadIdx.x & (DT - 1), row0 = threadIdx.x / DT;   // 4 rows per pass
-  double acc[DT / 4];
+  // symmetric D: the tiles below the diagonal are written by their transposes
+  if (sym && rb > pb) return;
+  const int col = threadIdx.x % DT, row0 = threadIdx.x / DT;
+  double acc[DEL];
 #pragma unroll
-  for (int i = 0; i < DT / 4; ++i) acc[i] = 0.0;
-  const int gc = sc * DT + col;
+  for (int i = 0; i < DEL; ++i) acc[i] = 0.0;
+  const int gc = pb * DT + col;
+  // independent loads of several partial sums in flight per thread
+#pragma unroll 4
   for (int z = 0; z < a.vsplit; ++z) {
     const double* Dz = a.Dpart + z * nn;
 #pragma unroll
-    for (int i = 0; i < DT / 4; ++i) {
-      const int gr = sr * DT + row0 + 4 * i;
+    for (int i = 0; i < DEL; ++i) {
+      const int gr = rb * DT + row0 + DRP * i;
       if (gr < a.naux && gc < a.naux) acc[i] += Dz[(int64_t)gr * a.naux + gc];
     }
   }
 #pragma unroll
-  for (int i = 0; i < DT / 4; ++i) t[row0 + 4 * i][col] = acc[i];
+  for (int i = 0; i < DEL; ++i) t[row0 + DRP * i][col] = acc[i];
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < DT / 4; ++i) {
-    const int lr = row0 + 4 * i, lc = col;      // output element (R, P) of tile (rb, pb)
+  for (int i = 0; i < DEL; ++i) {
+    const int lr = row0 + DRP * i, lc = col;
+    // element (R, P) of tile (rb, pb); on a symmetric diagonal tile the lower
+    // half comes from the upper
     const int R = rb * DT + lr, P = pb * DT + lc;
-    if (R >= a.naux || P >= a.naux) continue;
-    double v;
-    if (mirror) v = t[lc][lr];
-    else if (sym && rb == pb && R > P) v = t[lc][lr];
-    else v = t[lr][lc];
-    a.Sthc[(int64_t)R * a.s_ld + P] = -inv * v;
+    if (R < a.naux && P < a.naux) {
+      const double v = (sym && rb == pb && R > P) ? t[lc][lr] : t[lr][lc];
+      a.Sthc[(int64_t)R * a.s_ld + P] = -inv * v;
+    }
+    // symmetric, off the diagonal: element (R2, P2) of the transposed tile (pb, rb)
+    if (sym && rb < pb) {
+      const int R2 = pb * DT + lr, P2 = rb * DT + lc;
+      if (R2 < a.naux && P2 < a.naux) a.Sthc[(int64_t)R2 * a.s_ld + P2] = -inv * t[lc][lr];
+    }
   }
 }
 
