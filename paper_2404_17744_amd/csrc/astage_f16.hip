@@ -23,6 +23,7 @@
 #include "kernels.hpp"
 #include "mfma.hpp"
 #include "panel.hpp"
+#include "reduce.hpp"
 
 namespace thcsox {
 namespace {
@@ -43,11 +44,6 @@ template <int WBN> struct AFrags {
 
 __device__ __forceinline__ void a_vm_lds_barrier() {
   __asm__ volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
-}
-
-__device__ __forceinline__ double a_wave_max(double v) {
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
 }
 
 template <int WBN>
@@ -200,10 +196,7 @@ __device__ __forceinline__ void astage_body(const GemmKArgs& g, ABuf& b0, ABuf& 
   }
   // the last (repeated) memory-to-LDS loads land before the workgroup may end
   __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  if (g.amax != nullptr) {
-    lmax = a_wave_max(lmax);
-    if (lane == 0) atomicMax(g.amax, (unsigned long long)__double_as_longlong(lmax));
-  }
+  if (g.amax != nullptr) block_atomic_max<ANW>(lmax, g.amax);
 }
 
 // one kernel per column count (the body is a device template)

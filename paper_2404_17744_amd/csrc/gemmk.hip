@@ -8,14 +8,10 @@
 #include "kernels.hpp"
 #include "mfma.hpp"
 #include "panel.hpp"
+#include "reduce.hpp"
 
 namespace thcsox {
 namespace {
-
-__device__ __forceinline__ double wave_max_d(double v) {
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
-}
 
 template <int M, int WTI, int WTJ, typename OutT>
 __global__ __launch_bounds__(NT) void gemmk_kernel(GemmKArgs g) {
@@ -110,10 +106,7 @@ __global__ __launch_bounds__(NT) void gemmk_kernel(GemmKArgs g) {
           lmax = fmax(lmax, fabs((double)v));
         }
       }
-  if (g.amax != nullptr) {
-    lmax = wave_max_d(lmax);
-    if (lane == 0) atomicMax(g.amax, (unsigned long long)__double_as_longlong(lmax));
-  }
+  if (g.amax != nullptr) block_atomic_max<NT / 64>(lmax, g.amax);
 }
 
 inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }

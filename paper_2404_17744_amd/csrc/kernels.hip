@@ -2,6 +2,7 @@
 // kernels.hpp; the C interface that sequences them is in thcsox.hip.
 #include "kernels.hpp"
 #include "mfma.hpp"
+#include "reduce.hpp"
 
 namespace thcsox {
 
@@ -16,11 +17,6 @@ __device__ __forceinline__ double pow2_scale(const unsigned long long* amax) {
   double x = __longlong_as_double((long long)b);
   if (!(x < 1e300)) return 1.0;   // inf / nan: leave unscaled, the result shows it
   return ldexp(1.0, -ilogb(x));
-}
-
-__device__ __forceinline__ double wave_max(double v) {
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
 }
 
 // ---------------------------------------------------------------------------
@@ -125,8 +121,7 @@ __global__ __launch_bounds__(NT) void absmax_kernel(const double* x, int64_t len
   double m = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < len; i += (int64_t)gridDim.x * NT)
     m = fmax(m, fabs(xb[i]));
-  m = wave_max(m);
-  if ((threadIdx.x & 63) == 0) atomicMax(amax + b, (unsigned long long)__double_as_longlong(m));
+  block_atomic_max<NT / 64>(m, amax + b);
 }
 
 __global__ void fill_u64_kernel(unsigned long long* p, int64_t n, unsigned long long v) {
@@ -201,8 +196,7 @@ __global__ __launch_bounds__(NT) void asym_kernel(const double* G, int n,
     const int i = (int)(e / n), j = (int)(e % n);
     if (j > i) m = fmax(m, fabs(g[(int64_t)i * n + j] - g[(int64_t)j * n + i]));
   }
-  m = wave_max(m);
-  if ((threadIdx.x & 63) == 0) atomicMax(asym + k, (unsigned long long)__double_as_longlong(m));
+  block_atomic_max<NT / 64>(m, asym + k);
 }
 
 __global__ void sym_flags_kernel(const unsigned long long* asym, const unsigned long long* amax,
@@ -282,8 +276,9 @@ hipError_t split_planes(int mode, const SplitArgs& a, hipStream_t s) {
 hipError_t absmax64(const double* x, int64_t len, int64_t stride, int batch,
                     unsigned long long* amax, hipStream_t s) {
   if (len <= 0 || batch <= 0) return hipSuccess;
+  // a few workgroups per row: one atomic each
   unsigned bx = cdiv(len, NT);
-  if (bx > 1024) bx = 1024;
+  if (bx > 64) bx = 64;
   absmax_kernel<<<dim3(bx, batch), NT, 0, s>>>(x, len, stride, amax);
   return hipGetLastError();
 }
