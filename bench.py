@@ -60,10 +60,11 @@ def timed_steps(plan, Gd, S, steps, torch):
 
 
 def fused_source_hash():
-    """Hash of the sources that make up the fused kernel."""
+    """Hash of the sources that make up the fused kernel and of the plan code that
+    chooses its launch (the v split sets how often partial tiles are flushed)."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("fused.hip", "fused_f16.hip", "panel.hpp", "mfma.hpp", "kernels.hpp"):
+    for f in ("fused.hip", "fused_f16.hip", "panel.hpp", "mfma.hpp", "kernels.hpp", "thcsox.hip"):
         with open(os.path.join(ROOT, "paper_2404_17744_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

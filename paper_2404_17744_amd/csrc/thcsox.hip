@@ -416,6 +416,18 @@ int thcsox_plan(thcsox_plan_t* out, int n, int naux, int ntau, double beta,
       eff *= 1.0 - 0.002 * vs;                           // mild preference for long v ranges
       if (eff > best_eff) { best_eff = eff; best = vs; }
     }
+    // The reduced-precision kernels add their FP32 partial sum of D into the
+    // FP64 partial tile every 8 v; with v ranges of at most 8 each workgroup
+    // writes its tile once and never reads it back.  Use that split when the
+    // partial-D buffer stays small (measured at n = 300, naux = 1800: 2-4 %
+    // faster than the balance choice above, full and symmetric paths).
+    if (precision != THCSOX_FP64) {
+      const int vs8 = ((n + 7) / 8 + nx - 1) / nx * nx;
+      const double dbytes = 8.0 * vs8 * (double)naux * naux;
+      const bool fits = dbytes <= 2.0e9 &&
+                        (workspace_limit == 0 || dbytes <= 0.25 * (double)workspace_limit);
+      if (fits && vs8 > best) best = vs8;
+    }
     p->vsplit = best;
     p->vchunk = (n + best - 1) / best;   // trailing ranges may be empty (they write zeros)
   }
