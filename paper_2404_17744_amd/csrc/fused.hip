@@ -69,8 +69,9 @@ __global__ __launch_bounds__(NT) void fused_kernel(FusedArgs f) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   // XCD-aware placement.  Workgroups are dealt round-robin to the XCDs, so
-  // workgroup b runs on XCD b % NXCD.  Each XCD takes the v ranges z = xcd,
-  // xcd + NXCD, ... for every tile, and walks the tiles in bands of BAND R
+  // workgroup b runs on XCD b % NXCD.  Each XCD takes vsplit / NXCD partial
+  // slots z = xcd, xcd + NXCD, ... (a block of consecutive v ranges, below)
+  // for every tile, and walks the tiles in bands of BAND R
   // blocks, P block by P block: the workgroups resident on one XCD at a time
   // form a compact BAND x (CUs per XCD / BAND) block of tiles at the same v,
   // which share the U_v and A_v panels through that XCD's L2.
@@ -86,8 +87,12 @@ __global__ __launch_bounds__(NT) void fused_kernel(FusedArgs f) {
   const int P0 = (within / bh) * TP, R0 = (rb0 + within % bh) * TR;
   // symmetric D: a tile wholly below the diagonal is the mirror of one above it
   if (f.sym != nullptr && *f.sym != 0 && R0 >= P0 + TP) return;
-  const int v_lo = z * f.vchunk;
-  const int v_hi = min(f.n, v_lo + f.vchunk);
+  // v range: XCD x owns the consecutive ranges x q .. x q + q - 1 (q = vsplit / NXCD),
+  // and the ranges split n as evenly as floor division allows, so every XCD gets
+  // the same number of v to within one; range r is [r n / vsplit, (r + 1) n / vsplit)
+  const int vr = (z % NXCD) * (f.vsplit / NXCD) + z / NXCD;
+  const int v_lo = (int)((int64_t)vr * f.n / f.vsplit);
+  const int v_hi = (int)((int64_t)(vr + 1) * f.n / f.vsplit);
   const int kst = f.ldk / BK;
   const int nstage = (v_hi > v_lo) ? (v_hi - v_lo) * kst : 0;
   const int64_t ldk = f.ldk;

@@ -70,7 +70,8 @@ void fused_f16_kernel(FusedArgs f) {
   const int wr = wave / WP_, wc = wave % WP_;
 
   // tile and v range: XCD-aware order (workgroup b runs on XCD b mod 8; each XCD
-  // owns v ranges z = xcd, xcd + 8, ... and walks the tiles in bands of BAND16
+  // owns the partial slots z = xcd, xcd + 8, ..., a block of consecutive v ranges
+  // (below), and walks the tiles in bands of BAND16
   // R blocks so its resident workgroups share U_v and A_v panels in its L2)
   const int nb = (f.naux + TT - 1) / TT;
   const int tiles = nb * nb;
@@ -84,8 +85,12 @@ void fused_f16_kernel(FusedArgs f) {
   const int P0 = (within / bh) * TT, R0 = (rb0 + within % bh) * TT;
   if (f.sym != nullptr && *f.sym != 0 && R0 >= P0 + TT) return;
 
-  const int v_lo = z * f.vchunk;
-  const int v_hi = min(f.n, v_lo + f.vchunk);
+  // v range: XCD x owns the consecutive ranges x q .. x q + q - 1 (q = vsplit / NXCD16),
+  // and the ranges split n as evenly as floor division allows, so every XCD gets
+  // the same number of v to within one; range r is [r n / vsplit, (r + 1) n / vsplit)
+  const int vr = (z % NXCD16) * (f.vsplit / NXCD16) + z / NXCD16;
+  const int v_lo = (int)((int64_t)vr * f.n / f.vsplit);
+  const int v_hi = (int)((int64_t)(vr + 1) * f.n / f.vsplit);
   const int kst = f.ldk / KC;
   const int nstage = (v_hi > v_lo) ? (v_hi - v_lo) * kst : 0;
   const int64_t ldk = f.ldk;

@@ -429,7 +429,7 @@ int thcsox_plan(thcsox_plan_t* out, int n, int naux, int ntau, double beta,
       if (fits && vs8 > best) best = vs8;
     }
     p->vsplit = best;
-    p->vchunk = (n + best - 1) / best;   // trailing ranges may be empty (they write zeros)
+    p->vchunk = (n + best - 1) / best;   // longest v range (ranges are balanced over the XCDs)
   }
 
   int rc = 0;
