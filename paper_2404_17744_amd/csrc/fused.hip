@@ -156,6 +156,7 @@ __global__ __launch_bounds__(NT) void fused_kernel(FusedArgs f) {
         accD[ti][tj][r] = 0;
       }
   double* D = f.Dpart + (int64_t)z * f.naux * f.naux;
+  float* D32 = reinterpret_cast<float*>(f.Dpart) + (int64_t)z * f.naux * f.naux;
   // add (or, the first time, store) the register partial sums into the FP64 tile
   auto flush = [&](bool first) {
 #pragma unroll
@@ -167,8 +168,12 @@ __global__ __launch_bounds__(NT) void fused_kernel(FusedArgs f) {
           const int R = R0 + wr * 16 * WTI + 16 * ti + out_row<M>(lane, r);
           const int P = P0 + wc * 16 * WTJ + 16 * tj + (lane & 15);
           if (R < f.naux && P < f.naux) {
-            double* d = D + (int64_t)R * f.naux + P;
-            *d = (first ? 0.0 : *d) + (double)accD[ti][tj][r];
+            if (f.dpart_f32) {   // one range = one FP32 partial sum (first is true)
+              D32[(int64_t)R * f.naux + P] = (float)accD[ti][tj][r];
+            } else {
+              double* d = D + (int64_t)R * f.naux + P;
+              *d = (first ? 0.0 : *d) + (double)accD[ti][tj][r];
+            }
           }
           accD[ti][tj][r] = 0;
         }
@@ -295,6 +300,8 @@ hipError_t sox_fused(int mode, const FusedArgs& f, hipStream_t s) {
   int TR, TP;
   fused_tile(mode, &TR, &TP);
   if (f.vsplit % NXCD != 0 || (int64_t)f.vsplit * f.vchunk < f.n) return hipErrorInvalidValue;
+  // FP32 partial tiles only where each range is one FP32 partial sum
+  if (f.dpart_f32 && (mode == MODE_F64 || f.vchunk > FLUSH_V)) return hipErrorInvalidValue;
   // buffer offsets inside one tile's rows of U are 32-bit
   if ((int64_t)std::max(TR, TP) * f.n * f.ldk * 8 > 0x7fffffffLL) return hipErrorInvalidValue;
   dim3 grid(cdiv(f.naux, TP) * cdiv(f.naux, TR) * f.vsplit);

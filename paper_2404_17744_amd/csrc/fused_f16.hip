@@ -223,7 +223,9 @@ void fused_f16_kernel(FusedArgs f) {
 
   // this lane's first element of D: row R0 + wr*64 + 4*(lane/16), column P0 + wc*64 + lane%16
   const int Rl = R0 + wr * 16 * WBR + 4 * (lane >> 4), Pl = P0 + wc * 16 * WBP + (lane & 15);
-  double* const Dl = f.Dpart + (int64_t)z * f.naux * f.naux + (int64_t)Rl * f.naux + Pl;
+  const int64_t dl_off = (int64_t)z * f.naux * f.naux + (int64_t)Rl * f.naux + Pl;
+  double* const Dl = f.Dpart + dl_off;
+  float* const Dl32 = reinterpret_cast<float*>(f.Dpart) + dl_off;
   auto flush = [&](bool first) {
 #pragma unroll
     for (int ti = 0; ti < WBR; ++ti)
@@ -233,8 +235,12 @@ void fused_f16_kernel(FusedArgs f) {
 #pragma unroll
         for (int tj = 0; tj < WBP; ++tj) {
           if (row_ok && Pl + 16 * tj < f.naux) {
-            double* d = Dl + (16 * ti + r) * f.naux + 16 * tj;
-            *d = (first ? 0.0 : *d) + (double)accD[ti][tj][r];
+            if (f.dpart_f32) {   // one range = one FP32 partial sum (first is true)
+              Dl32[(16 * ti + r) * f.naux + 16 * tj] = accD[ti][tj][r];
+            } else {
+              double* d = Dl + (16 * ti + r) * f.naux + 16 * tj;
+              *d = (first ? 0.0 : *d) + (double)accD[ti][tj][r];
+            }
           }
           accD[ti][tj][r] = 0.f;
         }
@@ -318,6 +324,7 @@ void fused_f16_tile(int* rows, int* cols) {
 
 hipError_t sox_fused_f16(const FusedArgs& f, hipStream_t s) {
   if (!f.a_f32 || f.vsplit % NXCD16 != 0 || (int64_t)f.vsplit * f.vchunk < f.n ||
+      (f.dpart_f32 && f.vchunk > FLUSH16) ||
       f.ldk % (2 * KC) != 0)
     return hipErrorInvalidValue;
   // buffer offsets inside one tile's rows of U (fp16) and A (FP32) are 32-bit

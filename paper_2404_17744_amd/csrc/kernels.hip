@@ -138,6 +138,7 @@ __global__ void fill_u64_kernel(unsigned long long* p, int64_t n, unsigned long 
 constexpr int DT = 32;          // reduction tile edge
 constexpr int DRP = NT / DT;    // rows per pass
 constexpr int DEL = DT / DRP;   // elements per thread
+template <typename T>
 __global__ __launch_bounds__(NT) void dreduce_kernel(DReduceArgs a) {
   __shared__ double t[DT][DT + 1];
   const double f = pow2_scale(a.amax_gt) * pow2_scale(a.amax_gx) * pow2_scale(a.amax_gb) *
@@ -157,11 +158,11 @@ __global__ __launch_bounds__(NT) void dreduce_kernel(DReduceArgs a) {
   // independent loads of several partial sums in flight per thread
 #pragma unroll 4
   for (int z = 0; z < a.vsplit; ++z) {
-    const double* Dz = a.Dpart + z * nn;
+    const T* Dz = reinterpret_cast<const T*>(a.Dpart) + z * nn;
 #pragma unroll
     for (int i = 0; i < DEL; ++i) {
       const int gr = rb * DT + row0 + DRP * i;
-      if (gr < a.naux && gc < a.naux) acc[i] += Dz[(int64_t)gr * a.naux + gc];
+      if (gr < a.naux && gc < a.naux) acc[i] += (double)Dz[(int64_t)gr * a.naux + gc];
     }
   }
 #pragma unroll
@@ -294,7 +295,8 @@ hipError_t fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipS
 hipError_t dreduce(const DReduceArgs& a, hipStream_t s) {
   if (a.naux <= 0) return hipSuccess;
   const unsigned nt = cdiv(a.naux, DT);
-  dreduce_kernel<<<nt * nt, NT, 0, s>>>(a);
+  if (a.dpart_f32) dreduce_kernel<float><<<nt * nt, NT, 0, s>>>(a);
+  else dreduce_kernel<double><<<nt * nt, NT, 0, s>>>(a);
   return hipGetLastError();
 }
 

@@ -51,6 +51,10 @@ struct FusedArgs {
   bool a_f32;
   const unsigned long long* amax_a;
   double* Dpart;                                       // [vsplit][naux][naux]
+  // Dpart holds FP32 partial tiles (reinterpreted as float*).  Only with v ranges
+  // of at most 8 in the reduced-precision modes: each range is then one FP32
+  // partial sum, so storing it as FP32 is exact.
+  bool dpart_f32;
   // If sym != nullptr and *sym != 0, D is symmetric (G(tau) and G(beta - tau)
   // symmetric): tiles lying wholly below the diagonal (every R > every P) are
   // skipped and their Dpart entries are left untouched.
@@ -86,7 +90,8 @@ hipError_t fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipS
 // fused stage), entries with R > P are taken from the mirrored position P, R.
 struct DReduceArgs {
   int naux, vsplit;
-  const double* Dpart;
+  const double* Dpart;   // FP64 partial tiles, or FP32 ones if dpart_f32
+  bool dpart_f32;
   double* Sthc; int64_t s_ld;
   const unsigned long long* amax_gt; const unsigned long long* amax_gx;
   const unsigned long long* amax_gb; const unsigned long long* amax_a;

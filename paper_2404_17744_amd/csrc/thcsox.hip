@@ -95,7 +95,8 @@ struct thcsox_plan_s {
   int64_t gb_plane = 0;
   double* Gt64 = nullptr;   // [tb][naux][n]
   double* GX64 = nullptr;   // [tb][naux][n]
-  double* Dpart = nullptr;  // [vsplit][naux][naux]
+  double* Dpart = nullptr;  // [vsplit][naux][naux], FP64 or (dpart_f32) FP32
+  bool dpart_f32 = false;
   int vsplit = 1, vchunk = 1;
   double* Sthc = nullptr;   // [tb][naux][naux]
   double* T1 = nullptr;     // [tb][n][naux]
@@ -317,7 +318,7 @@ int sigma_batch(thcsox_plan_s* p, const double* G, double* Sigma, double* Sthc_o
     f.U = p->U; f.u_plane = p->u_plane;
     f.A = split_a ? static_cast<const void*>(p->A32) : p->A; f.a_plane = p->a_plane;
     f.a_f32 = split_a; f.amax_a = split_a ? p->am_a() + k : nullptr;
-    f.Dpart = p->Dpart;
+    f.Dpart = p->Dpart; f.dpart_f32 = p->dpart_f32;
     f.sym = sym;
     HIP_TRY(p->mark(THCSOX_STAGE_FUSED, true));
     HIP_TRY(sox_fused(mode, f, s));
@@ -325,7 +326,7 @@ int sigma_batch(thcsox_plan_s* p, const double* G, double* Sigma, double* Sthc_o
 
     HIP_TRY(p->mark(THCSOX_STAGE_BACK, true));
     DReduceArgs d{};
-    d.naux = naux; d.vsplit = p->vsplit; d.Dpart = p->Dpart;
+    d.naux = naux; d.vsplit = p->vsplit; d.Dpart = p->Dpart; d.dpart_f32 = p->dpart_f32;
     d.Sthc = Sthc_out ? Sthc_out + (int64_t)k * aa : p->Sthc + (int64_t)b * aa;
     d.s_ld = naux;
     d.amax_gt = p->am_gt() + k; d.amax_gx = p->am_gx() + k; d.amax_gb = p->am_g() + kb;
@@ -416,20 +417,23 @@ int thcsox_plan(thcsox_plan_t* out, int n, int naux, int ntau, double beta,
       eff *= 1.0 - 0.002 * vs;                           // mild preference for long v ranges
       if (eff > best_eff) { best_eff = eff; best = vs; }
     }
-    // The reduced-precision kernels add their FP32 partial sum of D into the
-    // FP64 partial tile every 8 v; with v ranges of at most 8 each workgroup
-    // writes its tile once and never reads it back.  Use that split when the
-    // partial-D buffer stays small (measured at n = 300, naux = 1800: 2-4 %
-    // faster than the balance choice above, full and symmetric paths).
+    // The reduced-precision kernels keep an FP32 partial sum of D for 8 v and
+    // then add it into the partial tile; with v ranges of at most 8 each
+    // workgroup writes its tile once, never reads it back, and the tile can be
+    // FP32.  Use that split when the partial-D buffer stays small (measured at
+    // n = 300, naux = 1800: 2-4 % faster than the balance choice above, full
+    // and symmetric paths).
     if (precision != THCSOX_FP64) {
       const int vs8 = ((n + 7) / 8 + nx - 1) / nx * nx;
-      const double dbytes = 8.0 * vs8 * (double)naux * naux;
+      const double dbytes = 4.0 * vs8 * (double)naux * naux;   // FP32 partial tiles
       const bool fits = dbytes <= 2.0e9 &&
                         (workspace_limit == 0 || dbytes <= 0.25 * (double)workspace_limit);
       if (fits && vs8 > best) best = vs8;
     }
     p->vsplit = best;
     p->vchunk = (n + best - 1) / best;   // longest v range (ranges are balanced over the XCDs)
+    // ranges of at most 8 v are one FP32 partial sum each: store them as FP32
+    p->dpart_f32 = precision != THCSOX_FP64 && p->vchunk <= 8;
   }
 
   int rc = 0;
@@ -446,7 +450,7 @@ int thcsox_plan(thcsox_plan_t* out, int n, int naux, int ntau, double beta,
       const double fixed = 8.0 * ((double)n * naux + 7.0 * ntau + 2.0) +
                            (double)p->np * p->esize * naux * n * ldk +
                            (p->np > 1 ? 4.0 : (double)p->esize) * n * naux * ldk +
-                           8.0 * p->vsplit * (double)naux * naux + (1 << 20);
+                           (p->dpart_f32 ? 4.0 : 8.0) * p->vsplit * (double)naux * naux + (1 << 20);
       cap = std::min(cap, (double)workspace_limit - fixed);
     }
     p->tb = (int)std::max(1.0, std::min({16.0, (double)ntau, std::floor(cap / per_tau)}));
@@ -476,7 +480,10 @@ int thcsox_plan(thcsox_plan_t* out, int n, int naux, int ntau, double beta,
   p->Gb = tmp;
   if ((rc = p->alloc(&p->Gt64, (size_t)p->tb * naux * n))) return bail(rc);
   if ((rc = p->alloc(&p->GX64, (size_t)p->tb * naux * n))) return bail(rc);
-  if ((rc = p->alloc(&p->Dpart, (size_t)p->vsplit * naux * naux))) return bail(rc);
+  {
+    const size_t dn = (size_t)p->vsplit * naux * naux;
+    if ((rc = p->alloc(&p->Dpart, p->dpart_f32 ? (dn + 1) / 2 : dn))) return bail(rc);
+  }
   if ((rc = p->alloc(&p->Sthc, (size_t)p->tb * naux * naux))) return bail(rc);
   if ((rc = p->alloc(&p->T1, (size_t)p->tb * n * naux))) return bail(rc);
 
