@@ -20,12 +20,32 @@ __device__ __forceinline__ double pow2_scale(const unsigned long long* amax) {
 }
 
 // ---------------------------------------------------------------------------
-// Strided FP64 GEMM (projections, back-projection, U precontraction)
+// Strided FP64 GEMM (projections, back-projection, U precontraction, Dyson
+// transforms): 64 x 64 tiles of C, k steps of 32, four waves of 32 x 32 on the
+// f64 matrix cores.  The next k step is loaded into registers while the current
+// one is multiplied out of LDS.  Operands are read in pairs of doubles (16-byte
+// loads) along their contiguous dimension: AM = 0 when A is contiguous in k
+// (a_k == 1), 1 when contiguous in i (a_i == 1); BM = 0 when B is contiguous in j
+// (b_j == 1), 1 when contiguous in k (b_k == 1).  VEC is false when a stride or
+// base is odd (then the pairs are two 8-byte loads).
 // ---------------------------------------------------------------------------
+constexpr int G64_BK = 32, G64_LD = G64_BK + 1;
+typedef double d2 __attribute__((ext_vector_type(2)));
+
+template <bool VEC>
+__device__ __forceinline__ d2 g64_pair(const double* p, int x, int lim) {
+  // elements x, x + 1 along the contiguous dimension (zero past lim)
+  if (VEC && x + 1 < lim) {
+    const double2 v = *reinterpret_cast<const double2*>(p + x);
+    return d2{v.x, v.y};
+  }
+  return d2{x < lim ? p[x] : 0.0, x + 1 < lim ? p[x + 1] : 0.0};
+}
+
+template <int AM, int BM, bool VEC>
 __global__ __launch_bounds__(NT) void gemm64_kernel(Gemm64Args g) {
-  constexpr int BK = 16, LD = 17;
-  __shared__ double sA[64 * LD];
-  __shared__ double sB[64 * LD];
+  __shared__ double sA[64 * G64_LD];   // [i][k]
+  __shared__ double sB[64 * G64_LD];   // [j][k]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
@@ -38,29 +58,65 @@ __global__ __launch_bounds__(NT) void gemm64_kernel(Gemm64Args g) {
 #pragma unroll
     for (int tj = 0; tj < 2; ++tj) acc[ti][tj] = d4{0.0, 0.0, 0.0, 0.0};
 
-  for (int k0 = 0; k0 < g.K; k0 += BK) {
+  // 1024 pairs per operand and k step, four per thread
+  d2 ra[4], rb[4];
+  auto load = [&](int k0) {
 #pragma unroll
-    for (int e = tid; e < 64 * BK; e += NT) {
-      int i, k;
-      if (g.a_k == 1) { i = e >> 4; k = e & 15; } else { i = e & 63; k = e >> 6; }
-      const int gi = i0 + i, gk = k0 + k;
-      sA[i * LD + k] = (gi < g.M && gk < g.K) ? A[(int64_t)gi * g.a_i + (int64_t)gk * g.a_k] : 0.0;
+    for (int t = 0; t < 4; ++t) {
+      const int e = tid + NT * t;
+      if (AM == 0) {   // row i, k pair
+        const int i = e >> 4, k = 2 * (e & 15), gi = i0 + i;
+        ra[t] = gi < g.M ? g64_pair<VEC>(A + (int64_t)gi * g.a_i, k0 + k, g.K) : d2{0.0, 0.0};
+      } else {         // column k, i pair
+        const int k = e >> 5, i = 2 * (e & 31), gk = k0 + k;
+        ra[t] = gk < g.K ? g64_pair<VEC>(A + (int64_t)gk * g.a_k, i0 + i, g.M) : d2{0.0, 0.0};
+      }
+      if (BM == 0) {   // row k, j pair
+        const int k = e >> 5, j = 2 * (e & 31), gk = k0 + k;
+        rb[t] = gk < g.K ? g64_pair<VEC>(B + (int64_t)gk * g.b_k, j0 + j, g.N) : d2{0.0, 0.0};
+      } else {         // column j, k pair
+        const int j = e >> 4, k = 2 * (e & 15), gj = j0 + j;
+        rb[t] = gj < g.N ? g64_pair<VEC>(B + (int64_t)gj * g.b_j, k0 + k, g.K) : d2{0.0, 0.0};
+      }
     }
+  };
+  auto store = [&]() {
 #pragma unroll
-    for (int e = tid; e < 64 * BK; e += NT) {
-      int j, k;
-      if (g.b_j == 1) { j = e & 63; k = e >> 6; } else { j = e >> 4; k = e & 15; }
-      const int gj = j0 + j, gk = k0 + k;
-      sB[j * LD + k] = (gj < g.N && gk < g.K) ? B[(int64_t)gk * g.b_k + (int64_t)gj * g.b_j] : 0.0;
+    for (int t = 0; t < 4; ++t) {
+      const int e = tid + NT * t;
+      if (AM == 0) {
+        const int i = e >> 4, k = 2 * (e & 15);
+        sA[i * G64_LD + k] = ra[t][0];
+        sA[i * G64_LD + k + 1] = ra[t][1];
+      } else {
+        const int k = e >> 5, i = 2 * (e & 31);
+        sA[i * G64_LD + k] = ra[t][0];
+        sA[(i + 1) * G64_LD + k] = ra[t][1];
+      }
+      if (BM == 0) {
+        const int k = e >> 5, j = 2 * (e & 31);
+        sB[j * G64_LD + k] = rb[t][0];
+        sB[(j + 1) * G64_LD + k] = rb[t][1];
+      } else {
+        const int j = e >> 4, k = 2 * (e & 15);
+        sB[j * G64_LD + k] = rb[t][0];
+        sB[j * G64_LD + k + 1] = rb[t][1];
+      }
     }
+  };
+
+  load(0);
+  for (int k0 = 0; k0 < g.K; k0 += G64_BK) {
+    store();
     __syncthreads();
+    if (k0 + G64_BK < g.K) load(k0 + G64_BK);   // in flight while this step is multiplied
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
+    for (int kk = 0; kk < G64_BK; kk += 4) {
       double a[2], bb[2];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
-        a[t] = sA[(32 * wr + 16 * t + (lane & 15)) * LD + kk + (lane >> 4)];
-        bb[t] = sB[(32 * wc + 16 * t + (lane & 15)) * LD + kk + (lane >> 4)];
+        a[t] = sA[(32 * wr + 16 * t + (lane & 15)) * G64_LD + kk + (lane >> 4)];
+        bb[t] = sB[(32 * wc + 16 * t + (lane & 15)) * G64_LD + kk + (lane >> 4)];
       }
 #pragma unroll
       for (int ti = 0; ti < 2; ++ti)
@@ -255,8 +311,33 @@ inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b);
 
 hipError_t gemm64(const Gemm64Args& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
+  if (g.K <= 0) return hipErrorInvalidValue;
+  // the contiguous dimension of each operand
+  int am, bm;
+  if (g.a_k == 1) am = 0;
+  else if (g.a_i == 1) am = 1;
+  else return hipErrorInvalidValue;
+  if (g.b_j == 1) bm = 0;
+  else if (g.b_k == 1) bm = 1;
+  else return hipErrorInvalidValue;
+  // 16-byte loads need even strides and 16-byte aligned bases (tile starts are even)
+  auto even = [](int64_t x) { return (x & 1) == 0; };
+  const int64_t a_other = am == 0 ? g.a_i : g.a_k, b_other = bm == 0 ? g.b_k : g.b_j;
+  const bool vec = even(a_other) && even(g.a_b) && even(b_other) && even(g.b_b) &&
+                   (reinterpret_cast<uintptr_t>(g.A) & 15) == 0 &&
+                   (reinterpret_cast<uintptr_t>(g.B) & 15) == 0;
   dim3 grid(cdiv(g.N, 64), cdiv(g.M, 64), g.batch);
-  gemm64_kernel<<<grid, NT, 0, s>>>(g);
+  const int sel = am * 4 + bm * 2 + (vec ? 1 : 0);
+  switch (sel) {
+    case 0: gemm64_kernel<0, 0, false><<<grid, NT, 0, s>>>(g); break;
+    case 1: gemm64_kernel<0, 0, true><<<grid, NT, 0, s>>>(g); break;
+    case 2: gemm64_kernel<0, 1, false><<<grid, NT, 0, s>>>(g); break;
+    case 3: gemm64_kernel<0, 1, true><<<grid, NT, 0, s>>>(g); break;
+    case 4: gemm64_kernel<1, 0, false><<<grid, NT, 0, s>>>(g); break;
+    case 5: gemm64_kernel<1, 0, true><<<grid, NT, 0, s>>>(g); break;
+    case 6: gemm64_kernel<1, 1, false><<<grid, NT, 0, s>>>(g); break;
+    default: gemm64_kernel<1, 1, true><<<grid, NT, 0, s>>>(g); break;
+  }
   return hipGetLastError();
 }
 
