@@ -60,31 +60,34 @@ def timed_steps(plan, Gd, S, steps, torch):
 
 
 def fused_source_hash():
-    """Hash of the sources that make up the fused kernel and of the plan code that
-    chooses its launch (the v split sets how often partial tiles are flushed)."""
+    """Hash of the sources that make up the fused kernel."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("fused.hip", "fused_f16.hip", "panel.hpp", "mfma.hpp", "kernels.hpp", "thcsox.hip"):
+    for f in ("fused.hip", "fused_f16.hip", "panel.hpp", "mfma.hpp", "kernels.hpp"):
         with open(os.path.join(ROOT, "paper_2404_17744_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(precision, workload, symmetry):
+def measured_traffic(precision, workload, symmetry, info):
     """HBM bytes per fused launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
-    summary, or None when there is none or the kernel has changed since."""
+    summary, or None when there is none, the kernel has changed since, or the plan
+    launches it differently (symmetry, v split, partial-tile type)."""
     path = os.path.join(ROOT, "profiles", f"hbm_traffic_fused_{precision}_{workload}.md")
     if not os.path.exists(path):
         return None
+    keys = ("traffic_bytes_per_launch", "source_sha256", "symmetry", "vsplit", "partial_tiles")
     kv = {}
     with open(path) as f:
         for line in f:
             key = line.split(":")[0]
-            if ":" in line and key in ("traffic_bytes_per_launch", "source_sha256", "symmetry"):
+            if ":" in line and key in keys:
                 kv[key] = line.split(":", 1)[1].strip()
     if kv.get("source_sha256") != fused_source_hash() or "traffic_bytes_per_launch" not in kv:
         return None
-    if kv.get("symmetry", "auto") != symmetry:
+    launch = {"symmetry": symmetry, "vsplit": str(info["vsplit"]),
+              "partial_tiles": "fp32" if info["partial_f32"] else "fp64"}
+    if any(kv.get(k) != v for k, v in launch.items()):
         return None
     return float(kv["traffic_bytes_per_launch"])
 
@@ -207,11 +210,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n": s.n, "naux": s.naux, "ntau": m,
                    "beta": beta, "seed": args.seed, "precision": args.precision,
-                   "symmetry": args.symmetry,
+                   "symmetry": args.symmetry, "vsplit": info["vsplit"],
+                   "partial_tiles": "fp32" if info["partial_f32"] else "fp64",
                    "parallelism": "none (one GPU; tau points are independent)"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak,
-                     "traffic": measured_traffic(args.precision, args.workload, args.symmetry),
+                     "traffic": measured_traffic(args.precision, args.workload, args.symmetry,
+                                                 info),
                      "kernel": ("fused_f16_kernel" if args.precision == "fp16x2"
                                 else f"fused_kernel<{args.precision}>"),
                      "avg_launch_ms": fused_avg, "launches": fused_n,

@@ -153,6 +153,10 @@ typedef struct {
   double fused_mac_per_tau;   /* of which in the fused B/C/D kernel: 2 naux^2 n^2 */
   double fused_bytes_per_tau; /* compulsory HBM bytes of the fused kernel per tau:
                                  U and A once each, plus the projected G */
+  int vsplit;                 /* v ranges of the fused kernel (partial D tiles per tau) */
+  int vrange;                 /* longest v range */
+  int partial_f32;            /* 1: partial D tiles are FP32 (each holds one FP32
+                                 partial sum), 0: FP64 */
 } thcsox_plan_info_t;
 int thcsox_plan_info(thcsox_plan_t p, thcsox_plan_info_t* info);
 

@@ -587,6 +587,9 @@ int thcsox_plan_info(thcsox_plan_t p, thcsox_plan_info_t* info) {
   info->fused_mac_per_tau = 2 * na * na * n * n;
   info->fused_bytes_per_tau =
       (double)p->np * p->esize * (2 * na * n * n + 2 * na * n);
+  info->vsplit = p->vsplit;
+  info->vrange = p->vchunk;
+  info->partial_f32 = p->dpart_f32 ? 1 : 0;
   return 0;
 }
 

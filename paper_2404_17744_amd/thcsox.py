@@ -51,7 +51,9 @@ class PlanInfo(ctypes.Structure):
                 ("precision", ctypes.c_int), ("tau_batch", ctypes.c_int),
                 ("bytes", ctypes.c_size_t), ("mac_per_tau", ctypes.c_double),
                 ("fused_mac_per_tau", ctypes.c_double),
-                ("fused_bytes_per_tau", ctypes.c_double)]
+                ("fused_bytes_per_tau", ctypes.c_double),
+                ("vsplit", ctypes.c_int), ("vrange", ctypes.c_int),
+                ("partial_f32", ctypes.c_int)]
 
 
 _lib = None

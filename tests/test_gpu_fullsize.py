@@ -38,10 +38,11 @@ def case(dev):
 def _evaluate(case, precision):
     plan = thcsox.Plan(case["X"], case["V"], case["tau"], case["w"], case["beta"],
                        precision=precision)
+    info = plan.info()
     S = plan.sigma(case["G"])
     E = plan.energy(case["G"], S)
     plan.close()
-    return S, E
+    return S, E, info
 
 
 def _sample_err(S, gold):
@@ -52,7 +53,15 @@ def _sample_err(S, gold):
 @pytest.mark.parametrize("precision", ["fp64", "fp16x2", "bf16x3", "fp32"])
 def test_fullsize_vs_oracle(case, precision):
     print(f"case {NAME} seed 0 {precision}", flush=True)
-    S, E = _evaluate(case, precision)
+    S, E, info = _evaluate(case, precision)
+    # v ranges: 40 ranges of 7 or 8 v, so the reduced-precision kernels write one
+    # FP32 partial tile per workgroup; the FP64 kernel keeps FP64 partial tiles
+    print(f"  vsplit {info['vsplit']} vrange {info['vrange']} partial_f32 {info['partial_f32']}")
+    assert info["vsplit"] % 8 == 0 and info["vsplit"] * info["vrange"] >= 300
+    if precision == "fp64":
+        assert info["partial_f32"] == 0
+    else:
+        assert (info["vsplit"], info["vrange"], info["partial_f32"]) == (40, 8, 1)
     gold = case["gold"]
     dE = E - gold["E_sox"]
     err = _sample_err(S, gold)

@@ -33,6 +33,10 @@ def case(dev):
 def _sigma(case, precision, sym="auto", scale=1.0):
     plan = thcsox.Plan(case["X"], case["V"], case["tau"], case["w"], case["beta"],
                        precision=precision)
+    info = plan.info()
+    # ranges of 8 v would need 144 partial tiles of 5500^2 (17 GB in FP32): the plan
+    # falls back to longer ranges with FP64 partial tiles flushed every 8 v
+    assert info["partial_f32"] == 0 and info["vrange"] > 8
     plan.set_symmetry(sym)
     G = case["G"] * scale if scale != 1.0 else case["G"]
     out = torch.zeros_like(case["G"])
