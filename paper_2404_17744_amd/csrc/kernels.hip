@@ -194,6 +194,16 @@ __global__ void fill_u64_kernel(unsigned long long* p, int64_t n, unsigned long 
 constexpr int DT = 32;          // reduction tile edge
 constexpr int DRP = NT / DT;    // rows per pass
 constexpr int DEL = DT / DRP;   // elements per thread
+__device__ __forceinline__ void add4(const float* p, double* acc) {
+  const float4 v = *reinterpret_cast<const float4*>(p);
+  acc[0] += v.x; acc[1] += v.y; acc[2] += v.z; acc[3] += v.w;
+}
+__device__ __forceinline__ void add4(const double* p, double* acc) {
+  const double2 v0 = *reinterpret_cast<const double2*>(p);
+  const double2 v1 = *reinterpret_cast<const double2*>(p + 2);
+  acc[0] += v0.x; acc[1] += v0.y; acc[2] += v1.x; acc[3] += v1.y;
+}
+
 template <typename T>
 __global__ __launch_bounds__(NT) void dreduce_kernel(DReduceArgs a) {
   __shared__ double t[DT][DT + 1];
@@ -206,24 +216,27 @@ __global__ __launch_bounds__(NT) void dreduce_kernel(DReduceArgs a) {
   const int rb = blockIdx.x / nt, pb = blockIdx.x % nt;
   // symmetric D: the tiles below the diagonal are written by their transposes
   if (sym && rb > pb) return;
-  const int col = threadIdx.x % DT, row0 = threadIdx.x / DT;
-  double acc[DEL];
-#pragma unroll
-  for (int i = 0; i < DEL; ++i) acc[i] = 0.0;
-  const int gc = pb * DT + col;
-  // independent loads of several partial sums in flight per thread
+  // sum over z: thread = (row ar, four consecutive columns ac..ac+3), 16-byte
+  // loads when the row length allows
+  const int ar = threadIdx.x / (DT / 4), ac = 4 * (threadIdx.x % (DT / 4));
+  const int gr = rb * DT + ar, gc = pb * DT + ac;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (gr < a.naux) {
+    const T* D0 = reinterpret_cast<const T*>(a.Dpart) + (int64_t)gr * a.naux + gc;
+    if (a.naux % 4 == 0 && gc + 3 < a.naux) {
 #pragma unroll 4
-  for (int z = 0; z < a.vsplit; ++z) {
-    const T* Dz = reinterpret_cast<const T*>(a.Dpart) + z * nn;
+      for (int z = 0; z < a.vsplit; ++z) add4(D0 + z * nn, acc);
+    } else {
+      for (int z = 0; z < a.vsplit; ++z)
 #pragma unroll
-    for (int i = 0; i < DEL; ++i) {
-      const int gr = rb * DT + row0 + DRP * i;
-      if (gr < a.naux && gc < a.naux) acc[i] += (double)Dz[(int64_t)gr * a.naux + gc];
+        for (int e = 0; e < 4; ++e)
+          if (gc + e < a.naux) acc[e] += (double)D0[z * nn + e];
     }
   }
 #pragma unroll
-  for (int i = 0; i < DEL; ++i) t[row0 + DRP * i][col] = acc[i];
+  for (int e = 0; e < 4; ++e) t[ar][ac + e] = acc[e];
   __syncthreads();
+  const int col = threadIdx.x % DT, row0 = threadIdx.x / DT;
 #pragma unroll
   for (int i = 0; i < DEL; ++i) {
     const int lr = row0 + DRP * i, lc = col;
