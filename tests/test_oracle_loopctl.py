@@ -1,0 +1,137 @@
+"""Pins for the oracle's loop control (chemical-potential search, damping,
+Pulay DIIS), each against something other than the oracle itself:
+
+* with Sigma = 0, N(mu) is the Fermi sum over the one-body levels, so the mu
+  that the search finds (through the Dyson solve and the Chebyshev fit) must
+  match the root of that closed form, found by a bracketing scalar solver;
+  N_el = n_occ - 1/2 puts the root at a steep point of N(mu) (half an electron in
+  the highest occupied level);
+* Pulay DIIS on a linear fixed-point map x = M x + b is a Krylov method: with
+  depth > dim it reaches (1 - M)^-1 b after at most dim + 1 extrapolations;
+* damping keeps the fixed point of a linear map and converges to it.
+"""
+import numpy as np
+import pytest
+from scipy.optimize import brentq
+
+from oracle import loopctl, transforms as tr
+from paper_2404_17744_amd import synth
+
+BETA = 100.0
+
+
+def _fermi_root(eps, nelec):
+    f = lambda mu: np.sum(1.0 / (1.0 + np.exp(np.clip(BETA * (eps - mu), -700, 700)))) - nelec
+    return brentq(f, eps.min() - 1.0, eps.max() + 1.0, xtol=1e-15, rtol=1e-15)
+
+
+@pytest.mark.parametrize("seed", [2, 5])
+def test_find_mu_matches_fermi_closed_form(seed):
+    s = synth.make_system(20, 40, seed=seed)
+    Tm = tr.cheb_to_matsubara(64, 256, BETA)
+    nelec = s.n_occ - 0.5
+    mu, N, evals = loopctl.find_mu(s.F, BETA, np.zeros((64, 20, 20)), Tm, nelec, s.mu,
+                                   tol=1e-10)
+    mu_exact = _fermi_root(s.eps, nelec)
+    assert abs(N - nelec) <= 1e-10
+    # the Chebyshev fit (m = 64) carries ~1e-7 in N, dN/dmu ~ beta/4
+    assert abs(mu - mu_exact) <= 5e-8, (mu, mu_exact)
+    assert evals < 40
+    # a start above the root walks down to the same mu
+    mu2, _, _ = loopctl.find_mu(s.F, BETA, np.zeros((64, 20, 20)), Tm, nelec, s.mu + 1.0,
+                                tol=1e-10)
+    assert abs(mu2 - mu) <= 1e-9
+
+
+def test_find_mu_with_sigma_conserves_electrons():
+    s = synth.make_system(12, 40, seed=3)
+    Tm = tr.cheb_to_matsubara(32, 64, BETA)
+    rng = np.random.default_rng(4)
+    S = 0.05 * rng.standard_normal((32, 12, 12))
+    S = 0.5 * (S + S.transpose(0, 2, 1))
+    nelec = s.n_occ + 0.25
+    G, gam, mu, _ = loopctl.loop_step_mu(s.F, s.mu, BETA, S, Tm, nelec, tol=1e-10)
+    assert abs(np.trace(gam) - nelec) <= 1e-10
+    # N(mu) increases with mu
+    S_iw = tr.tau_to_matsubara(S, Tm)
+    Ns = [loopctl.electron_number(s.F, mu + d, BETA, S_iw, Tm) for d in (-0.05, 0.0, 0.05)]
+    assert Ns[0] < Ns[1] < Ns[2]
+
+
+def _linear_map(d, seed):
+    rng = np.random.default_rng(seed)
+    M = rng.standard_normal((d, d))
+    M *= 0.8 / np.abs(np.linalg.eigvals(M)).max()
+    b = rng.standard_normal(d)
+    return M, b, np.linalg.solve(np.eye(d) - M, b)
+
+
+def test_diis_is_exact_on_a_linear_map():
+    d = 6
+    M, b, x_star = _linear_map(d, 1)
+    ins, outs = [], []
+    x = np.zeros(d)
+    for it in range(d + 1):
+        ins.append(x)
+        outs.append(M @ x + b)
+        x = loopctl.diis_next(ins, outs)
+    assert np.abs(x - x_star).max() <= 1e-10 * np.abs(x_star).max()
+
+
+def test_damping_keeps_the_fixed_point():
+    M, b, x_star = _linear_map(5, 2)
+    assert np.allclose(loopctl.damp(x_star, M @ x_star + b, 0.6), x_star, rtol=0, atol=1e-14)
+    x = np.zeros(5)
+    for _ in range(400):
+        x = loopctl.damp(x, M @ x + b, 0.5)
+    assert np.abs(x - x_star).max() <= 1e-10
+
+
+# Planted slips in copies of the loop-control steps must fail the pins above.
+def _diis_mutant(inputs, outputs, slip):
+    k = len(inputs)
+    res = [o - i for i, o in zip(inputs, outputs)]
+    B = np.zeros((k + 1, k + 1))
+    for i in range(k):
+        for j in range(k):
+            B[i, j] = float(np.dot(res[i].ravel(), res[j].ravel()))
+    B[k, :k] = 1.0
+    B[:k, k] = 1.0
+    rhs = np.zeros(k + 1)
+    rhs[k] = 1.0
+    if slip == "rhs_zero":          # lose the sum-to-one constraint
+        rhs[k] = 0.0
+        rhs[0] = 1.0
+    c = np.linalg.lstsq(B, rhs, rcond=None)[0][:k]
+    base = inputs if slip == "extrapolate_inputs" else outputs
+    out = np.zeros_like(outputs[0])
+    for ci, o in zip(c, base):
+        out += ci * o
+    return out
+
+
+@pytest.mark.parametrize("slip", ["rhs_zero", "extrapolate_inputs"])
+def test_diis_mutants_are_caught(slip):
+    d = 6
+    M, b, x_star = _linear_map(d, 1)
+    ins, outs = [], []
+    x = np.zeros(d)
+    for _ in range(d + 1):
+        ins.append(x)
+        outs.append(M @ x + b)
+        x = _diis_mutant(ins, outs, slip)
+    assert np.abs(x - x_star).max() > 1e-6 * np.abs(x_star).max()
+
+
+def test_density_sign_slip_is_caught():
+    """gamma = +G(beta^-) instead of -G(beta^-): no bracket for a positive N_el."""
+    s = synth.make_system(20, 40, seed=2)
+    Tm = tr.cheb_to_matsubara(64, 256, BETA)
+    S_iw = tr.tau_to_matsubara(np.zeros((64, 20, 20)), Tm)
+
+    def n_wrong(mu):
+        cG = tr.fit_coeffs_from_matsubara(tr.dyson(s.F, mu, S_iw, BETA), Tm)
+        return float(np.trace(np.sum(cG, axis=0)))
+
+    # -N(mu) <= 0 up to the fit noise: no positive electron count can be reached
+    assert max(n_wrong(mu) for mu in (-2.0, s.mu, 2.0)) < 1e-6
