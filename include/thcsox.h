@@ -33,6 +33,7 @@
 #define THCSOX_H
 
 #include <stddef.h>
+#include <stdint.h>
 
 #ifdef __cplusplus
 extern "C" {
@@ -186,10 +187,56 @@ int thcsox_dyson_plan(thcsox_dyson_t* out, int n, int ntau, int n_matsubara, dou
 int thcsox_dyson_step(thcsox_dyson_t d, const double* Sigma_dev, double* G_dev,
                       double* gamma_dev);
 
+/* The same step with the chemical potential chosen so that the electron number
+ * is conserved (size-consistency appendix, "optimized chemical potential";
+ * Sec. "Definitions": the Dyson solution "with the update of the chemical
+ * potential"): mu such that Tr gamma(mu) = nelec to within tol, where gamma(mu)
+ * comes from the Dyson solve at mu (Sigma(i w) is formed once).  Search: from
+ * *mu_io, steps of 0.1 Ha doubled until N(mu) - nelec changes sign, then the
+ * Illinois variant of regula falsi; at most 80 Dyson solves.  On success *mu_io
+ * is the chemical potential used (also kept by the plan for later
+ * thcsox_dyson_step calls), G_dev / gamma_dev are as for thcsox_dyson_step at
+ * that mu, and *evals_out (may be NULL) is the number of Dyson solves.
+ * THCSOX_EINVAL unless 0 <= nelec <= n and tol > 0; THCSOX_ENONFINITE if a
+ * matrix is singular or no bracket / no convergence within the limit.
+ * Synchronises the stream once per Dyson solve. */
+int thcsox_dyson_step_mu(thcsox_dyson_t d, const double* Sigma_dev, double nelec, double tol,
+                         double* mu_io, double* G_dev, double* gamma_dev, int* evals_out);
+
 /* E1 = Tr[F gamma] = sum_pq F_pq gamma_qp in FP64 (host scalar). */
 int thcsox_dyson_onebody(thcsox_dyson_t d, const double* gamma_dev, double* E1_host);
 
 int thcsox_dyson_destroy(thcsox_dyson_t d);
+
+/* ---------------------------------------------------------------------------
+ * Convergence aids for the self-consistency loop on device arrays of doubles
+ * (the paper's loop uses damping and DIIS-type linear combinations of
+ * self-energies; this is Pulay DIIS on the residual Sigma_out - Sigma_in, not
+ * the paper's frequency-dependent commutator variant).
+ * ------------------------------------------------------------------------- */
+
+/* Damping: sigma_io = alpha sigma_io + (1 - alpha) sigma_out, len doubles,
+ * asynchronous on hip_stream (NULL: the default stream). */
+int thcsox_mix(int64_t len, double alpha, const double* sigma_out, double* sigma_io,
+               void* hip_stream);
+
+typedef struct thcsox_diis_s* thcsox_diis_t;
+
+/* History of the last `depth` (Sigma_in, Sigma_out - Sigma_in) pairs, len doubles
+ * each, kept on the device (2 depth len doubles); depth >= 1. */
+int thcsox_diis_create(thcsox_diis_t* out, int64_t len, int depth, void* hip_stream);
+
+/* Adds (sigma_in, sigma_out) to the history (dropping the oldest beyond depth)
+ * and writes sigma_next = sum_i c_i Sigma_out_i with c minimising
+ * |sum_i c_i r_i|^2 under sum_i c_i = 1 (r_i the residuals; dot products in FP64
+ * on the device, the bordered (k+1) x (k+1) system solved on the host).  If that
+ * system is singular the oldest entries are dropped until it is not.
+ * sigma_next may alias sigma_in but not sigma_out.  Synchronises the stream.
+ * *n_used_out (may be NULL): the number of history entries combined. */
+int thcsox_diis_step(thcsox_diis_t d, const double* sigma_in, const double* sigma_out,
+                     double* sigma_next, int* n_used_out);
+
+int thcsox_diis_destroy(thcsox_diis_t d);
 
 /* ---------------------------------------------------------------------------
  * Learned warm start (not part of the paper's method; it only proposes a

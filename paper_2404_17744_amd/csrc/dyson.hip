@@ -431,6 +431,37 @@ __global__ __launch_bounds__(NT) void extract_inv(const double2* __restrict__ Am
   }
 }
 
+// tr[w] = Re Tr G(i w_w), tr[nw + w] = Im Tr G(i w_w): the diagonal of each
+// inverse, read through the column permutation (one workgroup per frequency).
+__global__ __launch_bounds__(NT) void inv_traces(const double2* __restrict__ Am,
+                                                 const int* __restrict__ perm, int n, int nw,
+                                                 double* __restrict__ tr) {
+  __shared__ double r_re[NT], r_im[NT];
+  const int w = blockIdx.x;
+  const double2* A = Am + (int64_t)w * n * n;
+  const int* pm = perm + (int64_t)w * n;
+  double re = 0.0, im = 0.0;
+  for (int i = threadIdx.x; i < n; i += NT) {
+    const double2 v = A[(int64_t)i * n + pm[i]];
+    re += v.x;
+    im += v.y;
+  }
+  r_re[threadIdx.x] = re;
+  r_im[threadIdx.x] = im;
+  __syncthreads();
+  for (int o = NT / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      r_re[threadIdx.x] += r_re[threadIdx.x + o];
+      r_im[threadIdx.x] += r_im[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    tr[w] = r_re[0];
+    tr[nw + w] = r_im[0];
+  }
+}
+
 // out = sum_pq A[p][q] B[q][p] (one workgroup, fixed order).
 __global__ __launch_bounds__(NT) void trace_ab(const double* A, const double* B, int n, double* out) {
   __shared__ double red[NT];
@@ -468,6 +499,8 @@ struct thcsox_dyson_s {
   double* Gout = nullptr;  // [m+1][n n]
   int* flag = nullptr;
   double* scal = nullptr;
+  double* traces = nullptr;   // [2 nw]
+  std::vector<double> gamma_row;   // the gamma row of Wb (host)
   std::vector<void*> allocs;
   ~thcsox_dyson_s() {
     for (void* p : allocs) (void)hipFree(p);
@@ -494,6 +527,89 @@ int dalloc(thcsox_dyson_s* d, T** p, size_t count) {
     if (e_ != hipSuccess)                                                               \
       return dfail(THCSOX_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));  \
   } while (0)
+}  // namespace
+
+namespace {
+
+// Sigma(i w) (real and imaginary rows) = Wf . Sigma(tau)
+int dy_forward(thcsox_dyson_s* d, const double* Sigma_dev) {
+  const int64_t nn = (int64_t)d->n * d->n;
+  Gemm64Args g{};
+  g.M = 2 * d->nw; g.N = (int)nn; g.K = d->m; g.batch = 1; g.alpha = 1.0; g.beta = 0.0;
+  g.A = d->Wf; g.a_i = d->m; g.a_k = 1;
+  g.B = Sigma_dev; g.b_k = nn; g.b_j = 1;
+  g.C = d->Siw; g.c_i = nn; g.c_j = 1; g.cj_in = nn; g.cj_out = 0;
+  DTRY(gemm64(g, d->stream));
+  return 0;
+}
+
+// G(i w) = [(i w + mu) 1 - F - Sigma(i w)]^-1 for every frequency, left in Am
+// (columns permuted by perm); flag set for a singular matrix.
+int dy_invert(thcsox_dyson_s* d, double mu) {
+  const int n = d->n, nw = d->nw;
+  const int64_t nn = (int64_t)n * n;
+  const hipStream_t s = d->stream;
+  const unsigned bx = (unsigned)std::min<int64_t>(64, (nn + NT - 1) / NT);
+  build_a<<<dim3(bx, nw), NT, 0, s>>>(d->Siw, d->F, mu, d->beta, n, nw, d->Am);
+  DTRY(hipGetLastError());
+  DTRY(hipMemsetAsync(d->flag, 0, sizeof(int), s));
+  const int bw = d->panel;
+  for (int k = 0; k < n; k += bw) {
+    const int w = std::min(bw, n - k);
+    gje_panel<<<nw, NT, 0, s>>>(d->Am, n, k, w, d->piv, d->flag);
+    DTRY(hipGetLastError());
+    gje_trail<<<dim3((unsigned)((n + GJ_TCB - 1) / GJ_TCB), nw), NT, 0, s>>>(d->Am, n, k, w);
+    DTRY(hipGetLastError());
+  }
+  gje_perm<<<(unsigned)((nw + NT - 1) / NT), NT, 0, s>>>(d->piv, n, nw, d->perm);
+  DTRY(hipGetLastError());
+  return 0;
+}
+
+// Tr gamma of the inverses in Am: gamma = sum_j Wb[m][j] [Re G; Im G]_j, so only
+// the traces of the G(i w) are needed.  Synchronises the stream.
+int dy_electrons(thcsox_dyson_s* d, double* N) {
+  inv_traces<<<d->nw, NT, 0, d->stream>>>(d->Am, d->perm, d->n, d->nw, d->traces);
+  DTRY(hipGetLastError());
+  std::vector<double> tr((size_t)2 * d->nw);
+  int flag = 0;
+  DTRY(hipMemcpyAsync(tr.data(), d->traces, sizeof(double) * tr.size(), hipMemcpyDeviceToHost,
+                      d->stream));
+  DTRY(hipMemcpyAsync(&flag, d->flag, sizeof(int), hipMemcpyDeviceToHost, d->stream));
+  DTRY(hipStreamSynchronize(d->stream));
+  if (flag) return dfail(THCSOX_ENONFINITE, "singular matrix in the Dyson solve");
+  double acc = 0.0;
+  for (size_t j = 0; j < tr.size(); ++j) acc += d->gamma_row[j] * tr[j];
+  *N = acc;
+  return 0;
+}
+
+// unpack the inverses, fit back to tau: G_dev[m][n][n] and gamma_dev[n][n]
+int dy_backward(thcsox_dyson_s* d, double* G_dev, double* gamma_dev) {
+  const int n = d->n, m = d->m, nw = d->nw;
+  const int64_t nn = (int64_t)n * n;
+  const hipStream_t s = d->stream;
+  const unsigned bx = (unsigned)std::min<int64_t>(64, (nn + NT - 1) / NT);
+  extract_inv<<<dim3(bx, nw), NT, 0, s>>>(d->Am, d->perm, n, nw, d->Gs);
+  DTRY(hipGetLastError());
+  // [G(tau_0) .. G(tau_{m-1}); gamma] = Wb . [Re G(i w); Im G(i w)]
+  Gemm64Args g{};
+  g.M = m + 1; g.N = (int)nn; g.K = 2 * nw; g.batch = 1; g.alpha = 1.0; g.beta = 0.0;
+  g.A = d->Wb; g.a_i = 2 * nw; g.a_k = 1;
+  g.B = d->Gs; g.b_k = nn; g.b_j = 1;
+  g.C = d->Gout; g.c_i = nn; g.c_j = 1; g.cj_in = nn; g.cj_out = 0;
+  DTRY(gemm64(g, s));
+  DTRY(hipMemcpyAsync(G_dev, d->Gout, sizeof(double) * m * nn, hipMemcpyDeviceToDevice, s));
+  if (gamma_dev)
+    DTRY(hipMemcpyAsync(gamma_dev, d->Gout + (int64_t)m * nn, sizeof(double) * nn,
+                        hipMemcpyDeviceToDevice, s));
+  int flag = 0;
+  DTRY(hipMemcpyAsync(&flag, d->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  DTRY(hipStreamSynchronize(s));
+  if (flag) return dfail(THCSOX_ENONFINITE, "singular matrix in the Dyson solve");
+  return 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -535,11 +651,12 @@ int thcsox_dyson_plan(thcsox_dyson_t* out, int n, int ntau, int n_matsubara, dou
       (rc = dalloc(d, &d->perm, (size_t)d->nw * n)) ||
       (rc = dalloc(d, &d->Gs, (size_t)2 * d->nw * nn)) ||
       (rc = dalloc(d, &d->Gout, (size_t)(d->m + 1) * nn)) || (rc = dalloc(d, &d->flag, 1)) ||
-      (rc = dalloc(d, &d->scal, 1))) {
+      (rc = dalloc(d, &d->scal, 1)) || (rc = dalloc(d, &d->traces, (size_t)2 * d->nw))) {
     delete d;
     return rc;
   }
   const Tables& tb = tables_for(d->m, d->nw, beta);
+  d->gamma_row.assign(tb.Wb.begin() + (size_t)d->m * 2 * d->nw, tb.Wb.begin() + (size_t)(d->m + 1) * 2 * d->nw);
   hipError_t e;
   if ((e = hipMemcpyAsync(d->F, F_dev, sizeof(double) * nn, hipMemcpyDeviceToDevice, d->stream)) ||
       (e = hipMemcpyAsync(d->Wf, tb.Wf.data(), sizeof(double) * tb.Wf.size(),
@@ -558,47 +675,72 @@ int thcsox_dyson_step(thcsox_dyson_t d, const double* Sigma_dev, double* G_dev, 
   clear_error();
   if (d == nullptr || Sigma_dev == nullptr || G_dev == nullptr)
     return dfail(THCSOX_EINVAL, "NULL argument");
-  const int n = d->n, m = d->m, nw = d->nw;
-  const int64_t nn = (int64_t)n * n;
-  const hipStream_t s = d->stream;
-  // Sigma(i w) (real and imaginary rows) = Wf . Sigma(tau)
-  Gemm64Args g{};
-  g.M = 2 * nw; g.N = (int)nn; g.K = m; g.batch = 1; g.alpha = 1.0; g.beta = 0.0;
-  g.A = d->Wf; g.a_i = m; g.a_k = 1;
-  g.B = Sigma_dev; g.b_k = nn; g.b_j = 1;
-  g.C = d->Siw; g.c_i = nn; g.c_j = 1; g.cj_in = nn; g.cj_out = 0;
-  DTRY(gemm64(g, s));
-  const unsigned bx = (unsigned)std::min<int64_t>(64, (nn + NT - 1) / NT);
-  build_a<<<dim3(bx, nw), NT, 0, s>>>(d->Siw, d->F, d->mu, d->beta, n, nw, d->Am);
-  DTRY(hipGetLastError());
-  DTRY(hipMemsetAsync(d->flag, 0, sizeof(int), s));
-  const int bw = d->panel;
-  for (int k = 0; k < n; k += bw) {
-    const int w = std::min(bw, n - k);
-    gje_panel<<<nw, NT, 0, s>>>(d->Am, n, k, w, d->piv, d->flag);
-    DTRY(hipGetLastError());
-    gje_trail<<<dim3((unsigned)((n + GJ_TCB - 1) / GJ_TCB), nw), NT, 0, s>>>(d->Am, n, k, w);
-    DTRY(hipGetLastError());
+  int rc;
+  if ((rc = dy_forward(d, Sigma_dev)) || (rc = dy_invert(d, d->mu))) return rc;
+  return dy_backward(d, G_dev, gamma_dev);
+}
+
+int thcsox_dyson_step_mu(thcsox_dyson_t d, const double* Sigma_dev, double nelec, double tol,
+                         double* mu_io, double* G_dev, double* gamma_dev, int* evals_out) {
+  clear_error();
+  if (d == nullptr || Sigma_dev == nullptr || G_dev == nullptr || mu_io == nullptr)
+    return dfail(THCSOX_EINVAL, "NULL argument");
+  if (!(nelec >= 0.0) || !(nelec <= d->n) || !(tol > 0.0) || !std::isfinite(*mu_io))
+    return dfail(THCSOX_EINVAL, "need 0 <= nelec <= n, tol > 0 and a finite starting mu");
+  int rc;
+  if ((rc = dy_forward(d, Sigma_dev))) return rc;
+  // f(mu) = Tr gamma(mu) - nelec, one Dyson solve per evaluation; the last
+  // evaluated mu is the answer, so its inverses are the ones left in Am
+  int evals = 0;
+  auto f = [&](double mu, double* val) -> int {
+    int r;
+    if ((r = dy_invert(d, mu)) || (r = dy_electrons(d, val))) return r;
+    *val -= nelec;
+    ++evals;
+    return 0;
+  };
+  constexpr int MAX_EVAL = 80;
+  constexpr double STEP = 0.1;   // first bracketing step (Ha), doubled while the sign holds
+  double a = *mu_io, fa, b, fb, mu = a;
+  bool done = false;
+  if ((rc = f(a, &fa))) return rc;
+  if (std::fabs(fa) <= tol) done = true;
+  if (!done) {
+    double step = fa > 0 ? -STEP : STEP;
+    b = a + step;
+    if ((rc = f(b, &fb))) return rc;
+    while (fa * fb > 0 && evals < MAX_EVAL) {
+      a = b;
+      fa = fb;
+      step *= 2.0;
+      b = a + step;
+      if ((rc = f(b, &fb))) return rc;
+    }
+    mu = b;
+    if (std::fabs(fb) <= tol) done = true;
+    else if (fa * fb > 0) return dfail(THCSOX_ENONFINITE, "no bracket for the chemical potential");
   }
-  gje_perm<<<(unsigned)((nw + NT - 1) / NT), NT, 0, s>>>(d->piv, n, nw, d->perm);
-  DTRY(hipGetLastError());
-  extract_inv<<<dim3(bx, nw), NT, 0, s>>>(d->Am, d->perm, n, nw, d->Gs);
-  DTRY(hipGetLastError());
-  // [G(tau_0) .. G(tau_{m-1}); gamma] = Wb . [Re G(i w); Im G(i w)]
-  g.M = m + 1; g.N = (int)nn; g.K = 2 * nw;
-  g.A = d->Wb; g.a_i = 2 * nw; g.a_k = 1;
-  g.B = d->Gs; g.b_k = nn; g.b_j = 1;
-  g.C = d->Gout;
-  DTRY(gemm64(g, s));
-  DTRY(hipMemcpyAsync(G_dev, d->Gout, sizeof(double) * m * nn, hipMemcpyDeviceToDevice, s));
-  if (gamma_dev)
-    DTRY(hipMemcpyAsync(gamma_dev, d->Gout + (int64_t)m * nn, sizeof(double) * nn,
-                        hipMemcpyDeviceToDevice, s));
-  int flag = 0;
-  DTRY(hipMemcpyAsync(&flag, d->flag, sizeof(int), hipMemcpyDeviceToHost, s));
-  DTRY(hipStreamSynchronize(s));
-  if (flag) return dfail(THCSOX_ENONFINITE, "singular matrix in the Dyson solve");
-  return 0;
+  // Illinois variant of regula falsi on the bracket (a, b)
+  while (!done) {
+    if (evals >= MAX_EVAL) return dfail(THCSOX_ENONFINITE, "chemical potential search did not converge");
+    const double c = (a * fb - b * fa) / (fb - fa);
+    double fc;
+    if ((rc = f(c, &fc))) return rc;
+    mu = c;
+    if (std::fabs(fc) <= tol || std::fabs(b - a) <= 1e-14 * (1.0 + std::fabs(c))) break;
+    if (fc * fb < 0) {
+      a = b;
+      fa = fb;
+    } else {
+      fa *= 0.5;
+    }
+    b = c;
+    fb = fc;
+  }
+  d->mu = mu;
+  *mu_io = mu;
+  if (evals_out) *evals_out = evals;
+  return dy_backward(d, G_dev, gamma_dev);
 }
 
 int thcsox_dyson_onebody(thcsox_dyson_t d, const double* gamma_dev, double* E1_host) {

@@ -35,7 +35,8 @@ EXPORTS = ("thcsox_plan", "thcsox_sigma_sox", "thcsox_energy", "thcsox_destroy",
            "thcsox_mlp_forward", "thcsox_mlp_gradients", "thcsox_mlp_train_step",
            "thcsox_mlp_params", "thcsox_mlp_destroy", "thcsox_pair_scale",
            "thcsox_pair_gather", "thcsox_pair_scatter", "thcsox_set_symmetry",
-           "thcsox_symmetric_flags")
+           "thcsox_symmetric_flags", "thcsox_dyson_step_mu", "thcsox_mix",
+           "thcsox_diis_create", "thcsox_diis_step", "thcsox_diis_destroy")
 SYMMETRY = {"auto": 0, "off": 1}
 STAGES = ("project", "a_stage", "fused", "back")
 
@@ -98,6 +99,17 @@ def lib() -> ctypes.CDLL:
         L.thcsox_dyson_onebody.restype = i
         L.thcsox_dyson_destroy.argtypes = [vp]
         L.thcsox_dyson_destroy.restype = i
+        L.thcsox_dyson_step_mu.argtypes = [vp, vp, d, d, ctypes.POINTER(d), vp, vp,
+                                           ctypes.POINTER(i)]
+        L.thcsox_dyson_step_mu.restype = i
+        L.thcsox_mix.argtypes = [ctypes.c_int64, d, vp, vp, vp]
+        L.thcsox_mix.restype = i
+        L.thcsox_diis_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int64, i, vp]
+        L.thcsox_diis_create.restype = i
+        L.thcsox_diis_step.argtypes = [vp, vp, vp, vp, ctypes.POINTER(i)]
+        L.thcsox_diis_step.restype = i
+        L.thcsox_diis_destroy.argtypes = [vp]
+        L.thcsox_diis_destroy.restype = i
         fp = ctypes.c_float
         L.thcsox_mlp_create.argtypes = [ctypes.POINTER(vp), i, i, i, vp, vp]
         L.thcsox_mlp_create.restype = i
@@ -213,6 +225,36 @@ def thcsox_dyson_destroy(d) -> None:
     _check(lib().thcsox_dyson_destroy(d))
 
 
+def thcsox_dyson_step_mu(d, Sigma_dev: int, nelec: float, tol: float, mu: float, G_dev: int,
+                         gamma_dev: int | None):
+    """Returns (mu, number of Dyson solves)."""
+    m = ctypes.c_double(mu)
+    ev = ctypes.c_int(0)
+    _check(lib().thcsox_dyson_step_mu(d, Sigma_dev, nelec, tol, ctypes.byref(m), G_dev,
+                                      gamma_dev, ctypes.byref(ev)))
+    return m.value, ev.value
+
+
+def thcsox_mix(length: int, alpha: float, sigma_out: int, sigma_io: int, stream: int) -> None:
+    _check(lib().thcsox_mix(length, alpha, sigma_out, sigma_io, stream))
+
+
+def thcsox_diis_create(length: int, depth: int, stream: int):
+    h = ctypes.c_void_p()
+    _check(lib().thcsox_diis_create(ctypes.byref(h), length, depth, stream))
+    return h
+
+
+def thcsox_diis_step(h, sigma_in: int, sigma_out: int, sigma_next: int) -> int:
+    used = ctypes.c_int(0)
+    _check(lib().thcsox_diis_step(h, sigma_in, sigma_out, sigma_next, ctypes.byref(used)))
+    return used.value
+
+
+def thcsox_diis_destroy(h) -> None:
+    _check(lib().thcsox_diis_destroy(h))
+
+
 class Dyson:
     """Owns one Dyson/transform plan; tensors are torch float64 device tensors."""
 
@@ -234,6 +276,19 @@ class Dyson:
             gamma_out = torch.empty((self.n, self.n), dtype=torch.float64, device=self.device)
         thcsox_dyson_step(self.handle, Sigma.data_ptr(), G_out.data_ptr(), gamma_out.data_ptr())
         return G_out, gamma_out
+
+    def step_mu(self, Sigma, nelec: float, mu: float, tol: float = 1e-8, G_out=None,
+                gamma_out=None):
+        """Dyson step with the chemical potential that conserves nelec electrons:
+        returns (G, gamma, mu, number of Dyson solves)."""
+        import torch
+        if G_out is None:
+            G_out = torch.empty((self.ntau, self.n, self.n), dtype=torch.float64, device=self.device)
+        if gamma_out is None:
+            gamma_out = torch.empty((self.n, self.n), dtype=torch.float64, device=self.device)
+        mu, ev = thcsox_dyson_step_mu(self.handle, Sigma.data_ptr(), float(nelec), float(tol),
+                                      float(mu), G_out.data_ptr(), gamma_out.data_ptr())
+        return G_out, gamma_out, mu, ev
 
     def onebody(self, gamma) -> float:
         return thcsox_dyson_onebody(self.handle, gamma.data_ptr())
@@ -392,6 +447,39 @@ class Plan:
     def close(self) -> None:
         if getattr(self, "handle", None):
             thcsox_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mix(alpha: float, sigma_out, sigma_io, stream=None) -> None:
+    """sigma_io = alpha sigma_io + (1 - alpha) sigma_out (float64 device tensors)."""
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream(sigma_io.device)
+    thcsox_mix(sigma_io.numel(), float(alpha), sigma_out.data_ptr(), sigma_io.data_ptr(),
+               st.cuda_stream)
+
+
+class Diis:
+    """Pulay DIIS over (Sigma_in, Sigma_out) pairs held on the device."""
+
+    def __init__(self, like, depth: int = 6, stream=None):
+        import torch
+        self.stream = stream if stream is not None else torch.cuda.current_stream(like.device)
+        self.handle = thcsox_diis_create(like.numel(), depth, self.stream.cuda_stream)
+
+    def step(self, sigma_in, sigma_out, sigma_next) -> int:
+        """Writes the extrapolated input into sigma_next; returns the entries used."""
+        return thcsox_diis_step(self.handle, sigma_in.data_ptr(), sigma_out.data_ptr(),
+                                sigma_next.data_ptr())
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            thcsox_diis_destroy(self.handle)
             self.handle = None
 
     def __del__(self):
