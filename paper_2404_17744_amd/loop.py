@@ -1,19 +1,25 @@
-"""SOX-only self-consistency loop on one GPU (fixed F and mu):
+"""SOX-only self-consistency loop on one GPU (fixed F):
 
-    G0 (independent particles) -> Sigma^SOX[G] -> Dyson on the Matsubara grid -> G -> ...
+    G0 (independent particles) -> Sigma^SOX[G] -> (damping or DIIS on Sigma)
+       -> Dyson on the Matsubara grid (optionally with the chemical potential
+          that conserves the electron number) -> G -> ...
 
 Every step runs in libthcsox (SOX evaluation, energy, tau -> i omega transform,
-batched Dyson inversion, least-squares fit back to tau, one-body energy);
-torch only provides device buffers.  Prints one JSON line per iteration and a
-summary line, e.g. for the paper-scale one-GPU share:
+batched Dyson inversion, chemical-potential search, least-squares fit back to
+tau, one-body energy, damping, DIIS); torch only provides device buffers.
+Prints one JSON line per iteration and a summary line, e.g. for the paper-scale
+one-GPU share:
 
     python -m paper_2404_17744_amd.loop --workload sox_n1100_naux5500_ntau100 --iters 10
+    python -m paper_2404_17744_amd.loop --workload sox_n300_naux1800_ntau100 --diis 6 --mu-search
 """
 from __future__ import annotations
 
 import argparse
 import json
 import time
+
+import numpy as np
 
 from . import synth, thcsox
 
@@ -27,6 +33,14 @@ def main() -> None:
     ap.add_argument("--precision", default="fp16x2")
     ap.add_argument("--matsubara", type=int, default=256)
     ap.add_argument("--tol", type=float, default=1e-7)
+    ap.add_argument("--damping", type=float, default=0.0,
+                    help="Sigma_in <- d Sigma_in + (1 - d) Sigma_out (0: none)")
+    ap.add_argument("--diis", type=int, default=0, help="Pulay DIIS depth on Sigma (0: none)")
+    ap.add_argument("--mu-search", action="store_true",
+                    help="chemical potential that keeps n_occ electrons at every Dyson step")
+    # above the transforms' accuracy in N (~1e-7 at 64 Chebyshev points, beta = 100):
+    # in a gap N(mu) is flat to that level, and a tighter target drives mu to a gap edge
+    ap.add_argument("--mu-tol", type=float, default=1e-5)
     a = ap.parse_args()
 
     import torch
@@ -43,20 +57,38 @@ def main() -> None:
     dyson = thcsox.Dyson(torch.from_numpy(s.F).to(dev), s.mu, tau, beta, a.matsubara)
     torch.cuda.synchronize()
     t_plan = time.time() - t0
-    S = torch.zeros_like(G)
+    S_out = torch.zeros_like(G)    # Sigma^SOX of the current G
+    S_in = torch.zeros_like(G)     # the Sigma fed to the Dyson step
+    S_next = torch.empty_like(G)
+    diis = thcsox.Diis(S_out, depth=a.diis) if a.diis > 0 else None
+    mu = s.mu
     E_prev, iters = None, []
     for it in range(a.iters):
         torch.cuda.synchronize()
         t1 = time.time()
-        plan.sigma(G, out=S)
-        E_sox = plan.energy(G, S)
+        plan.sigma(G, out=S_out)
+        E_sox = plan.energy(G, S_out)
         t2 = time.time()
-        G, gamma = dyson.step(S, G_out=G)
+        used = 1
+        if it == 0 or (diis is None and a.damping == 0.0):
+            S_in.copy_(S_out)
+        elif diis is not None:
+            used = diis.step(S_in, S_out, S_next)
+            S_in, S_next = S_next, S_in
+        else:
+            thcsox.mix(a.damping, S_out, S_in)
+        solves = 1
+        if a.mu_search:
+            G, gamma, mu, solves = dyson.step_mu(S_in, s.n_occ, mu, tol=a.mu_tol, G_out=G)
+        else:
+            G, gamma = dyson.step(S_in, G_out=G)
         E1 = dyson.onebody(gamma)
         t3 = time.time()
+        nelec = float(np.trace(gamma.cpu().numpy()))   # host diagnostic
         E = E1 + E_sox
         row = {"iter": it + 1, "E_total": E, "E_sox": E_sox, "E_onebody": E1,
                "dE": None if E_prev is None else E - E_prev,
+               "mu": mu, "nelec": nelec, "dyson_solves": solves, "diis_used": used,
                "sox_s": t2 - t1, "dyson_s": t3 - t2,
                "symmetric_tau_points": int(plan.symmetric_flags().sum()),
                "tau_points_per_s": len(tau) / (t2 - t1)}
@@ -65,11 +97,16 @@ def main() -> None:
         if E_prev is not None and abs(E - E_prev) < a.tol:
             break
         E_prev = E
+    if diis is not None:
+        diis.close()
     plan.close()
     dyson.close()
     sox = [r["sox_s"] for r in iters]
     print(json.dumps({"workload": a.workload, "n": s.n, "naux": s.naux, "ntau": len(tau),
-                      "lam": a.lam, "precision": a.precision, "iterations": len(iters),
+                      "lam": a.lam, "precision": a.precision, "damping": a.damping,
+                      "diis": a.diis, "mu_search": a.mu_search, "iterations": len(iters),
+                      "converged": len(iters) > 1 and abs(iters[-1]["dE"]) < a.tol,
+                      "E_total": iters[-1]["E_total"],
                       "generate_s": t_gen, "plan_s": t_plan,
                       "sox_s_mean": sum(sox) / len(sox),
                       "dyson_s_mean": sum(r["dyson_s"] for r in iters) / len(iters),
