@@ -130,6 +130,23 @@ int thcsox_symmetric_flags(thcsox_plan_t p, int* flags_host);
 int thcsox_energy(thcsox_plan_t p, const double* G_dev, const double* Sigma_dev,
                   double* E_host);
 
+/* The second-order direct (bubble) self-energy of GF2 on the same THC data
+ * (Sec. "Self-energy functionals": full scGF2 = direct + SOX terms; the paper
+ * treats this term as in the THC-GW work it cites and prints no formula).
+ * Definition, in the spin-orbital convention of the SOX term and with G(-tau)
+ * read as G(beta - tau) = G[ntau-1-k]:
+ *     Sigma^dir_tr = + sum_{pqsuvw} (tu|vw) (pr|qs) G_up G_wq G_sv(-tau)
+ * computed in THC form in FP64 for every plan precision:
+ *     Gt = X^T G[k] X, Gbt = X^T G[ntau-1-k] X, Pi_QS = Gt_QS Gbt_SQ,
+ *     W = V Pi V, Sigma^dir[k] = X (W o Gt) X^T      (2 naux^3 + O(naux^2 n) per tau)
+ * for k in [k_begin, k_end).  G_dev, Sigma_dev: [ntau][n][n] device arrays (Sigma
+ * must not alias G).  The first call allocates 3 x 8 naux^2 bytes per tau point
+ * of its batch (about 1 GB at most; counted against workspace_limit).
+ * Asynchronous on the plan's stream.  Add it to the SOX term for scGF2; the
+ * energy of either term (or of their sum) is thcsox_energy of that Sigma. */
+int thcsox_sigma_direct(thcsox_plan_t p, const double* G_dev, double* Sigma_dev, int k_begin,
+                        int k_end);
+
 /* Back-projection alone (the last equation of the THC sequence):
  *     Sigma_tr = sum_PR X_tR Sig_RP X_rP       for k in [k_begin, k_end)
  *   Sigma_thc_dev[ntau][naux][naux] (read), Sigma_dev[ntau][n][n] (written).

@@ -12,6 +12,7 @@
 
 #include "../../include/thcsox.h"
 #include "error.hpp"
+#include "direct.hpp"
 #include "kernels.hpp"
 #include "mfma.hpp"
 
@@ -81,6 +82,9 @@ struct thcsox_plan_s {
   size_t bytes = 0, limit = 0;
 
   double* X = nullptr;      // [n][naux]
+  double* V = nullptr;      // [naux][naux] (the direct term)
+  double* dbuf = nullptr;   // direct term: 3 x [tbd][naux][naux], allocated on first use
+  int tbd = 0;              // tau points per direct-term batch
   double* w = nullptr;      // [m]
   void* U = nullptr;        // planes of [naux][n][ldk]
   int64_t u_plane = 0;
@@ -344,6 +348,48 @@ int sigma_batch(thcsox_plan_s* p, const double* G, double* Sigma, double* Sthc_o
   return 0;
 }
 
+// GF2 direct (bubble) term for tau points k0 <= k < k1 (k1 - k0 <= tbd), FP64:
+//   Gt = X^T G[k] X, Gbt = X^T G[m-1-k] X, Pi = Gt o Gbt^T, W = V Pi V,
+//   Sigma[k] = X (W o Gt) X^T.
+int direct_batch(thcsox_plan_s* p, const double* G, double* Sigma, int k0, int k1) {
+  const int n = p->n, naux = p->naux, m = p->m, nb = k1 - k0;
+  const hipStream_t s = p->stream;
+  const int64_t nn = (int64_t)n * n, aa = (int64_t)naux * naux;
+  double* bufA = p->dbuf;                          // Gt
+  double* bufB = p->dbuf + (int64_t)p->tbd * aa;   // Gbt, then V Pi
+  double* bufC = bufB + (int64_t)p->tbd * aa;      // Pi, then W, then W o Gt
+  // T = X^T G for the batch (into Gt64, [nb][naux][n]) and Gt = T X; the same
+  // for the mirrored points, walking G backwards
+  for (int mirror = 0; mirror < 2; ++mirror) {
+    Gemm64Args g{};
+    g.M = naux; g.N = n; g.K = n; g.batch = nb; g.alpha = 1.0; g.beta = 0.0;
+    g.A = p->X; g.a_i = 1; g.a_k = naux; g.a_b = 0;
+    g.B = mirror ? G + (int64_t)(m - 1 - k0) * nn : G + (int64_t)k0 * nn;
+    g.b_k = n; g.b_j = 1; g.b_b = mirror ? -nn : nn;
+    g.C = p->Gt64; g.c_i = n; g.c_j = 1; g.cj_in = n; g.cj_out = 0; g.c_b = (int64_t)naux * n;
+    HIP_TRY(gemm64(g, s));
+    g.M = naux; g.N = naux; g.K = n;
+    g.A = p->Gt64; g.a_i = n; g.a_k = 1; g.a_b = (int64_t)naux * n;
+    g.B = p->X; g.b_k = naux; g.b_j = 1; g.b_b = 0;
+    g.C = mirror ? bufB : bufA; g.c_i = naux; g.c_j = 1; g.cj_in = naux; g.cj_out = 0; g.c_b = aa;
+    HIP_TRY(gemm64(g, s));
+  }
+  HIP_TRY(bubble_pi(bufA, bufB, bufC, naux, nb, s));
+  // W = (V Pi) V
+  Gemm64Args g{};
+  g.M = naux; g.N = naux; g.K = naux; g.batch = nb; g.alpha = 1.0; g.beta = 0.0;
+  g.A = p->V; g.a_i = naux; g.a_k = 1; g.a_b = 0;
+  g.B = bufC; g.b_k = naux; g.b_j = 1; g.b_b = aa;
+  g.C = bufB; g.c_i = naux; g.c_j = 1; g.cj_in = naux; g.cj_out = 0; g.c_b = aa;
+  HIP_TRY(gemm64(g, s));
+  g.A = bufB; g.a_i = naux; g.a_k = 1; g.a_b = aa;
+  g.B = p->V; g.b_k = naux; g.b_j = 1; g.b_b = 0;
+  g.C = bufC;
+  HIP_TRY(gemm64(g, s));
+  HIP_TRY(hadamard64(bufC, bufA, bufC, (int64_t)nb * aa, s));
+  return backproject_batch(p, bufC, aa, Sigma + (int64_t)k0 * nn, nb);
+}
+
 }  // namespace
 
 extern "C" {
@@ -505,6 +551,10 @@ int thcsox_plan(thcsox_plan_t* out, int n, int naux, int ntau, double beta,
     return hip_bail(e, "zero flags");
   if (p->A32 && (e = hipMemsetAsync(p->A32, 0, sizeof(float) * (size_t)p->a_plane, s)))
     return hip_bail(e, "zero A32");
+  if ((rc = p->alloc(&p->V, (size_t)naux * naux))) return bail(rc);
+  if ((e = hipMemcpyAsync(p->V, V_dev, sizeof(double) * (size_t)naux * naux,
+                          hipMemcpyDeviceToDevice, s)))
+    return hip_bail(e, "copy V");
   if ((rc = build_u(p, V_dev))) return bail(rc);
   if ((e = hipStreamSynchronize(s))) return hip_bail(e, "plan synchronise");
   *out = p;
@@ -550,6 +600,29 @@ int thcsox_backproject(thcsox_plan_t p, const double* Sigma_thc_dev, double* Sig
   for (int k = k_begin; k < k_end; k += p->tb)
     TRY(backproject_batch(p, Sigma_thc_dev + k * aa, aa, Sigma_dev + k * nn,
                           std::min(k_end, k + p->tb) - k));
+  return 0;
+}
+
+int thcsox_sigma_direct(thcsox_plan_t p, const double* G_dev, double* Sigma_dev, int k_begin,
+                        int k_end) {
+  clear_error();
+  if (p == nullptr) return fail(THCSOX_EINVAL, "plan is NULL");
+  if (k_begin < 0 || k_end > p->m || k_begin >= k_end)
+    return fail(THCSOX_EINVAL, "need 0 <= k_begin < k_end <= ntau");
+  TRY(check_dev(G_dev, "G_dev"));
+  TRY(check_dev(Sigma_dev, "Sigma_dev"));
+  const size_t gbytes = sizeof(double) * (size_t)p->m * p->n * p->n;
+  const char* g0 = reinterpret_cast<const char*>(G_dev);
+  const char* s0 = reinterpret_cast<const char*>(Sigma_dev);
+  if (s0 < g0 + gbytes && g0 < s0 + gbytes) return fail(THCSOX_EINVAL, "Sigma aliases G");
+  if (p->dbuf == nullptr) {
+    // three naux^2 blocks per tau point, about 1 GB per batch at most
+    const double per_tau = 3.0 * 8.0 * (double)p->naux * p->naux;
+    p->tbd = (int)std::max(1.0, std::min((double)p->tb, std::floor(1.0e9 / per_tau)));
+    TRY(p->alloc(&p->dbuf, (size_t)3 * p->tbd * p->naux * p->naux));
+  }
+  for (int k = k_begin; k < k_end; k += p->tbd)
+    TRY(direct_batch(p, G_dev, Sigma_dev, k, std::min(k_end, k + p->tbd)));
   return 0;
 }
 

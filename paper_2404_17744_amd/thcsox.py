@@ -36,7 +36,8 @@ EXPORTS = ("thcsox_plan", "thcsox_sigma_sox", "thcsox_energy", "thcsox_destroy",
            "thcsox_mlp_params", "thcsox_mlp_destroy", "thcsox_pair_scale",
            "thcsox_pair_gather", "thcsox_pair_scatter", "thcsox_set_symmetry",
            "thcsox_symmetric_flags", "thcsox_dyson_step_mu", "thcsox_mix",
-           "thcsox_diis_create", "thcsox_diis_step", "thcsox_diis_destroy")
+           "thcsox_diis_create", "thcsox_diis_step", "thcsox_diis_destroy",
+           "thcsox_sigma_direct")
 SYMMETRY = {"auto": 0, "off": 1}
 STAGES = ("project", "a_stage", "fused", "back")
 
@@ -102,6 +103,8 @@ def lib() -> ctypes.CDLL:
         L.thcsox_dyson_step_mu.argtypes = [vp, vp, d, d, ctypes.POINTER(d), vp, vp,
                                            ctypes.POINTER(i)]
         L.thcsox_dyson_step_mu.restype = i
+        L.thcsox_sigma_direct.argtypes = [vp, vp, vp, i, i]
+        L.thcsox_sigma_direct.restype = i
         L.thcsox_mix.argtypes = [ctypes.c_int64, d, vp, vp, vp]
         L.thcsox_mix.restype = i
         L.thcsox_diis_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int64, i, vp]
@@ -414,6 +417,15 @@ class Plan:
         thcsox_sigma_sox(self.handle, G.data_ptr(), out.data_ptr(),
                          out_thc.data_ptr() if thc else None, k_begin, k_end)
         return (out, out_thc) if thc else out
+
+    def sigma_direct(self, G, k_begin: int = 0, k_end: int | None = None, out=None):
+        """Second-order direct (bubble) self-energy, FP64, for k in [k_begin, k_end)."""
+        import torch
+        k_end = self.ntau if k_end is None else k_end
+        if out is None:
+            out = torch.zeros((self.ntau, self.n, self.n), dtype=torch.float64, device=self.device)
+        _check(lib().thcsox_sigma_direct(self.handle, G.data_ptr(), out.data_ptr(), k_begin, k_end))
+        return out
 
     def energy(self, G, Sigma) -> float:
         return thcsox_energy(self.handle, G.data_ptr(), Sigma.data_ptr())
