@@ -128,6 +128,8 @@ def main():
     ap.add_argument("--cpu-taus", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--symmetry", default="auto", choices=["auto", "off"])
+    ap.add_argument("--no-direct", action="store_true",
+                    help="skip the GF2 direct-term measurement beside the SOX one")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -158,6 +160,25 @@ def main():
     ms, E_mixed, st = timed_steps(plan, Gd, S, args.steps, torch)
     S_mixed = S.clone()
     fused_flop, n_sym = fused_flop_per_launch(plan, info, m)
+    # the GF2 direct (bubble) term on the same plan (FP64), one full evaluation
+    direct = None
+    if not args.no_direct:
+        Sd = torch.zeros_like(Gd)
+        plan.sigma_direct(Gd, out=Sd)   # warm-up; allocates the term's buffers
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(plan.stream)
+        plan.sigma_direct(Gd, out=Sd)
+        E_dir = plan.energy(Gd, Sd)
+        e1.record(plan.stream)
+        torch.cuda.synchronize()
+        ms_d = e0.elapsed_time(e1)
+        na, nn_ = float(s.naux), float(s.n)
+        mac_d = 2 * na ** 3 + 3 * na * na * nn_ + 3 * na * nn_ * nn_
+        direct = {"tau_points_per_s": m / (ms_d * 1e-3), "ms_per_step": ms_d, "E_dir": E_dir,
+                  "mac_per_tau": mac_d, "tflops": 2 * mac_d * m / (ms_d * 1e-3) / 1e12,
+                  "E_gf2_second_order": E_dir + E_mixed}
     plan.close()
 
     fused_ms, fused_n = st["fused"]
@@ -229,6 +250,7 @@ def main():
         "plan_s": plan_s,
         "fp64_path": fp64,
         "speedup_vs_fp64_path": (m / (ms * 1e-3)) / fp64["tau_points_per_s"] if fp64 else None,
+        "gf2_direct_term": direct,
         "accuracy": accuracy,
     }
     if not args.no_cpu_baseline:
