@@ -140,12 +140,14 @@ int thcsox_energy(thcsox_plan_t p, const double* G_dev, const double* Sigma_dev,
  *     Gt = X^T G[k] X, Gbt = X^T G[ntau-1-k] X, Pi_QS = Gt_QS Gbt_SQ,
  *     W = V Pi V, Sigma^dir[k] = X (W o Gt) X^T      (2 naux^3 + O(naux^2 n) per tau)
  * for k in [k_begin, k_end).  G_dev, Sigma_dev: [ntau][n][n] device arrays (Sigma
- * must not alias G).  The first call allocates 3 x 8 naux^2 bytes per tau point
+ * must not alias G).  accumulate = 0 writes Sigma[k]; accumulate = 1 adds to it
+ * (e.g. onto the SOX term from thcsox_sigma_sox, giving the full second-order
+ * scGF2 self-energy).  The first call allocates 3 x 8 naux^2 bytes per tau point
  * of its batch (about 1 GB at most; counted against workspace_limit).
- * Asynchronous on the plan's stream.  Add it to the SOX term for scGF2; the
- * energy of either term (or of their sum) is thcsox_energy of that Sigma. */
+ * Asynchronous on the plan's stream.  The energy of either term (or of their
+ * sum) is thcsox_energy of that Sigma. */
 int thcsox_sigma_direct(thcsox_plan_t p, const double* G_dev, double* Sigma_dev, int k_begin,
-                        int k_end);
+                        int k_end, int accumulate);
 
 /* Back-projection alone (the last equation of the THC sequence):
  *     Sigma_tr = sum_PR X_tR Sig_RP X_rP       for k in [k_begin, k_end)

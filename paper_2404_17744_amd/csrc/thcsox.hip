@@ -230,9 +230,9 @@ int build_u(thcsox_plan_s* p, const double* V) {
 }
 
 // Sigma[b] = X Sig_thc[b] X^T for nb tau points at once (FP64 matrix cores);
-// Sig_thc[b] = St + b * st_stride, Sigma[b] = Sig + b * n * n.
+// Sig_thc[b] = St + b * st_stride, Sigma[b] = Sig + b * n * n (beta_out = 1: Sigma[b] +=).
 int backproject_batch(thcsox_plan_s* p, const double* St, int64_t st_stride, double* Sig,
-                      int nb) {
+                      int nb, double beta_out = 0.0) {
   const int n = p->n, naux = p->naux;
   const hipStream_t s = p->stream;
   Gemm64Args b{};
@@ -245,6 +245,7 @@ int backproject_batch(thcsox_plan_s* p, const double* St, int64_t st_stride, dou
   b.A = p->T1; b.a_i = naux; b.a_k = 1; b.a_b = (int64_t)n * naux;
   b.B = p->X; b.b_k = 1; b.b_j = naux; b.b_b = 0;
   b.C = Sig; b.c_i = n; b.c_j = 1; b.cj_in = n; b.cj_out = 0; b.c_b = (int64_t)n * n;
+  b.beta = beta_out;   // 1: add to what Sig holds
   HIP_TRY(gemm64(b, s));
   return 0;
 }
@@ -351,7 +352,8 @@ int sigma_batch(thcsox_plan_s* p, const double* G, double* Sigma, double* Sthc_o
 // GF2 direct (bubble) term for tau points k0 <= k < k1 (k1 - k0 <= tbd), FP64:
 //   Gt = X^T G[k] X, Gbt = X^T G[m-1-k] X, Pi = Gt o Gbt^T, W = V Pi V,
 //   Sigma[k] = X (W o Gt) X^T.
-int direct_batch(thcsox_plan_s* p, const double* G, double* Sigma, int k0, int k1) {
+int direct_batch(thcsox_plan_s* p, const double* G, double* Sigma, int k0, int k1,
+                 bool accumulate) {
   const int n = p->n, naux = p->naux, m = p->m, nb = k1 - k0;
   const hipStream_t s = p->stream;
   const int64_t nn = (int64_t)n * n, aa = (int64_t)naux * naux;
@@ -387,7 +389,7 @@ int direct_batch(thcsox_plan_s* p, const double* G, double* Sigma, int k0, int k
   g.C = bufC;
   HIP_TRY(gemm64(g, s));
   HIP_TRY(hadamard64(bufC, bufA, bufC, (int64_t)nb * aa, s));
-  return backproject_batch(p, bufC, aa, Sigma + (int64_t)k0 * nn, nb);
+  return backproject_batch(p, bufC, aa, Sigma + (int64_t)k0 * nn, nb, accumulate ? 1.0 : 0.0);
 }
 
 }  // namespace
@@ -604,7 +606,7 @@ int thcsox_backproject(thcsox_plan_t p, const double* Sigma_thc_dev, double* Sig
 }
 
 int thcsox_sigma_direct(thcsox_plan_t p, const double* G_dev, double* Sigma_dev, int k_begin,
-                        int k_end) {
+                        int k_end, int accumulate) {
   clear_error();
   if (p == nullptr) return fail(THCSOX_EINVAL, "plan is NULL");
   if (k_begin < 0 || k_end > p->m || k_begin >= k_end)
@@ -622,7 +624,7 @@ int thcsox_sigma_direct(thcsox_plan_t p, const double* G_dev, double* Sigma_dev,
     TRY(p->alloc(&p->dbuf, (size_t)3 * p->tbd * p->naux * p->naux));
   }
   for (int k = k_begin; k < k_end; k += p->tbd)
-    TRY(direct_batch(p, G_dev, Sigma_dev, k, std::min(k_end, k + p->tbd)));
+    TRY(direct_batch(p, G_dev, Sigma_dev, k, std::min(k_end, k + p->tbd), accumulate != 0));
   return 0;
 }
 

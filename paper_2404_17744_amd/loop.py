@@ -1,6 +1,6 @@
-"""SOX-only self-consistency loop on one GPU (fixed F):
+"""Self-consistency loop (SOX, or full second order: direct + SOX) on one GPU, fixed F:
 
-    G0 (independent particles) -> Sigma^SOX[G] -> (damping or DIIS on Sigma)
+    G0 (independent particles) -> Sigma[G] -> (damping or DIIS on Sigma)
        -> Dyson on the Matsubara grid (optionally with the chemical potential
           that conserves the electron number) -> G -> ...
 
@@ -33,6 +33,8 @@ def main() -> None:
     ap.add_argument("--precision", default="fp16x2")
     ap.add_argument("--matsubara", type=int, default=256)
     ap.add_argument("--tol", type=float, default=1e-7)
+    ap.add_argument("--terms", default="sox", choices=["sox", "gf2"],
+                    help="self-energy: the SOX term, or full second order (direct + SOX)")
     ap.add_argument("--damping", type=float, default=0.0,
                     help="Sigma_in <- d Sigma_in + (1 - d) Sigma_out (0: none)")
     ap.add_argument("--diis", type=int, default=0, help="Pulay DIIS depth on Sigma (0: none)")
@@ -67,7 +69,9 @@ def main() -> None:
         torch.cuda.synchronize()
         t1 = time.time()
         plan.sigma(G, out=S_out)
-        E_sox = plan.energy(G, S_out)
+        if a.terms == "gf2":
+            plan.sigma_direct(G, out=S_out, accumulate=True)   # direct + SOX
+        E_2 = plan.energy(G, S_out)
         t2 = time.time()
         used = 1
         if it == 0 or (diis is None and a.damping == 0.0):
@@ -85,11 +89,11 @@ def main() -> None:
         E1 = dyson.onebody(gamma)
         t3 = time.time()
         nelec = float(np.trace(gamma.cpu().numpy()))   # host diagnostic
-        E = E1 + E_sox
-        row = {"iter": it + 1, "E_total": E, "E_sox": E_sox, "E_onebody": E1,
+        E = E1 + E_2
+        row = {"iter": it + 1, "E_total": E, "E_2": E_2, "E_onebody": E1,
                "dE": None if E_prev is None else E - E_prev,
                "mu": mu, "nelec": nelec, "dyson_solves": solves, "diis_used": used,
-               "sox_s": t2 - t1, "dyson_s": t3 - t2,
+               "sigma_s": t2 - t1, "dyson_s": t3 - t2,
                "symmetric_tau_points": int(plan.symmetric_flags().sum()),
                "tau_points_per_s": len(tau) / (t2 - t1)}
         print(json.dumps(row), flush=True)
@@ -101,16 +105,17 @@ def main() -> None:
         diis.close()
     plan.close()
     dyson.close()
-    sox = [r["sox_s"] for r in iters]
+    sig = [r["sigma_s"] for r in iters]
     print(json.dumps({"workload": a.workload, "n": s.n, "naux": s.naux, "ntau": len(tau),
-                      "lam": a.lam, "precision": a.precision, "damping": a.damping,
+                      "lam": a.lam, "precision": a.precision, "terms": a.terms,
+                      "damping": a.damping,
                       "diis": a.diis, "mu_search": a.mu_search, "iterations": len(iters),
                       "converged": len(iters) > 1 and abs(iters[-1]["dE"]) < a.tol,
                       "E_total": iters[-1]["E_total"],
                       "generate_s": t_gen, "plan_s": t_plan,
-                      "sox_s_mean": sum(sox) / len(sox),
+                      "sigma_s_mean": sum(sig) / len(sig),
                       "dyson_s_mean": sum(r["dyson_s"] for r in iters) / len(iters),
-                      "tau_points_per_s": len(tau) * len(sox) / sum(sox)}), flush=True)
+                      "tau_points_per_s": len(tau) * len(sig) / sum(sig)}), flush=True)
 
 
 if __name__ == "__main__":

@@ -103,7 +103,7 @@ def lib() -> ctypes.CDLL:
         L.thcsox_dyson_step_mu.argtypes = [vp, vp, d, d, ctypes.POINTER(d), vp, vp,
                                            ctypes.POINTER(i)]
         L.thcsox_dyson_step_mu.restype = i
-        L.thcsox_sigma_direct.argtypes = [vp, vp, vp, i, i]
+        L.thcsox_sigma_direct.argtypes = [vp, vp, vp, i, i, i]
         L.thcsox_sigma_direct.restype = i
         L.thcsox_mix.argtypes = [ctypes.c_int64, d, vp, vp, vp]
         L.thcsox_mix.restype = i
@@ -418,13 +418,16 @@ class Plan:
                          out_thc.data_ptr() if thc else None, k_begin, k_end)
         return (out, out_thc) if thc else out
 
-    def sigma_direct(self, G, k_begin: int = 0, k_end: int | None = None, out=None):
-        """Second-order direct (bubble) self-energy, FP64, for k in [k_begin, k_end)."""
+    def sigma_direct(self, G, k_begin: int = 0, k_end: int | None = None, out=None,
+                     accumulate: bool = False):
+        """Second-order direct (bubble) self-energy, FP64, for k in [k_begin, k_end);
+        accumulate=True adds it to `out` (e.g. onto the SOX term)."""
         import torch
         k_end = self.ntau if k_end is None else k_end
         if out is None:
             out = torch.zeros((self.ntau, self.n, self.n), dtype=torch.float64, device=self.device)
-        _check(lib().thcsox_sigma_direct(self.handle, G.data_ptr(), out.data_ptr(), k_begin, k_end))
+        _check(lib().thcsox_sigma_direct(self.handle, G.data_ptr(), out.data_ptr(), k_begin, k_end,
+                                         1 if accumulate else 0))
         return out
 
     def energy(self, G, Sigma) -> float:

@@ -56,7 +56,8 @@ def test_direct_and_full_gf2_energy(dev, precision):
     Sd = plan.sigma_direct(Gd)
     Sx = plan.sigma(Gd)
     E_d = plan.energy(Gd, Sd)
-    E_tot = plan.energy(Gd, Sd + Sx)
+    plan.sigma_direct(Gd, out=Sx, accumulate=True)   # Sx now holds direct + SOX
+    E_tot = plan.energy(Gd, Sx)
     plan.close()
     Ed_ref = oenergy.energy_tau(G, ref, w)
     Ex_ref = oenergy.energy_tau(G, ref_x, w)
