@@ -121,6 +121,32 @@ def sigma_thc_paper(X: np.ndarray, V: np.ndarray, G: np.ndarray, Gb: np.ndarray,
     return sigma
 
 
+def sig_thc_elements(X: np.ndarray, V: np.ndarray, G: np.ndarray, Gb: np.ndarray,
+                     pairs) -> np.ndarray:
+    """Selected elements Sig_RP = -D_PR of the paper's sequence (the equations
+    listed in ``sigma_thc_paper``) for a list of (R, P) pairs, without forming
+    U, A, B, C or D whole -- for sizes where those do not fit in host memory.
+
+    For one pair only the slices with first index P or R enter:
+        U_Pqs = sum_Q V_PQ X_qQ X_sQ     (Eq. U_contraction: X diag(V_P) X^T)
+        A_Pqv = sum_s U_Pqs G_sv(-tau)
+        B_PRv = sum_q A_Pqv G_Rq,  G_Rq = sum_u X_uR G_uq(tau)
+        C_RvP = sum_w U_Rvw G_wP,  G_wP = sum_p G_wp(tau) X_pP
+        D_PR  = sum_v C_RvP B_PRv
+    """
+    out = np.empty(len(pairs))
+    for i, (R, P) in enumerate(pairs):
+        U_P = (X * V[P]) @ X.T             # U[P, q, s]
+        U_R = (X * V[R]) @ X.T             # U[R, v, w]
+        A_P = U_P @ Gb                     # A[P, q, v]
+        G_R = X[:, R] @ G                  # G_Rq
+        G_P = G @ X[:, P]                  # G_wP
+        B = G_R @ A_P                      # B[P, R, v]
+        C = U_R @ G_P                      # C[R, v, P]
+        out[i] = -float(C @ B)             # Sig_RP = -sum_v C_RvP B_PRv
+    return out
+
+
 def precontract_u(X: np.ndarray, V: np.ndarray) -> np.ndarray:
     """U_Pqs = sum_Q V_PQ X_qQ X_sQ (Eq. U_contraction); shape [naux, n, n]."""
     n, naux = X.shape

@@ -42,6 +42,8 @@ WORKLOADS = {
     "sox_n300_naux1800_ntau100": dict(n=300, naux=1800, m=100, beta=100.0),
     # one-GPU share at paper scale
     "sox_n1100_naux5500_ntau100": dict(n=1100, naux=5500, m=100, beta=100.0),
+    # the paper's largest system size with its interpolation ratio naux / n = 10
+    "sox_n1127_naux11270_ntau100": dict(n=1127, naux=11270, m=100, beta=100.0),
 }
 
 

@@ -65,6 +65,27 @@ def test_all_forms_match_bruteforce_nonsymmetric_g():
     assert rel(osox.sigma_all_tau(osox.sigma_thc_basis, G, s.X, s.V), ref) < 1e-13
 
 
+def test_thc_elements_match_bruteforce_nonsymmetric_g():
+    """The element-at-a-time form (used at sizes where U does not fit on the
+    host): with every (R, P) pair requested, X Sig_thc X^T equals the six-index
+    definition on a non-symmetric G, and the elements equal the whole-array
+    sequence's Sig_thc.  With R and P swapped the first check fails (Sig_thc is
+    not symmetric here), so the orientation is pinned too."""
+    s = synth.make_system(6, 20, seed=2)
+    G = synth.random_general_g(6, 4, seed=3)
+    v = osox.thc_eri(s.X, s.V)
+    pairs = [(R, P) for R in range(20) for P in range(20)]
+    for k in range(4):
+        ref = osox.sigma_bruteforce(v, G[k], G[3 - k])
+        el = osox.sig_thc_elements(s.X, s.V, G[k], G[3 - k], pairs).reshape(20, 20)
+        assert rel(s.X @ el @ s.X.T, ref) < 1e-13
+        _, thc = osox.sigma_thc_paper(s.X, s.V, G[k], G[3 - k], return_thc=True)
+        assert rel(el, thc) < 1e-13
+        swapped = osox.sig_thc_elements(s.X, s.V, G[k], G[3 - k],
+                                        [(P, R) for R, P in pairs]).reshape(20, 20)
+        assert rel(s.X @ swapped @ s.X.T, ref) > 1e-3
+
+
 def test_symmetric_sigma_for_symmetric_inputs(tiny):
     s, tau, w, G, beta = tiny
     S = osox.sigma_all_tau(osox.sigma_thc_paper, G, s.X, s.V)
