@@ -130,6 +130,19 @@ int thcsox_symmetric_flags(thcsox_plan_t p, int* flags_host);
 int thcsox_energy(thcsox_plan_t p, const double* G_dev, const double* Sigma_dev,
                   double* E_host);
 
+/* The same energy on a grid whose quadrature is a basis expansion (the IR
+ * sampling grid of thcsox_ir_create): with coefficients g = C G(tau),
+ * sigma = C Sigma(tau) (C: coef_host [ntau][ntau], row l maps the tau values to
+ * coefficient l) and u_l(beta - tau) = sign_l u_l(tau) for an orthonormal basis,
+ *     E = -1/2 int_0^beta Tr[G(beta - tau) Sigma(tau)] dtau
+ *       = -1/2 sum_l sign_l sum_pq g_l[p][q] sigma_l[q][p].
+ * The plan's tau points must be the basis's sampling points (mirror-symmetric,
+ * so that the SOX evaluation finds G(beta - tau_k) at index ntau-1-k).  The
+ * first call allocates 2 ntau n^2 doubles (kept by the plan).  FP64, fixed
+ * summation order; synchronises the plan's stream. */
+int thcsox_energy_basis(thcsox_plan_t p, const double* G_dev, const double* Sigma_dev,
+                        const double* coef_host, const double* sign_host, double* E_host);
+
 /* The second-order direct (bubble) self-energy of GF2 on the same THC data
  * (Sec. "Self-energy functionals": full scGF2 = direct + SOX terms; the paper
  * treats this term as in the THC-GW work it cites and prints no formula).
@@ -156,6 +169,35 @@ int thcsox_sigma_direct(thcsox_plan_t p, const double* G_dev, double* Sigma_dev,
  * back to the orbital basis.  FP64, asynchronous. */
 int thcsox_backproject(thcsox_plan_t p, const double* Sigma_thc_dev, double* Sigma_dev,
                        int k_begin, int k_end);
+
+/* ---------------------------------------------------------------------------
+ * IR basis and sparse sampling (computational-details section: the paper's loop
+ * runs on the intermediate-representation grids of the references it cites,
+ * at beta = 1000 and Lambda = 1e5).  Built on the host from the definition:
+ * the singular value expansion of the fermionic kernel
+ *     K(tau, omega) = exp(-tau omega) / (1 + exp(-beta omega)),
+ *     tau in [0, beta], |omega| <= wmax, Lambda = beta wmax,
+ * truncated at s_l / s_0 >= eps (L functions).  Sampling points: the L roots of
+ * u_L in tau; the n >= 0 where the Matsubara transform of u_{L-1} or u_L
+ * changes sign, and n = 0, in frequency.
+ *   thcsox_ir_create : eps in [1e-13, 1); Lambda <= 1e7.  Host-only (no HIP
+ *       calls); about a second at Lambda = 1e5.  THCSOX_EINVAL for bad
+ *       arguments or an eps finer than the FP64 discretisation resolves (the
+ *       root count of u_L is checked).
+ *   thcsox_ir_sizes  : ntau = L, nfreq.
+ *   thcsox_ir_get    : copies (each pointer may be NULL) tau[ntau] ascending,
+ *       freq_n[nfreq] ascending, Wf[2 nfreq][ntau] and Wb[ntau + 1][2 nfreq]
+ *       (as thcsox_dyson_plan_sampled takes them), coef[ntau][ntau] (tau values
+ *       -> coefficients) and sign[ntau] (u_l(beta - tau) = sign_l u_l(tau)) for
+ *       thcsox_energy_basis, and the singular values sv[ntau] (tau, omega units).
+ *   thcsox_ir_destroy: accepts NULL.
+ * ------------------------------------------------------------------------- */
+typedef struct thcsox_ir_s* thcsox_ir_t;
+int thcsox_ir_create(thcsox_ir_t* out, double beta, double wmax, double eps);
+int thcsox_ir_sizes(thcsox_ir_t g, int* ntau, int* nfreq);
+int thcsox_ir_get(thcsox_ir_t g, double* tau, int* freq_n, double* Wf, double* Wb, double* coef,
+                  double* sign, double* sv);
+int thcsox_ir_destroy(thcsox_ir_t g);
 
 /* Release a plan and all its device memory.  Accepts NULL. */
 int thcsox_destroy(thcsox_plan_t p);
@@ -223,6 +265,20 @@ int thcsox_dyson_step_mu(thcsox_dyson_t d, const double* Sigma_dev, double nelec
                          double* mu_io, double* G_dev, double* gamma_dev, int* evals_out);
 
 /* E1 = Tr[F gamma] = sum_pq F_pq gamma_qp in FP64 (host scalar). */
+/* A Dyson plan on caller-given sampling grids (e.g. the IR grids of
+ * thcsox_ir_create) instead of the Chebyshev grid: ntau tau points, and nfreq
+ * fermionic frequencies w_j = (2 freq_n[j] + 1) pi / beta, freq_n ascending,
+ * >= 0 (the negative ones are the complex conjugates for real G(tau)).
+ *   Wf_host [2 nfreq][ntau]   : [Re; Im] F(i w_j) = Wf F(tau)
+ *   Wb_host [ntau + 1][2 nfreq]: F(tau_k) (rows 0..ntau-1) and F(beta^-) (last
+ *                                row) from [Re; Im] F(i w_j)
+ * Both are copied.  Steps, the mu search and the energies are then as for
+ * thcsox_dyson_plan (gamma = -G(beta^-) from the last row of Wb).  THCSOX_EINVAL
+ * for 2 nfreq < ntau, unsorted or negative freq_n, or non-finite tables. */
+int thcsox_dyson_plan_sampled(thcsox_dyson_t* out, int n, int ntau, int nfreq, double beta,
+                              double mu, const int* freq_n_host, const double* Wf_host,
+                              const double* Wb_host, const double* F_dev, void* hip_stream);
+
 int thcsox_dyson_onebody(thcsox_dyson_t d, const double* gamma_dev, double* E1_host);
 
 int thcsox_dyson_destroy(thcsox_dyson_t d);

@@ -204,3 +204,10 @@ def dyson_step_sampled(F: np.ndarray, mu: float, beta: float, Sigma_tau: np.ndar
     Gri = np.concatenate([Giw.real, Giw.imag])            # [2 nf, n, n]
     out = np.tensordot(Wb, Gri, axes=(1, 0))              # [m + 1, n, n]
     return out[:m], -out[m]
+
+
+def evaluate_at(b: IRBasis, tau: np.ndarray, F_tau: np.ndarray, tau_new: np.ndarray) -> np.ndarray:
+    """The basis expansion fitted to F on the sampling points tau, evaluated at
+    tau_new: F(tau_new) = U(tau_new) Ut^-1 F(tau).  F_tau: [m, ...]."""
+    coef = np.linalg.solve(b.u_tau(tau), F_tau.reshape(len(tau), -1))
+    return (b.u_tau(np.asarray(tau_new)) @ coef).reshape((len(tau_new),) + F_tau.shape[1:])

@@ -226,12 +226,12 @@ const Tables& tables_for(int m, int nw, double beta) {
 // Kernels
 // ----------------------------------------------------------------------------
 
-// Am[w] = (i w + mu) 1 - F - Sigma(i w) as complex [n][n].
+// Am[w] = (i w_w + mu) 1 - F - Sigma(i w_w) as complex [n][n]; wfreq[w] = w_w.
 __global__ __launch_bounds__(NT) void build_a(const double* __restrict__ S, const double* __restrict__ F,
-                                              double mu, double beta, int n, int nw,
-                                              double2* __restrict__ Am) {
+                                              double mu, const double* __restrict__ wfreq, int n,
+                                              int nw, double2* __restrict__ Am) {
   const int w = blockIdx.y;
-  const double wn = (2.0 * w + 1.0) * M_PI / beta;
+  const double wn = wfreq[w];
   const int64_t nn = (int64_t)n * n;
   const double* Sre = S + (int64_t)w * nn;
   const double* Sim = S + (int64_t)(nw + w) * nn;
@@ -491,6 +491,7 @@ struct thcsox_dyson_s {
   double* F = nullptr;     // [n][n]
   double* Wf = nullptr;    // [2nw][m]
   double* Wb = nullptr;    // [m+1][2nw]
+  double* wfreq = nullptr; // [nw] the frequencies w_j
   double* Siw = nullptr;   // [2nw][n n]
   double2* Am = nullptr;   // [nw][n][n]
   int* piv = nullptr;      // [nw][n]
@@ -550,7 +551,7 @@ int dy_invert(thcsox_dyson_s* d, double mu) {
   const int64_t nn = (int64_t)n * n;
   const hipStream_t s = d->stream;
   const unsigned bx = (unsigned)std::min<int64_t>(64, (nn + NT - 1) / NT);
-  build_a<<<dim3(bx, nw), NT, 0, s>>>(d->Siw, d->F, mu, d->beta, n, nw, d->Am);
+  build_a<<<dim3(bx, nw), NT, 0, s>>>(d->Siw, d->F, mu, d->wfreq, n, nw, d->Am);
   DTRY(hipGetLastError());
   DTRY(hipMemsetAsync(d->flag, 0, sizeof(int), s));
   const int bw = d->panel;
@@ -612,6 +613,55 @@ int dy_backward(thcsox_dyson_s* d, double* G_dev, double* gamma_dev) {
 
 }  // namespace
 
+namespace {
+// The plan on given transform tables (Wf [2 nw][m], Wb [m + 1][2 nw]) and
+// frequencies wf[nw]; F_dev is checked to be device memory.
+int dyson_create(thcsox_dyson_t* out, int n, int m, int nw, double beta, double mu,
+                 const std::vector<double>& wf, const std::vector<double>& Wf,
+                 const std::vector<double>& Wb, const double* F_dev, void* hip_stream) {
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, F_dev) != hipSuccess ||
+      (a.type != hipMemoryTypeDevice && a.type != hipMemoryTypeManaged)) {
+    (void)hipGetLastError();
+    return dfail(THCSOX_ENOTDEV, "F_dev is not device memory");
+  }
+  auto* d = new thcsox_dyson_s();
+  d->n = n; d->m = m; d->nw = nw; d->beta = beta; d->mu = mu;
+  while (d->panel > 1 && (int64_t)d->panel * n > GJ_LDS) d->panel /= 2;
+  d->stream = static_cast<hipStream_t>(hip_stream);
+  const int64_t nn = (int64_t)n * n;
+  int rc;
+  if ((rc = dalloc(d, &d->F, nn)) || (rc = dalloc(d, &d->Wf, (size_t)2 * d->nw * d->m)) ||
+      (rc = dalloc(d, &d->Wb, (size_t)(d->m + 1) * 2 * d->nw)) ||
+      (rc = dalloc(d, &d->wfreq, (size_t)d->nw)) ||
+      (rc = dalloc(d, &d->Siw, (size_t)2 * d->nw * nn)) ||
+      (rc = dalloc(d, &d->Am, (size_t)d->nw * nn)) ||
+      (rc = dalloc(d, &d->piv, (size_t)d->nw * n)) ||
+      (rc = dalloc(d, &d->perm, (size_t)d->nw * n)) ||
+      (rc = dalloc(d, &d->Gs, (size_t)2 * d->nw * nn)) ||
+      (rc = dalloc(d, &d->Gout, (size_t)(d->m + 1) * nn)) || (rc = dalloc(d, &d->flag, 1)) ||
+      (rc = dalloc(d, &d->scal, 1)) || (rc = dalloc(d, &d->traces, (size_t)2 * d->nw))) {
+    delete d;
+    return rc;
+  }
+  d->gamma_row.assign(Wb.begin() + (size_t)d->m * 2 * d->nw, Wb.begin() + (size_t)(d->m + 1) * 2 * d->nw);
+  hipError_t e;
+  if ((e = hipMemcpyAsync(d->F, F_dev, sizeof(double) * nn, hipMemcpyDeviceToDevice, d->stream)) ||
+      (e = hipMemcpyAsync(d->Wf, Wf.data(), sizeof(double) * Wf.size(),
+                          hipMemcpyHostToDevice, d->stream)) ||
+      (e = hipMemcpyAsync(d->Wb, Wb.data(), sizeof(double) * Wb.size(),
+                          hipMemcpyHostToDevice, d->stream)) ||
+      (e = hipMemcpyAsync(d->wfreq, wf.data(), sizeof(double) * wf.size(),
+                          hipMemcpyHostToDevice, d->stream)) ||
+      (e = hipStreamSynchronize(d->stream))) {
+    delete d;
+    return dfail(THCSOX_EDEVICE, std::string("dyson plan: ") + hipGetErrorString(e));
+  }
+  *out = d;
+  return 0;
+}
+}  // namespace
+
 extern "C" {
 
 int thcsox_dyson_plan(thcsox_dyson_t* out, int n, int ntau, int n_matsubara, double beta,
@@ -631,44 +681,39 @@ int thcsox_dyson_plan(thcsox_dyson_t* out, int n, int ntau, int n_matsubara, dou
     if (std::fabs(tau_host[k] - 0.5 * beta * (1.0 + x)) > 1e-12 * beta)
       return dfail(THCSOX_EINVAL, "tau grid is not the Chebyshev-root grid");
   }
-  hipPointerAttribute_t a;
-  if (hipPointerGetAttributes(&a, F_dev) != hipSuccess ||
-      (a.type != hipMemoryTypeDevice && a.type != hipMemoryTypeManaged)) {
-    (void)hipGetLastError();
-    return dfail(THCSOX_ENOTDEV, "F_dev is not device memory");
-  }
-  auto* d = new thcsox_dyson_s();
-  d->n = n; d->m = ntau; d->nw = n_matsubara; d->beta = beta; d->mu = mu;
-  while (d->panel > 1 && (int64_t)d->panel * n > GJ_LDS) d->panel /= 2;
-  d->stream = static_cast<hipStream_t>(hip_stream);
-  const int64_t nn = (int64_t)n * n;
-  int rc;
-  if ((rc = dalloc(d, &d->F, nn)) || (rc = dalloc(d, &d->Wf, (size_t)2 * d->nw * d->m)) ||
-      (rc = dalloc(d, &d->Wb, (size_t)(d->m + 1) * 2 * d->nw)) ||
-      (rc = dalloc(d, &d->Siw, (size_t)2 * d->nw * nn)) ||
-      (rc = dalloc(d, &d->Am, (size_t)d->nw * nn)) ||
-      (rc = dalloc(d, &d->piv, (size_t)d->nw * n)) ||
-      (rc = dalloc(d, &d->perm, (size_t)d->nw * n)) ||
-      (rc = dalloc(d, &d->Gs, (size_t)2 * d->nw * nn)) ||
-      (rc = dalloc(d, &d->Gout, (size_t)(d->m + 1) * nn)) || (rc = dalloc(d, &d->flag, 1)) ||
-      (rc = dalloc(d, &d->scal, 1)) || (rc = dalloc(d, &d->traces, (size_t)2 * d->nw))) {
-    delete d;
-    return rc;
-  }
-  const Tables& tb = tables_for(d->m, d->nw, beta);
-  d->gamma_row.assign(tb.Wb.begin() + (size_t)d->m * 2 * d->nw, tb.Wb.begin() + (size_t)(d->m + 1) * 2 * d->nw);
-  hipError_t e;
-  if ((e = hipMemcpyAsync(d->F, F_dev, sizeof(double) * nn, hipMemcpyDeviceToDevice, d->stream)) ||
-      (e = hipMemcpyAsync(d->Wf, tb.Wf.data(), sizeof(double) * tb.Wf.size(),
-                          hipMemcpyHostToDevice, d->stream)) ||
-      (e = hipMemcpyAsync(d->Wb, tb.Wb.data(), sizeof(double) * tb.Wb.size(),
-                          hipMemcpyHostToDevice, d->stream)) ||
-      (e = hipStreamSynchronize(d->stream))) {
-    delete d;
-    return dfail(THCSOX_EDEVICE, std::string("dyson plan: ") + hipGetErrorString(e));
-  }
-  *out = d;
-  return 0;
+  const Tables& tb = tables_for(ntau, n_matsubara, beta);
+  std::vector<double> wf(n_matsubara);
+  for (int j = 0; j < n_matsubara; ++j) wf[j] = (2.0 * j + 1.0) * M_PI / beta;
+  return dyson_create(out, n, ntau, n_matsubara, beta, mu, wf, tb.Wf, tb.Wb, F_dev, hip_stream);
+}
+
+int thcsox_dyson_plan_sampled(thcsox_dyson_t* out, int n, int ntau, int nfreq, double beta,
+                              double mu, const int* freq_n_host, const double* Wf_host,
+                              const double* Wb_host, const double* F_dev, void* hip_stream) {
+  clear_error();
+  if (out == nullptr) return dfail(THCSOX_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n <= 0 || ntau <= 1 || nfreq <= 0 || !(beta > 0.0))
+    return dfail(THCSOX_EINVAL, "need n > 0, ntau > 1, nfreq > 0, beta > 0");
+  if ((int64_t)n > GJ_LDS)
+    return dfail(THCSOX_EINVAL, "n too large for the in-LDS panel of the Dyson inversion (n <= 9216)");
+  if (2 * nfreq < ntau) return dfail(THCSOX_EINVAL, "need 2 nfreq >= ntau for the fit");
+  if (freq_n_host == nullptr || Wf_host == nullptr || Wb_host == nullptr || F_dev == nullptr)
+    return dfail(THCSOX_EINVAL, "NULL argument");
+  for (int j = 0; j < nfreq; ++j)
+    if (freq_n_host[j] < 0 || (j > 0 && freq_n_host[j] <= freq_n_host[j - 1]))
+      return dfail(THCSOX_EINVAL, "freq_n must be ascending and >= 0");
+  std::vector<double> Wf(Wf_host, Wf_host + (size_t)2 * nfreq * ntau);
+  std::vector<double> Wb(Wb_host, Wb_host + (size_t)(ntau + 1) * 2 * nfreq);
+  for (double v : Wf)
+    if (!std::isfinite(v)) return dfail(THCSOX_EINVAL, "Wf has a non-finite entry");
+  for (double v : Wb)
+    if (!std::isfinite(v)) return dfail(THCSOX_EINVAL, "Wb has a non-finite entry");
+  // the plan's last table row gives gamma = -G(beta^-) directly
+  for (size_t j = (size_t)ntau * 2 * nfreq; j < Wb.size(); ++j) Wb[j] = -Wb[j];
+  std::vector<double> wf(nfreq);
+  for (int j = 0; j < nfreq; ++j) wf[j] = (2.0 * freq_n_host[j] + 1.0) * M_PI / beta;
+  return dyson_create(out, n, ntau, nfreq, beta, mu, wf, Wf, Wb, F_dev, hip_stream);
 }
 
 int thcsox_dyson_step(thcsox_dyson_t d, const double* Sigma_dev, double* G_dev, double* gamma_dev) {

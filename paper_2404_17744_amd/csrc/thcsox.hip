@@ -84,6 +84,9 @@ struct thcsox_plan_s {
   double* X = nullptr;      // [n][naux]
   double* V = nullptr;      // [naux][naux] (the direct term)
   double* dbuf = nullptr;   // direct term: 3 x [tbd][naux][naux], allocated on first use
+  double* ebuf = nullptr;   // basis energy: 2 x [ntau][n][n] coefficients, on first use
+  double* ecoef = nullptr;  // basis energy: [2][ntau][ntau] (rows reversed, then as given)
+  double* esign = nullptr;  // basis energy: [ntau]
   int tbd = 0;              // tau points per direct-term batch
   double* w = nullptr;      // [m]
   void* U = nullptr;        // planes of [naux][n][ldk]
@@ -638,6 +641,52 @@ int thcsox_energy(thcsox_plan_t p, const double* G_dev, const double* Sigma_dev,
   const hipStream_t s = p->stream;
   HIP_TRY(energy_partials(G_dev, Sigma_dev, p->n, p->m, p->tr, s));
   HIP_TRY(energy_final(p->tr, p->w, p->m, p->E, s));
+  HIP_TRY(hipMemcpyAsync(E_host, p->E, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return 0;
+}
+
+int thcsox_energy_basis(thcsox_plan_t p, const double* G_dev, const double* Sigma_dev,
+                        const double* coef_host, const double* sign_host, double* E_host) {
+  clear_error();
+  if (p == nullptr) return fail(THCSOX_EINVAL, "plan is NULL");
+  if (E_host == nullptr || coef_host == nullptr || sign_host == nullptr)
+    return fail(THCSOX_EINVAL, "NULL argument");
+  TRY(check_dev(G_dev, "G_dev"));
+  TRY(check_dev(Sigma_dev, "Sigma_dev"));
+  const int m = p->m, n = p->n;
+  const int64_t nn = (int64_t)n * n, mm = (int64_t)m * m;
+  for (int l = 0; l < m; ++l)
+    if (sign_host[l] != 1.0 && sign_host[l] != -1.0) return fail(THCSOX_EINVAL, "sign must be +-1");
+  for (int64_t i = 0; i < mm; ++i)
+    if (!std::isfinite(coef_host[i])) return fail(THCSOX_EINVAL, "coef has a non-finite entry");
+  if (p->ebuf == nullptr) {
+    TRY(p->alloc(&p->ebuf, (size_t)(2 * m * nn)));
+    TRY(p->alloc(&p->ecoef, (size_t)(2 * mm)));
+    TRY(p->alloc(&p->esign, (size_t)m));
+  }
+  // g = C G with the rows of C reversed, sigma = C Sigma: the trace kernel pairs
+  // index k of its first operand with index m-1-k of the second, so it meets
+  // g_l with sigma_l
+  std::vector<double> c2((size_t)(2 * mm));
+  for (int l = 0; l < m; ++l)
+    for (int k = 0; k < m; ++k) {
+      c2[(size_t)(m - 1 - l) * m + k] = coef_host[(size_t)l * m + k];
+      c2[(size_t)mm + (size_t)l * m + k] = coef_host[(size_t)l * m + k];
+    }
+  const hipStream_t s = p->stream;
+  HIP_TRY(hipMemcpyAsync(p->ecoef, c2.data(), sizeof(double) * c2.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(p->esign, sign_host, sizeof(double) * m, hipMemcpyHostToDevice, s));
+  for (int t = 0; t < 2; ++t) {
+    Gemm64Args g{};
+    g.M = m; g.N = (int)nn; g.K = m; g.batch = 1; g.alpha = 1.0; g.beta = 0.0;
+    g.A = p->ecoef + t * mm; g.a_i = m; g.a_k = 1;
+    g.B = t == 0 ? G_dev : Sigma_dev; g.b_k = nn; g.b_j = 1;
+    g.C = p->ebuf + t * m * nn; g.c_i = nn; g.c_j = 1; g.cj_in = nn; g.cj_out = 0;
+    HIP_TRY(gemm64(g, s));
+  }
+  HIP_TRY(energy_partials(p->ebuf, p->ebuf + m * nn, n, m, p->tr, s));
+  HIP_TRY(energy_final(p->tr, p->esign, m, p->E, s));
   HIP_TRY(hipMemcpyAsync(E_host, p->E, sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   return 0;

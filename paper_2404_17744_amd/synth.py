@@ -139,6 +139,25 @@ def workload(name: str, seed: int = 0, lam: float = 1.0):
     return s, tau, w, G, cfg["beta"]
 
 
+def pole_sigma(n: int, tau: np.ndarray, beta: float, seed: int, npoles: int = 4,
+               scale: float = 0.05) -> np.ndarray:
+    """A self-energy-like input with a closed form at any tau: a sum of poles,
+    Sigma(tau) = -sum_j A_j K(tau, w_j), K(tau, w) = exp(-tau w) / (1 + exp(-beta w)),
+    A_j random symmetric (n x n, entries ~ scale), w_j = +-U(0.2, 3) Ha.
+    Returns [len(tau), n, n]."""
+    rng = np.random.default_rng(seed)
+    out = np.zeros((len(tau), n, n))
+    for _ in range(npoles):
+        A = rng.normal(0.0, scale, (n, n))
+        A = 0.5 * (A + A.T)
+        w = rng.uniform(0.2, 3.0) * (1 if rng.random() < 0.5 else -1)
+        t = np.asarray(tau)
+        k = (np.exp(-t * w) / (1 + np.exp(-beta * w)) if w >= 0
+             else np.exp(w * (beta - t)) / (1 + np.exp(beta * w)))
+        out -= k[:, None, None] * A[None]
+    return out
+
+
 def random_general_g(n: int, m: int, seed: int, scale: float = 0.3) -> np.ndarray:
     """Non-symmetric dense G[m,n,n] for checks that must not lean on G = G^T."""
     rng = np.random.default_rng(seed)

@@ -37,7 +37,8 @@ EXPORTS = ("thcsox_plan", "thcsox_sigma_sox", "thcsox_energy", "thcsox_destroy",
            "thcsox_pair_gather", "thcsox_pair_scatter", "thcsox_set_symmetry",
            "thcsox_symmetric_flags", "thcsox_dyson_step_mu", "thcsox_mix",
            "thcsox_diis_create", "thcsox_diis_step", "thcsox_diis_destroy",
-           "thcsox_sigma_direct")
+           "thcsox_sigma_direct", "thcsox_energy_basis", "thcsox_dyson_plan_sampled",
+           "thcsox_ir_create", "thcsox_ir_sizes", "thcsox_ir_get", "thcsox_ir_destroy")
 SYMMETRY = {"auto": 0, "off": 1}
 STAGES = ("project", "a_stage", "fused", "back")
 
@@ -105,6 +106,19 @@ def lib() -> ctypes.CDLL:
         L.thcsox_dyson_step_mu.restype = i
         L.thcsox_sigma_direct.argtypes = [vp, vp, vp, i, i, i]
         L.thcsox_sigma_direct.restype = i
+        L.thcsox_energy_basis.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(d)]
+        L.thcsox_energy_basis.restype = i
+        L.thcsox_dyson_plan_sampled.argtypes = [ctypes.POINTER(vp), i, i, i, d, d, vp, vp, vp,
+                                                vp, vp]
+        L.thcsox_dyson_plan_sampled.restype = i
+        L.thcsox_ir_create.argtypes = [ctypes.POINTER(vp), d, d, d]
+        L.thcsox_ir_create.restype = i
+        L.thcsox_ir_sizes.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i)]
+        L.thcsox_ir_sizes.restype = i
+        L.thcsox_ir_get.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+        L.thcsox_ir_get.restype = i
+        L.thcsox_ir_destroy.argtypes = [vp]
+        L.thcsox_ir_destroy.restype = i
         L.thcsox_mix.argtypes = [ctypes.c_int64, d, vp, vp, vp]
         L.thcsox_mix.restype = i
         L.thcsox_diis_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int64, i, vp]
@@ -214,6 +228,52 @@ def thcsox_dyson_plan(n: int, ntau: int, n_matsubara: int, beta: float, mu: floa
     return h
 
 
+def thcsox_dyson_plan_sampled(n: int, ntau: int, nfreq: int, beta: float, mu: float,
+                              freq_n: np.ndarray, Wf: np.ndarray, Wb: np.ndarray, F_dev: int,
+                              hip_stream: int = 0):
+    fn = np.ascontiguousarray(freq_n, dtype=np.int32)
+    wf = np.ascontiguousarray(Wf, dtype=np.float64)
+    wb = np.ascontiguousarray(Wb, dtype=np.float64)
+    if fn.shape != (nfreq,) or wf.shape != (2 * nfreq, ntau) or wb.shape != (ntau + 1, 2 * nfreq):
+        raise ValueError("freq_n [nfreq], Wf [2 nfreq, ntau], Wb [ntau + 1, 2 nfreq] expected")
+    h = ctypes.c_void_p()
+    vpp = ctypes.c_void_p
+    _check(lib().thcsox_dyson_plan_sampled(ctypes.byref(h), n, ntau, nfreq, beta, mu,
+                                           fn.ctypes.data_as(vpp), wf.ctypes.data_as(vpp),
+                                           wb.ctypes.data_as(vpp), F_dev, hip_stream))
+    return h
+
+
+def thcsox_energy_basis(plan, G_dev: int, Sigma_dev: int, coef: np.ndarray,
+                        sign: np.ndarray) -> float:
+    c = np.ascontiguousarray(coef, dtype=np.float64)
+    sg = np.ascontiguousarray(sign, dtype=np.float64)
+    E = ctypes.c_double()
+    _check(lib().thcsox_energy_basis(plan, G_dev, Sigma_dev, c.ctypes.data_as(ctypes.c_void_p),
+                                     sg.ctypes.data_as(ctypes.c_void_p), ctypes.byref(E)))
+    return E.value
+
+
+def thcsox_ir_grid(beta: float, wmax: float, eps: float = 1e-10) -> dict:
+    """The IR basis sampling grids and tables (host only)."""
+    h = ctypes.c_void_p()
+    _check(lib().thcsox_ir_create(ctypes.byref(h), float(beta), float(wmax), float(eps)))
+    try:
+        m, nf = ctypes.c_int(), ctypes.c_int()
+        _check(lib().thcsox_ir_sizes(h, ctypes.byref(m), ctypes.byref(nf)))
+        m, nf = m.value, nf.value
+        out = {"tau": np.empty(m), "freq_n": np.empty(nf, dtype=np.int32),
+               "Wf": np.empty((2 * nf, m)), "Wb": np.empty((m + 1, 2 * nf)),
+               "coef": np.empty((m, m)), "sign": np.empty(m), "sv": np.empty(m)}
+        ptr = {k: v.ctypes.data_as(ctypes.c_void_p) for k, v in out.items()}
+        _check(lib().thcsox_ir_get(h, ptr["tau"], ptr["freq_n"], ptr["Wf"], ptr["Wb"],
+                                   ptr["coef"], ptr["sign"], ptr["sv"]))
+    finally:
+        lib().thcsox_ir_destroy(h)
+    out.update(beta=float(beta), wmax=float(wmax), eps=float(eps))
+    return out
+
+
 def thcsox_dyson_step(d, Sigma_dev: int, G_dev: int, gamma_dev: int | None) -> None:
     _check(lib().thcsox_dyson_step(d, Sigma_dev, G_dev, gamma_dev))
 
@@ -261,15 +321,27 @@ def thcsox_diis_destroy(h) -> None:
 class Dyson:
     """Owns one Dyson/transform plan; tensors are torch float64 device tensors."""
 
-    def __init__(self, F, mu: float, tau, beta: float, n_matsubara: int = 256, stream=None):
+    def __init__(self, F, mu: float, tau, beta: float, n_matsubara: int = 256, stream=None,
+                 grid: dict | None = None):
+        """Chebyshev-root tau grid with n_matsubara frequencies, or (grid given)
+        the sampling grids of thcsox_ir_grid, whose tau points `tau` must be."""
         import torch
         self.n = F.shape[0]
         self.ntau = len(tau)
         self.device = F.device
         self.stream = stream if stream is not None else torch.cuda.current_stream(F.device)
         Fc = F.contiguous().to(torch.float64)
-        self.handle = thcsox_dyson_plan(self.n, self.ntau, n_matsubara, float(beta), float(mu),
-                                        np.asarray(tau), Fc.data_ptr(), self.stream.cuda_stream)
+        if grid is None:
+            self.handle = thcsox_dyson_plan(self.n, self.ntau, n_matsubara, float(beta),
+                                            float(mu), np.asarray(tau), Fc.data_ptr(),
+                                            self.stream.cuda_stream)
+        else:
+            if not np.array_equal(np.asarray(tau, dtype=np.float64), grid["tau"]):
+                raise ValueError("tau must be the grid's sampling points")
+            self.handle = thcsox_dyson_plan_sampled(self.n, self.ntau, len(grid["freq_n"]),
+                                                    float(beta), float(mu), grid["freq_n"],
+                                                    grid["Wf"], grid["Wb"], Fc.data_ptr(),
+                                                    self.stream.cuda_stream)
 
     def step(self, Sigma, G_out=None, gamma_out=None):
         import torch
@@ -432,6 +504,11 @@ class Plan:
 
     def energy(self, G, Sigma) -> float:
         return thcsox_energy(self.handle, G.data_ptr(), Sigma.data_ptr())
+
+    def energy_basis(self, G, Sigma, grid: dict) -> float:
+        """The energy on an IR grid (thcsox_ir_grid): the basis-coefficient form."""
+        return thcsox_energy_basis(self.handle, G.data_ptr(), Sigma.data_ptr(), grid["coef"],
+                                   grid["sign"])
 
     def backproject(self, Sigma_thc, k_begin: int = 0, k_end: int | None = None, out=None):
         import torch
