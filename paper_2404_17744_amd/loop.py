@@ -12,6 +12,10 @@ one-GPU share:
 
     python -m paper_2404_17744_amd.loop --workload sox_n1100_naux5500_ntau100 --iters 10
     python -m paper_2404_17744_amd.loop --workload sox_n300_naux1800_ntau100 --diis 6 --mu-search
+
+With --grid ir the loop runs on the IR sparse-sampling grids (tau points and
+Matsubara frequencies of the basis at --beta and Lambda = beta --wmax), with
+the energy from the basis expansion; the workload then only sets n and naux.
 """
 from __future__ import annotations
 
@@ -43,12 +47,23 @@ def main() -> None:
     # above the transforms' accuracy in N (~1e-7 at 64 Chebyshev points, beta = 100):
     # in a gap N(mu) is flat to that level, and a tighter target drives mu to a gap edge
     ap.add_argument("--mu-tol", type=float, default=1e-5)
+    ap.add_argument("--grid", default="cheb", choices=["cheb", "ir"],
+                    help="Chebyshev roots (the workload's grid) or IR sparse sampling")
+    ap.add_argument("--beta", type=float, default=1000.0, help="inverse temperature (--grid ir)")
+    ap.add_argument("--wmax", type=float, default=100.0, help="frequency window (--grid ir)")
+    ap.add_argument("--ir-eps", type=float, default=1e-10, help="basis cut s_l / s_0 (--grid ir)")
     a = ap.parse_args()
 
     import torch
     dev = torch.device("cuda:0")
     t0 = time.time()
     s, tau, w, G0, beta = synth.workload(a.workload, seed=a.seed, lam=a.lam)
+    grid = None
+    if a.grid == "ir":
+        grid = thcsox.thcsox_ir_grid(a.beta, a.wmax, a.ir_eps)
+        beta, tau = a.beta, grid["tau"]
+        w = np.zeros(len(tau))            # the energy comes from the basis expansion
+        G0 = synth.g0_tau(s, tau, beta)
     t_gen = time.time() - t0
     X = torch.from_numpy(s.X).to(dev)
     V = torch.from_numpy(s.V).to(dev)
@@ -56,7 +71,8 @@ def main() -> None:
     torch.cuda.synchronize()
     t0 = time.time()
     plan = thcsox.Plan(X, V, tau, w, beta, precision=a.precision)
-    dyson = thcsox.Dyson(torch.from_numpy(s.F).to(dev), s.mu, tau, beta, a.matsubara)
+    dyson = thcsox.Dyson(torch.from_numpy(s.F).to(dev), s.mu, tau, beta, a.matsubara,
+                         grid=grid)
     torch.cuda.synchronize()
     t_plan = time.time() - t0
     S_out = torch.zeros_like(G)    # Sigma^SOX of the current G
@@ -71,7 +87,7 @@ def main() -> None:
         plan.sigma(G, out=S_out)
         if a.terms == "gf2":
             plan.sigma_direct(G, out=S_out, accumulate=True)   # direct + SOX
-        E_2 = plan.energy(G, S_out)
+        E_2 = plan.energy(G, S_out) if grid is None else plan.energy_basis(G, S_out, grid)
         t2 = time.time()
         used = 1
         if it == 0 or (diis is None and a.damping == 0.0):
@@ -108,6 +124,8 @@ def main() -> None:
     sig = [r["sigma_s"] for r in iters]
     print(json.dumps({"workload": a.workload, "n": s.n, "naux": s.naux, "ntau": len(tau),
                       "lam": a.lam, "precision": a.precision, "terms": a.terms,
+                      "grid": a.grid, "beta": beta,
+                      "nfreq": len(grid["freq_n"]) if grid else a.matsubara,
                       "damping": a.damping,
                       "diis": a.diis, "mu_search": a.mu_search, "iterations": len(iters),
                       "converged": len(iters) > 1 and abs(iters[-1]["dE"]) < a.tol,
