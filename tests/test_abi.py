@@ -81,6 +81,26 @@ def test_plan_argument_checks_without_device(L):
     assert rc == -1 and b"tau_host" in L.thcsox_last_error()
 
 
+def test_sampled_dyson_and_basis_energy_checks_without_device(L):
+    """Argument checks of the sampled-grid Dyson plan and of the basis energy that
+    run before the library touches the device."""
+    out = ctypes.c_void_p()
+    freq = (ctypes.c_int * 3)(0, 4, 9)
+    wf = (ctypes.c_double * (6 * 4))(*([0.0] * 24))
+    wb = (ctypes.c_double * (5 * 6))(*([0.0] * 30))
+    sp = L.thcsox_dyson_plan_sampled
+    assert sp(None, 8, 4, 3, 100.0, 0.0, freq, wf, wb, None, None) == -1
+    assert sp(ctypes.byref(out), 0, 4, 3, 100.0, 0.0, freq, wf, wb, None, None) == -1
+    assert sp(ctypes.byref(out), 8, 8, 3, 100.0, 0.0, freq, wf, wb, None, None) == -1
+    assert b"2 nfreq" in L.thcsox_last_error()
+    bad = (ctypes.c_int * 3)(0, 9, 4)
+    assert sp(ctypes.byref(out), 8, 4, 3, 100.0, 0.0, bad, wf, wb, None, None) == -1
+    assert sp(ctypes.byref(out), 8, 4, 3, 100.0, 0.0, freq, None, wb, None, None) == -1
+    assert out.value is None
+    E = ctypes.c_double()
+    assert L.thcsox_energy_basis(None, None, None, None, None, ctypes.byref(E)) == -1
+
+
 def test_null_handles_rejected(L):
     assert L.thcsox_sigma_sox(None, None, None, None, 0, 1) == -1
     assert L.thcsox_destroy(None) == 0          # destroying nothing is a no-op
