@@ -85,12 +85,14 @@ double kern(double x, double y, double lam) {
 // One-sided Jacobi SVD of the M x N matrix A (column-major, column j at
 // A + j M): column pairs are rotated until orthogonal, so that A V = U diag(s).
 // Returns s and V (N x N, column-major); A is overwritten by U diag(s).
-void jacobi_svd(int M, int N, std::vector<double>& A, std::vector<double>& V,
+// False if a sweep still rotated after the sweep limit (not converged).
+bool jacobi_svd(int M, int N, std::vector<double>& A, std::vector<double>& V,
                 std::vector<double>& s) {
   V.assign((size_t)N * N, 0.0);
   for (int j = 0; j < N; ++j) V[(size_t)j * N + j] = 1.0;
   std::vector<double> nrm(N);
-  for (int sweep = 0; sweep < 80; ++sweep) {
+  bool converged = false;
+  for (int sweep = 0; sweep < 80 && !converged; ++sweep) {
     for (int j = 0; j < N; ++j) {
       double a = 0.0;
       const double* c = &A[(size_t)j * M];
@@ -125,7 +127,7 @@ void jacobi_svd(int M, int N, std::vector<double>& A, std::vector<double>& V,
         nrm[i] = a - t * g;
         nrm[j] = b + t * g;
       }
-    if (!rotated) break;
+    converged = !rotated;
   }
   s.assign(N, 0.0);
   for (int j = 0; j < N; ++j) {
@@ -134,15 +136,17 @@ void jacobi_svd(int M, int N, std::vector<double>& A, std::vector<double>& V,
     for (int r = 0; r < M; ++r) a += c[r] * c[r];
     s[j] = std::sqrt(a);
   }
+  return converged;
 }
 
 // Pseudo-inverse of the M x N row-major matrix B (M >= N, full column rank) by
-// the Jacobi SVD: pinv = V diag(1/s) U^T, returned N x M row-major.
+// the Jacobi SVD: pinv = V diag(1/s) U^T, returned N x M row-major (empty if
+// the SVD did not converge).
 std::vector<double> pinv_svd(const std::vector<double>& B, int M, int N) {
   std::vector<double> A((size_t)M * N), V, s;
   for (int r = 0; r < M; ++r)
     for (int c = 0; c < N; ++c) A[(size_t)c * M + r] = B[(size_t)r * N + c];
-  jacobi_svd(M, N, A, V, s);
+  if (!jacobi_svd(M, N, A, V, s)) return {};
   std::vector<double> P((size_t)N * M, 0.0);
   for (int k = 0; k < N; ++k) {
     if (s[k] == 0.0) continue;
@@ -231,7 +235,8 @@ int build_basis(double beta, double wmax, double eps, Basis& B, int& L) {
       for (int i = 0; i < M; ++i)
         A[(size_t)j * M + i] = std::sqrt(wx[i] * wy[j]) *
                                (kern(B.xh[i], B.y[j], B.lam) + sg * kern(B.xh[i], -B.y[j], B.lam));
-    jacobi_svd(M, N, A, V, s);
+    if (!jacobi_svd(M, N, A, V, s))
+      return set_error(THCSOX_EINVAL, "IR basis: the Jacobi SVD did not converge");
     for (int k = 0; k < N; ++k) {
       Fn f;
       f.parity = par;
@@ -270,7 +275,8 @@ int tau_roots(const Basis& B, int L, std::vector<double>& xr) {
   double fa = B.u(L, xs[0]);
   for (size_t i = 0; i + 1 < xs.size(); ++i) {
     const double fb = B.u(L, xs[i + 1]);
-    if (i > 0 || xs[0] > 0.0 || fa != 0.0) {
+    {
+      // a sign change strictly inside (a zero at x = 0 is the odd-parity root added below)
       if ((fa < 0) != (fb < 0) && fa != 0.0 && fb != 0.0) {
         double a = xs[i], b = xs[i + 1], ga = fa;
         for (int it = 0; it < 200; ++it) {
@@ -351,6 +357,10 @@ int thcsox_ir_create(thcsox_ir_t* out, double beta, double wmax, double eps) {
   for (int k = 0; k < L; ++k)
     for (int l = 0; l < L; ++l) Ut[(size_t)k * L + l] = B.u_tau(l, g->tau[k]);
   g->coef = pinv_svd(Ut, L, L);   // [L][L]
+  if (g->coef.empty()) {
+    delete g;
+    return set_error(THCSOX_EINVAL, "IR basis: the Jacobi SVD of the tau sampling matrix did not converge");
+  }
   // [Re; Im] transform rows: H[j][l] = Re uhat_l(n_j), H[nf + j][l] = Im uhat_l(n_j)
   std::vector<double> H((size_t)2 * nf * L);
   for (int j = 0; j < nf; ++j)
@@ -370,6 +380,10 @@ int thcsox_ir_create(thcsox_ir_t* out, double beta, double wmax, double eps) {
     }
   // backward: coefficients = pinv(H) [Re; Im] F, then F(tau_k) and F(beta^-)
   const std::vector<double> P = pinv_svd(H, 2 * nf, L);   // [L][2 nf]
+  if (P.empty()) {
+    delete g;
+    return set_error(THCSOX_EINVAL, "IR basis: the Jacobi SVD of the frequency sampling matrix did not converge");
+  }
   g->Wb.assign((size_t)(L + 1) * 2 * nf, 0.0);
   for (int k = 0; k <= L; ++k) {
     for (int l = 0; l < L; ++l) {
