@@ -158,6 +158,16 @@ def pole_sigma(n: int, tau: np.ndarray, beta: float, seed: int, npoles: int = 4,
     return out
 
 
+def thc_factors(n: int, naux: int, seed: int):
+    """X ~ N(0, 1/n) [n, naux] and V = L L^T / naux (L ~ N(0, 1)) alone, for
+    cases without an orbital spectrum (e.g. a single spin-orbital)."""
+    rng = np.random.default_rng(seed)
+    X = rng.normal(0.0, math.sqrt(1.0 / n), size=(n, naux))
+    L = rng.standard_normal((naux, naux))
+    V = (L @ L.T) / naux
+    return np.ascontiguousarray(X), np.ascontiguousarray(0.5 * (V + V.T))
+
+
 def random_general_g(n: int, m: int, seed: int, scale: float = 0.3) -> np.ndarray:
     """Non-symmetric dense G[m,n,n] for checks that must not lean on G = G^T."""
     rng = np.random.default_rng(seed)

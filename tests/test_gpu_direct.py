@@ -85,3 +85,26 @@ def test_direct_fullsize_sampled(dev):
     for k in (0, 37):
         ref = od.sigma_direct_thc(s.X, s.V, G[k], G[m - 1 - k])
         assert _rel(S[k].cpu().numpy(), ref) <= 1e-11, k
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp16x2"])
+def test_single_spin_orbital_direct_cancels_sox(dev, precision):
+    """n = 1 (one v, a k row padded to the full stage width, v ranges left empty),
+    naux = 37 (one ragged tile): the SOX term against the oracle, and the direct
+    term equal to minus the SOX term (Pauli: one spin-orbital holds one electron)."""
+    X, V = synth.thc_factors(1, 37, seed=11)
+    G = synth.random_general_g(1, 8, seed=1)
+    tau, w = synth.cheb_tau_grid(8, 100.0)
+    print(f"case n1 naux37 ntau8 {precision}", flush=True)
+    ref = osox.sigma_all_tau(osox.sigma_thc_paper, G, X, V)
+    plan = thcsox.Plan(torch.from_numpy(X).to(dev), torch.from_numpy(V).to(dev), tau, w, 100.0,
+                       precision=precision)
+    Gd = torch.from_numpy(G).to(dev)
+    Sx = plan.sigma(Gd).cpu().numpy()
+    Sd = plan.sigma_direct(Gd).cpu().numpy()
+    plan.close()
+    ex = np.abs(Sx - ref).max() / np.abs(ref).max()
+    canc = np.abs(Sx + Sd).max() / np.abs(ref).max()
+    print(f"  SOX rel err {ex:.2e}  |SOX + direct| / |SOX| {canc:.2e}")
+    tol = 1e-12 if precision == "fp64" else 2e-6
+    assert ex <= tol and canc <= tol

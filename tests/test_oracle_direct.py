@@ -67,3 +67,15 @@ def test_mutants_are_caught(general_case, slip):
     errs = [_rel(_mutant(s.X, s.V, G[k], G[3 - k], slip),
                  od.sigma_direct_bruteforce(v, G[k], G[3 - k])) for k in range(4)]
     assert max(errs) > 1e-3
+
+
+def test_single_spin_orbital_terms_cancel():
+    """One spin-orbital cannot hold two electrons: at second order the direct and
+    the exchange diagrams cancel exactly (Sigma^dir = -Sigma^SOX for n = 1, any G).
+    Pins the relative sign of the two oracles to the Pauli principle."""
+    X, V = synth.thc_factors(1, 37, seed=11)
+    G = synth.random_general_g(1, 8, seed=1)
+    for k in range(8):
+        a = osox.sigma_thc_paper(X, V, G[k], G[7 - k])
+        b = od.sigma_direct_thc(X, V, G[k], G[7 - k])
+        assert abs(a[0, 0] + b[0, 0]) <= 1e-13 * abs(a[0, 0])
