@@ -660,11 +660,10 @@ int thcsox_energy_basis(thcsox_plan_t p, const double* G_dev, const double* Sigm
     if (sign_host[l] != 1.0 && sign_host[l] != -1.0) return fail(THCSOX_EINVAL, "sign must be +-1");
   for (int64_t i = 0; i < mm; ++i)
     if (!std::isfinite(coef_host[i])) return fail(THCSOX_EINVAL, "coef has a non-finite entry");
-  if (p->ebuf == nullptr) {
-    TRY(p->alloc(&p->ebuf, (size_t)(2 * m * nn)));
-    TRY(p->alloc(&p->ecoef, (size_t)(2 * mm)));
-    TRY(p->alloc(&p->esign, (size_t)m));
-  }
+  // allocated on first use; a failed allocation leaves the others for the next call
+  if (p->ebuf == nullptr) TRY(p->alloc(&p->ebuf, (size_t)(2 * m * nn)));
+  if (p->ecoef == nullptr) TRY(p->alloc(&p->ecoef, (size_t)(2 * mm)));
+  if (p->esign == nullptr) TRY(p->alloc(&p->esign, (size_t)m));
   // g = C G with the rows of C reversed, sigma = C Sigma: the trace kernel pairs
   // index k of its first operand with index m-1-k of the second, so it meets
   // g_l with sigma_l
