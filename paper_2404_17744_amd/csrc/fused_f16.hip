@@ -44,7 +44,7 @@ constexpr int KC = 32;         // k per stage (one f16 MFMA)
 constexpr int PANEL = TT * KC; // halves per panel plane
 constexpr int FLUSH16 = 8;     // v per FP32 partial sum of D
 constexpr int NXCD16 = 8;
-constexpr int BAND16 = 4;
+constexpr int BAND16 = 2;   // R blocks per band (measured: 2 beats 1, 3, 4, 5, 6, 8, 15)
 
 typedef _Float16 h4 __attribute__((ext_vector_type(4)));
 
