@@ -9,12 +9,17 @@ reference (it matches the oracle to 1e-10 at n=8, 100 and 300):
 * Sigma(tau) symmetric for the symmetric inputs;
 * the symmetric-D path against the full path;
 * homogeneity Sigma[c G] = c^3 Sigma[G] (c a power of two, so exact up to the
-  rounding of the contraction).
+  rounding of the contraction);
+* sampled Sig_thc elements of the fp16x2 path against the oracle's sequence
+  evaluated one (R, P) pair at a time (which needs only the P and R slices of
+  U), across tile boundaries, both triangles and the ragged last tile
+  (5500 = 42 * 128 + 124): 1e-6 of the largest sampled magnitude.
 """
 import numpy as np
 import pytest
 import torch
 
+from oracle import sox as osox
 from paper_2404_17744_amd import synth, thcsox
 
 pytestmark = pytest.mark.gpu
@@ -75,3 +80,29 @@ def test_paperscale_symmetric_path_and_homogeneity(case):
     S2 = _sigma(case, "fp16x2", scale=2.0)
     # the per-tau power-of-two scaling absorbs the factor: the same bits, times 8
     assert _rel(S2, 8.0 * S_sym) <= 1e-12
+
+
+def test_paperscale_sampled_sig_thc_vs_oracle(case):
+    s, m = case["s"], len(case["tau"])
+    naux = s.naux
+    print(f"case {NAME} fp16x2 Sig_thc k=0,1 vs oracle elements", flush=True)
+    plan = thcsox.Plan(case["X"], case["V"], case["tau"], case["w"], case["beta"],
+                       precision="fp16x2")
+    out = torch.zeros_like(case["G"])
+    St = torch.zeros((2, naux, naux), dtype=torch.float64, device=case["G"].device)
+    plan.sigma(case["G"], 0, 2, thc=True, out=out, out_thc=St)
+    torch.cuda.synchronize()
+    plan.close()
+    last = naux - 1
+    pairs = [(0, 0), (last, last), (last, 0), (0, last), (127, 128), (128, 127),
+             (5376, 17), (17, 5376), (2750, 2750), (1000, 4000), (4000, 1000)]
+    rng = np.random.default_rng(9)
+    pairs += [tuple(int(x) for x in rng.integers(0, naux, 2)) for _ in range(5)]
+    G = case["G"].cpu().numpy()
+    for k in range(2):
+        ref = osox.sig_thc_elements(s.X, s.V, G[k], G[m - 1 - k], pairs)
+        got = St[k].cpu().numpy()
+        vals = np.array([got[R, P] for R, P in pairs])
+        err = float(np.abs(vals - ref).max() / np.abs(ref).max())
+        print(f"  k={k}: rel err {err:.2e} over {len(pairs)} elements")
+        assert err <= 1e-6
