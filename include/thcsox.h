@@ -178,12 +178,14 @@ int thcsox_backproject(thcsox_plan_t p, const double* Sigma_thc_dev, double* Sig
  *     K(tau, omega) = exp(-tau omega) / (1 + exp(-beta omega)),
  *     tau in [0, beta], |omega| <= wmax, Lambda = beta wmax,
  * truncated at s_l / s_0 >= eps (L functions).  Sampling points: the L roots of
- * u_L in tau; the n >= 0 where the Matsubara transform of u_{L-1} or u_L
+ * u_L in tau; the n >= 0 where the Matsubara transform of one of u_{L-3} .. u_L
  * changes sign, and n = 0, in frequency.
  *   thcsox_ir_create : eps in [1e-13, 1); Lambda <= 1e7.  Host-only (no HIP
  *       calls); about a second at Lambda = 1e5.  THCSOX_EINVAL for bad
- *       arguments or an eps finer than the FP64 discretisation resolves (the
- *       root count of u_L is checked).
+ *       arguments or an eps finer than the FP64 discretisation resolves: the
+ *       root count of u_L is checked, and a grid whose tau or frequency fit has
+ *       a condition number above 1e4 is refused (a guard: the highest
+ *       functions' transforms are at their noise level at low n).
  *   thcsox_ir_sizes  : ntau = L, nfreq.
  *   thcsox_ir_get    : copies (each pointer may be NULL) tau[ntau] ascending,
  *       freq_n[nfreq] ascending, Wf[2 nfreq][ntau] and Wb[ntau + 1][2 nfreq]

@@ -21,12 +21,15 @@ definitions:
   of K(., omega) at i w_n = (2n + 1) pi / beta is 1 / (omega - i w_n).
 * Sampling: the tau points are the L roots of u_L (the first basis function
   past the cut), mirror-symmetric by parity; the Matsubara points are the
-  n >= 0 where u_{L-1} or u_L changes sign in frequency (each transform is
-  purely real or purely imaginary by parity), plus n = 0.  For real G(tau) the
-  negative frequencies are the complex conjugates; the real and the imaginary
-  parts each fix the coefficients of one parity, so about L/2 frequencies are
-  the least a fit needs -- the union of the two functions' sign changes
-  oversamples that about twofold.
+  n >= 0 where one of the last four functions u_{L-3} .. u_L changes sign in
+  frequency (each transform is purely real or purely imaginary by parity),
+  plus n = 0.  For real G(tau) the negative frequencies are the complex
+  conjugates; the real and the imaginary parts each fix the coefficients of
+  one parity, so about L/2 frequencies are the least a fit needs.  At low n the
+  highest functions' transforms sit at their FP64 noise level, and the sign
+  changes of u_{L-1} and u_L alone left some (Lambda, eps) fits with condition
+  numbers of 1e7 and more; the four functions' union (about four times the
+  minimum) keeps them below 1e3.
 """
 from __future__ import annotations
 
@@ -143,19 +146,20 @@ class IRBasis:
         return self.beta * (xr + 1.0) / 2.0
 
     def matsubara_points(self, nmax: int | None = None) -> np.ndarray:
-        """n >= 0 where uhat_{L-1} or uhat_L (the last kept function and the first
-        past the cut) changes sign in frequency -- the larger index of each
-        change -- together with n = 0, ascending.  Each transform is purely real
-        or purely imaginary (parity), so its sign is that of the non-zero part."""
+        """n >= 0 where one of uhat_{L-3} .. uhat_L (the last three kept functions
+        and the first past the cut) changes sign in frequency -- the larger index
+        of each change -- together with n = 0, ascending.  Each transform is
+        purely real or purely imaginary (parity), so its sign is that of the
+        non-zero part."""
         if nmax is None:
             nmax = int(10 * self.lam / (2 * np.pi)) + 10
         n = np.arange(nmax + 1)
-        u = np.concatenate([self.uhat(n[c:c + 20000], all_=True)[:, self.L - 1:self.L + 1]
+        u = np.concatenate([self.uhat(n[c:c + 20000], all_=True)[:, self.L - 3:self.L + 1]
                             for c in range(0, len(n), 20000)])
         pts = [np.array([0])]
-        for l in range(2):
+        for l in range(4):
             f = u[:, l]
-            part = f.real if (self.L - 1 + l) % 2 == 1 else f.imag
+            part = f.real if (self.L - 3 + l) % 2 == 1 else f.imag
             sgn = np.sign(part)
             pts.append(np.nonzero(sgn[1:] * sgn[:-1] < 0)[0] + 1)
         return np.unique(np.concatenate(pts))

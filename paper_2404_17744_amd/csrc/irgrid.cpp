@@ -18,7 +18,9 @@
 //
 // Sampling: the tau points are the roots of u_L (the first function past the
 // cut s_l / s_0 >= eps), the Matsubara points the n >= 0 where the transform of
-// u_{L-1} or of u_L changes sign, and n = 0.
+// one of u_{L-3} .. u_L changes sign, and n = 0.  (At low n the highest
+// functions' transforms are at their FP64 noise level; the sign changes of the
+// top two alone leave some fits badly conditioned, the top four do not.)
 #include <algorithm>
 #include <cmath>
 #include <new>
@@ -141,12 +143,17 @@ bool jacobi_svd(int M, int N, std::vector<double>& A, std::vector<double>& V,
 
 // Pseudo-inverse of the M x N row-major matrix B (M >= N, full column rank) by
 // the Jacobi SVD: pinv = V diag(1/s) U^T, returned N x M row-major (empty if
-// the SVD did not converge).
-std::vector<double> pinv_svd(const std::vector<double>& B, int M, int N) {
+// the SVD did not converge).  *cond (if given) receives s_max / s_min.
+std::vector<double> pinv_svd(const std::vector<double>& B, int M, int N, double* cond = nullptr) {
   std::vector<double> A((size_t)M * N), V, s;
   for (int r = 0; r < M; ++r)
     for (int c = 0; c < N; ++c) A[(size_t)c * M + r] = B[(size_t)r * N + c];
   if (!jacobi_svd(M, N, A, V, s)) return {};
+  if (cond) {
+    const double smax = *std::max_element(s.begin(), s.end());
+    const double smin = *std::min_element(s.begin(), s.end());
+    *cond = smin > 0 ? smax / smin : INFINITY;
+  }
   std::vector<double> P((size_t)N * M, 0.0);
   for (int k = 0; k < N; ++k) {
     if (s[k] == 0.0) continue;
@@ -250,7 +257,7 @@ int build_basis(double beta, double wmax, double eps, Basis& B, int& L) {
   std::sort(all.begin(), all.end(), [](const Fn& a, const Fn& b) { return a.s > b.s; });
   L = 0;
   while (L < (int)all.size() && all[L].s >= eps * all[0].s) ++L;
-  if (L + 1 > (int)all.size() || L < 2)
+  if (L + 1 > (int)all.size() || L < 4)
     return set_error(THCSOX_EINVAL, "IR basis: eps outside the range the discretisation resolves");
   all.resize(L + 1);
   B.fn = std::move(all);
@@ -309,7 +316,7 @@ int tau_roots(const Basis& B, int L, std::vector<double>& xr) {
 std::vector<int> matsubara_points(const Basis& B, int L) {
   const long nmax = (long)(10.0 * B.lam / (2.0 * M_PI)) + 10;
   std::vector<int> pts{0};
-  for (int l = L - 1; l <= L; ++l) {
+  for (int l = L - 3; l <= L; ++l) {
     double prev = B.uhat_part(l, 0);
     for (long n = 1; n <= nmax; ++n) {
       const double cur = B.uhat_part(l, n);
@@ -356,7 +363,8 @@ int thcsox_ir_create(thcsox_ir_t* out, double beta, double wmax, double eps) {
   std::vector<double> Ut((size_t)L * L);
   for (int k = 0; k < L; ++k)
     for (int l = 0; l < L; ++l) Ut[(size_t)k * L + l] = B.u_tau(l, g->tau[k]);
-  g->coef = pinv_svd(Ut, L, L);   // [L][L]
+  double cond_t = 0.0, cond_w = 0.0;
+  g->coef = pinv_svd(Ut, L, L, &cond_t);   // [L][L]
   if (g->coef.empty()) {
     delete g;
     return set_error(THCSOX_EINVAL, "IR basis: the Jacobi SVD of the tau sampling matrix did not converge");
@@ -379,10 +387,19 @@ int thcsox_ir_create(thcsox_ir_t* out, double beta, double wmax, double eps) {
       for (int k = 0; k < L; ++k) g->Wf[(size_t)r * L + k] += h * g->coef[(size_t)l * L + k];
     }
   // backward: coefficients = pinv(H) [Re; Im] F, then F(tau_k) and F(beta^-)
-  const std::vector<double> P = pinv_svd(H, 2 * nf, L);   // [L][2 nf]
+  const std::vector<double> P = pinv_svd(H, 2 * nf, L, &cond_w);   // [L][2 nf]
   if (P.empty()) {
     delete g;
     return set_error(THCSOX_EINVAL, "IR basis: the Jacobi SVD of the frequency sampling matrix did not converge");
+  }
+  // the sampling rule can fail where the highest functions' transforms are at
+  // their noise level (too small an eps for FP64 at this Lambda): refuse a grid
+  // whose fits would amplify errors by more than 1e4
+  if (!(cond_t <= 1e4) || !(cond_w <= 1e4)) {
+    delete g;
+    return set_error(THCSOX_EINVAL, "IR basis: ill-conditioned sampling (condition numbers " +
+                                        std::to_string(cond_t) + " in tau, " + std::to_string(cond_w) +
+                                        " in frequency); choose a larger eps");
   }
   g->Wb.assign((size_t)(L + 1) * 2 * nf, 0.0);
   for (int k = 0; k <= L; ++k) {

@@ -1,9 +1,13 @@
 """The library's IR grid generator (host code of libthcsox; no GPU needed)
 against the IR oracle and against closed forms.
 
-* Same basis size, the same Matsubara sampling set, and the same tau points to
-  the accuracy an FP64 singular value expansion fixes them (the roots of u_L,
-  whose singular value is ~1e-10 of the largest: ~1e-8 relative).
+* Same basis size and the same tau points to the accuracy an FP64 singular
+  value expansion fixes them (the roots of u_L, whose singular value is ~1e-10
+  of the largest: ~1e-8 relative).  The Matsubara sampling sets agree except
+  where a sign is decided at the noise level of the highest functions (their
+  transform within 1e-4 of its scale at that n or the one before, e.g. at
+  n = 1, 2 where it is ~1e-6): either choice is a valid sampling point, and
+  the library's own tables are checked against closed forms below.
 * The library's own tables reproduce the single-pole closed forms (transform
   1 / (i w_n - xi); G(tau) and G(beta^-) back from the sampled frequencies), and
   its energy form integrates a particle-hole pole pair exactly.
@@ -17,7 +21,7 @@ import pytest
 from oracle import ir
 from paper_2404_17744_amd import thcsox
 
-PARAMS = [(100.0, 10.0), (1000.0, 100.0)]
+PARAMS = [(10.0, 1.0), (100.0, 10.0), (100.0, 100.0), (1000.0, 100.0)]
 
 
 def _kt(tau, w, beta):
@@ -26,7 +30,8 @@ def _kt(tau, w, beta):
     return np.exp(w * (beta - tau)) / (1 + np.exp(beta * w))
 
 
-@pytest.fixture(scope="module", params=PARAMS, ids=["beta100_L1e3", "beta1000_L1e5"])
+@pytest.fixture(scope="module", params=PARAMS,
+                ids=["beta10_L1e1", "beta100_L1e3", "beta100_L1e4", "beta1000_L1e5"])
 def grids(request):
     beta, wmax = request.param
     g = thcsox.thcsox_ir_grid(beta, wmax, 1e-10)
@@ -38,7 +43,16 @@ def test_same_grid_as_oracle(grids):
     g, b, tau, nf = grids
     assert len(g["tau"]) == b.L
     assert np.abs(g["tau"] - tau).max() <= 1e-7 * b.beta
-    assert set(g["freq_n"].tolist()) == set(nf.tolist())
+    diff = sorted(set(g["freq_n"].tolist()) ^ set(nf.tolist()))
+    assert len(diff) <= 4, diff
+    if diff:
+        L = b.L
+        scale = np.abs(b.uhat(np.arange(2000), all_=True)[:, L - 1:L + 1]).max(axis=0)
+        for n in diff:
+            u = b.uhat(np.array([max(n - 1, 0), n]), all_=True)[:, L - 1:L + 1]
+            part = np.stack([u[:, 0].real if (L - 1) % 2 else u[:, 0].imag,
+                             u[:, 1].real if L % 2 else u[:, 1].imag], axis=1)
+            assert (np.abs(part) <= 1e-4 * scale).any(), (n, part, scale)
     # singular values to the absolute accuracy of an FP64 SVD of the two discretisations
     s_ref = b.s_all[:b.L] * np.sqrt(b.beta * b.wmax / 2)
     assert np.abs(g["sv"] - s_ref).max() <= 1e-13 * s_ref[0]
@@ -81,3 +95,15 @@ def test_argument_errors():
                             (10.0, 1.0, 1.5)]:
         assert L.thcsox_ir_create(ctypes.byref(h), beta, wmax, eps) == -1
     assert L.thcsox_ir_destroy(None) == 0
+
+
+def test_ill_conditioned_sampling_is_refused():
+    """Past what FP64 resolves (here Lambda = 1e6 with eps = 1e-10) the sampling
+    fits would amplify errors by 1e7: the library refuses the grid rather than
+    return it; a larger eps works at the same Lambda."""
+    h = ctypes.c_void_p()
+    L = thcsox.lib()
+    assert L.thcsox_ir_create(ctypes.byref(h), 10000.0, 100.0, 1e-10) == -1
+    assert b"ill-conditioned" in L.thcsox_last_error()
+    g = thcsox.thcsox_ir_grid(10000.0, 100.0, 1e-9)
+    assert len(g["tau"]) > 0
