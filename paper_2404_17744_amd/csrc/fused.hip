@@ -25,13 +25,14 @@ namespace {
 
 constexpr int FLUSH_V = 8;   // v per FP32 partial sum of D before it is added in FP64
 constexpr int NXCD = 8;      // accelerator complex dies of an MI355X
-constexpr int BAND = 4;      // R blocks per band of the tile walk
 
 // MFMA tiles per wave (rows x cols); the workgroup is 2 x 2 waves.  Sized so
-// that two stages of operand panels fit the 160 KiB of LDS.
+// that two stages of operand panels fit the 160 KiB of LDS.  BAND: R blocks per
+// band of the tile walk (measured at n = 300: 1 is 5 % faster than 4 for FP64
+// and FP32, 2 % slower for bf16x3).
 template <int M> struct FusedCfg;
-template <> struct FusedCfg<MODE_F64> { static constexpr int WTI = 2, WTJ = 2; };
-template <> struct FusedCfg<MODE_F32> { static constexpr int WTI = 4, WTJ = 3; };
+template <> struct FusedCfg<MODE_F64> { static constexpr int WTI = 2, WTJ = 2, BAND = 1; };
+template <> struct FusedCfg<MODE_F32> { static constexpr int WTI = 4, WTJ = 3, BAND = 1; };
 #ifndef THCSOX_BF_ROWS
 #define THCSOX_BF_ROWS 3
 #endif
@@ -39,7 +40,7 @@ template <> struct FusedCfg<MODE_F32> { static constexpr int WTI = 4, WTJ = 3; }
 #define THCSOX_BF_COLS 3
 #endif
 template <> struct FusedCfg<MODE_BF16X3> {
-  static constexpr int WTI = THCSOX_BF_ROWS, WTJ = THCSOX_BF_COLS;
+  static constexpr int WTI = THCSOX_BF_ROWS, WTJ = THCSOX_BF_COLS, BAND = 4;
 };
 #ifndef THCSOX_WT_ROWS
 #define THCSOX_WT_ROWS 4
@@ -48,7 +49,7 @@ template <> struct FusedCfg<MODE_BF16X3> {
 #define THCSOX_WT_COLS 3
 #endif
 template <> struct FusedCfg<MODE_F16X2> {
-  static constexpr int WTI = THCSOX_WT_ROWS, WTJ = THCSOX_WT_COLS;
+  static constexpr int WTI = THCSOX_WT_ROWS, WTJ = THCSOX_WT_COLS, BAND = 4;
 };
 
 template <int M, bool AF32>
@@ -81,6 +82,7 @@ __global__ __launch_bounds__(NT) void fused_kernel(FusedArgs f) {
   const int xcd = b % NXCD, local = b / NXCD;
   const int z = xcd + NXCD * (local / tiles);
   const int to = local % tiles;
+  constexpr int BAND = FusedCfg<M>::BAND;
   const int band = to / (BAND * npb);
   const int rb0 = band * BAND, bh = min(BAND, nrb - rb0);
   const int within = to - rb0 * npb;
