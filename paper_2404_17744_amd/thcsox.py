@@ -349,6 +349,9 @@ class Dyson:
             G_out = torch.empty((self.ntau, self.n, self.n), dtype=torch.float64, device=self.device)
         if gamma_out is None:
             gamma_out = torch.empty((self.n, self.n), dtype=torch.float64, device=self.device)
+        _dev64(Sigma, "Sigma", (self.n, self.n), self.ntau, exact=True)
+        _dev64(G_out, "G_out", (self.n, self.n), self.ntau, exact=True)
+        _dev64(gamma_out, "gamma_out", (self.n,), self.n, exact=True)
         thcsox_dyson_step(self.handle, Sigma.data_ptr(), G_out.data_ptr(), gamma_out.data_ptr())
         return G_out, gamma_out
 
@@ -361,6 +364,9 @@ class Dyson:
             G_out = torch.empty((self.ntau, self.n, self.n), dtype=torch.float64, device=self.device)
         if gamma_out is None:
             gamma_out = torch.empty((self.n, self.n), dtype=torch.float64, device=self.device)
+        _dev64(Sigma, "Sigma", (self.n, self.n), self.ntau, exact=True)
+        _dev64(G_out, "G_out", (self.n, self.n), self.ntau, exact=True)
+        _dev64(gamma_out, "gamma_out", (self.n,), self.n, exact=True)
         mu, ev = thcsox_dyson_step_mu(self.handle, Sigma.data_ptr(), float(nelec), float(tol),
                                       float(mu), G_out.data_ptr(), gamma_out.data_ptr())
         return G_out, gamma_out, mu, ev
@@ -458,6 +464,21 @@ class MLP:
             pass
 
 
+def _dev64(t, name: str, tail: tuple, lead: int, exact: bool = False):
+    """Check that t is a contiguous float64 device tensor of shape [lead, *tail]
+    (or [>= lead, *tail] unless exact): the library indexes its arrays by raw
+    pointer, so a short buffer would be written past its end."""
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 \
+            or not t.is_contiguous():
+        raise ValueError(f"{name}: a contiguous float64 device tensor is required")
+    shape = tuple(t.shape)
+    if shape[1:] != tuple(tail) or (shape[0] != lead if exact else shape[0] < lead):
+        want = f"[{lead}{'' if exact else '+'}, {', '.join(str(x) for x in tail)}]"
+        raise ValueError(f"{name}: shape {shape}, expected {want}")
+    return t
+
+
 class Plan:
     """Owns one libthcsox plan; tensors are torch CUDA (HIP) float64 tensors."""
 
@@ -481,11 +502,16 @@ class Plan:
               out=None, out_thc=None):
         import torch
         k_end = self.ntau if k_end is None else k_end
+        nn, aa = (self.n, self.n), (self.naux, self.naux)
+        _dev64(G, "G", nn, self.ntau, exact=True)
         if out is None:
             out = torch.zeros((self.ntau, self.n, self.n), dtype=torch.float64, device=self.device)
+        _dev64(out, "out", nn, k_end)
         if thc and out_thc is None:
             out_thc = torch.zeros((self.ntau, self.naux, self.naux), dtype=torch.float64,
                                   device=self.device)
+        if thc:
+            _dev64(out_thc, "out_thc", aa, k_end)
         thcsox_sigma_sox(self.handle, G.data_ptr(), out.data_ptr(),
                          out_thc.data_ptr() if thc else None, k_begin, k_end)
         return (out, out_thc) if thc else out
@@ -496,25 +522,35 @@ class Plan:
         accumulate=True adds it to `out` (e.g. onto the SOX term)."""
         import torch
         k_end = self.ntau if k_end is None else k_end
+        _dev64(G, "G", (self.n, self.n), self.ntau, exact=True)
         if out is None:
             out = torch.zeros((self.ntau, self.n, self.n), dtype=torch.float64, device=self.device)
+        _dev64(out, "out", (self.n, self.n), k_end)
         _check(lib().thcsox_sigma_direct(self.handle, G.data_ptr(), out.data_ptr(), k_begin, k_end,
                                          1 if accumulate else 0))
         return out
 
     def energy(self, G, Sigma) -> float:
+        _dev64(G, "G", (self.n, self.n), self.ntau, exact=True)
+        _dev64(Sigma, "Sigma", (self.n, self.n), self.ntau, exact=True)
         return thcsox_energy(self.handle, G.data_ptr(), Sigma.data_ptr())
 
     def energy_basis(self, G, Sigma, grid: dict) -> float:
         """The energy on an IR grid (thcsox_ir_grid): the basis-coefficient form."""
+        _dev64(G, "G", (self.n, self.n), self.ntau, exact=True)
+        _dev64(Sigma, "Sigma", (self.n, self.n), self.ntau, exact=True)
+        if np.shape(grid["coef"]) != (self.ntau, self.ntau) or len(grid["sign"]) != self.ntau:
+            raise ValueError("the grid's basis size differs from the plan's tau count")
         return thcsox_energy_basis(self.handle, G.data_ptr(), Sigma.data_ptr(), grid["coef"],
                                    grid["sign"])
 
     def backproject(self, Sigma_thc, k_begin: int = 0, k_end: int | None = None, out=None):
         import torch
         k_end = self.ntau if k_end is None else k_end
+        _dev64(Sigma_thc, "Sigma_thc", (self.naux, self.naux), k_end)
         if out is None:
             out = torch.zeros((self.ntau, self.n, self.n), dtype=torch.float64, device=self.device)
+        _dev64(out, "out", (self.n, self.n), k_end)
         thcsox_backproject(self.handle, Sigma_thc.data_ptr(), out.data_ptr(), k_begin, k_end)
         return out
 

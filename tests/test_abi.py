@@ -120,3 +120,20 @@ def test_no_undefined_library_symbols(L):
                          text=True, check=True).stdout
     bad = [l for l in out.splitlines() if "thcsox" in l]
     assert not bad, bad
+
+
+def test_binding_rejects_bad_tensors():
+    """The binding checks device, dtype, contiguity and shape before passing raw
+    pointers on (the library would index a short buffer past its end)."""
+    import torch
+    t = torch.zeros((3, 4, 4), dtype=torch.float64)          # host tensor
+    with pytest.raises(ValueError, match="device tensor"):
+        thcsox._dev64(t, "G", (4, 4), 3, exact=True)
+    if not torch.cuda.is_available():
+        return
+    g = t.cuda()
+    thcsox._dev64(g, "G", (4, 4), 3, exact=True)
+    with pytest.raises(ValueError, match="shape"):
+        thcsox._dev64(g, "out_thc", (4, 4), 5)
+    with pytest.raises(ValueError, match="device tensor"):
+        thcsox._dev64(g.float(), "G", (4, 4), 3)
