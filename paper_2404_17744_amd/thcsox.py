@@ -587,6 +587,8 @@ class Plan:
 def mix(alpha: float, sigma_out, sigma_io, stream=None) -> None:
     """sigma_io = alpha sigma_io + (1 - alpha) sigma_out (float64 device tensors)."""
     import torch
+    _dev64(sigma_io, "sigma_io", tuple(sigma_io.shape[1:]), sigma_io.shape[0], exact=True)
+    _dev64(sigma_out, "sigma_out", tuple(sigma_io.shape[1:]), sigma_io.shape[0], exact=True)
     st = stream if stream is not None else torch.cuda.current_stream(sigma_io.device)
     thcsox_mix(sigma_io.numel(), float(alpha), sigma_out.data_ptr(), sigma_io.data_ptr(),
                st.cuda_stream)
@@ -598,10 +600,14 @@ class Diis:
     def __init__(self, like, depth: int = 6, stream=None):
         import torch
         self.stream = stream if stream is not None else torch.cuda.current_stream(like.device)
+        self.shape = tuple(like.shape)
         self.handle = thcsox_diis_create(like.numel(), depth, self.stream.cuda_stream)
 
     def step(self, sigma_in, sigma_out, sigma_next) -> int:
         """Writes the extrapolated input into sigma_next; returns the entries used."""
+        for name, t in (("sigma_in", sigma_in), ("sigma_out", sigma_out),
+                        ("sigma_next", sigma_next)):
+            _dev64(t, name, self.shape[1:], self.shape[0], exact=True)
         return thcsox_diis_step(self.handle, sigma_in.data_ptr(), sigma_out.data_ptr(),
                                 sigma_next.data_ptr())
 
