@@ -429,12 +429,16 @@ class MLP:
 
     def forward(self, x, out=None):
         import torch
+        _dev64(x, "x", (self.m,), x.shape[0], exact=True, f32=True)
         if out is None:
             out = torch.empty_like(x)
+        _dev64(out, "out", (self.m,), x.shape[0], exact=True, f32=True)
         _check(lib().thcsox_mlp_forward(self.handle, x.data_ptr(), out.data_ptr(), x.shape[0]))
         return out
 
     def gradients(self, x, t):
+        _dev64(x, "x", (self.m,), x.shape[0], exact=True, f32=True)
+        _dev64(t, "t", (self.m,), x.shape[0], exact=True, f32=True)
         g = np.empty(self.nparam, dtype=np.float32)
         loss = ctypes.c_double()
         _check(lib().thcsox_mlp_gradients(self.handle, x.data_ptr(), t.data_ptr(), x.shape[0],
@@ -442,6 +446,8 @@ class MLP:
         return loss.value, self._unpack(g)
 
     def train_step(self, x, t, lr: float, want_loss: bool = True):
+        _dev64(x, "x", (self.m,), x.shape[0], exact=True, f32=True)
+        _dev64(t, "t", (self.m,), x.shape[0], exact=True, f32=True)
         loss = ctypes.c_double()
         _check(lib().thcsox_mlp_train_step(self.handle, x.data_ptr(), t.data_ptr(), x.shape[0],
                                            lr, ctypes.byref(loss) if want_loss else None))
@@ -464,14 +470,16 @@ class MLP:
             pass
 
 
-def _dev64(t, name: str, tail: tuple, lead: int, exact: bool = False):
-    """Check that t is a contiguous float64 device tensor of shape [lead, *tail]
-    (or [>= lead, *tail] unless exact): the library indexes its arrays by raw
-    pointer, so a short buffer would be written past its end."""
+def _dev64(t, name: str, tail: tuple, lead: int, exact: bool = False, f32: bool = False):
+    """Check that t is a contiguous float64 (float32 with f32) device tensor of
+    shape [lead, *tail] (or [>= lead, *tail] unless exact): the library indexes
+    its arrays by raw pointer, so a short buffer would be written past its end."""
     import torch
-    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 \
+    dt = torch.float32 if f32 else torch.float64
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dt \
             or not t.is_contiguous():
-        raise ValueError(f"{name}: a contiguous float64 device tensor is required")
+        raise ValueError(f"{name}: a contiguous {'float32' if f32 else 'float64'} device tensor "
+                         "is required")
     shape = tuple(t.shape)
     if shape[1:] != tuple(tail) or (shape[0] != lead if exact else shape[0] < lead):
         want = f"[{lead}{'' if exact else '+'}, {', '.join(str(x) for x in tail)}]"
