@@ -19,6 +19,7 @@
 #include <complex>
 #include <map>
 #include <mutex>
+#include <new>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -625,7 +626,8 @@ int dyson_create(thcsox_dyson_t* out, int n, int m, int nw, double beta, double 
     (void)hipGetLastError();
     return dfail(THCSOX_ENOTDEV, "F_dev is not device memory");
   }
-  auto* d = new thcsox_dyson_s();
+  auto* d = new (std::nothrow) thcsox_dyson_s();
+  if (d == nullptr) return dfail(THCSOX_ENOMEM, "host allocation failed");
   d->n = n; d->m = m; d->nw = nw; d->beta = beta; d->mu = mu;
   while (d->panel > 1 && (int64_t)d->panel * n > GJ_LDS) d->panel /= 2;
   d->stream = static_cast<hipStream_t>(hip_stream);
@@ -681,10 +683,14 @@ int thcsox_dyson_plan(thcsox_dyson_t* out, int n, int ntau, int n_matsubara, dou
     if (std::fabs(tau_host[k] - 0.5 * beta * (1.0 + x)) > 1e-12 * beta)
       return dfail(THCSOX_EINVAL, "tau grid is not the Chebyshev-root grid");
   }
-  const Tables& tb = tables_for(ntau, n_matsubara, beta);
-  std::vector<double> wf(n_matsubara);
-  for (int j = 0; j < n_matsubara; ++j) wf[j] = (2.0 * j + 1.0) * M_PI / beta;
-  return dyson_create(out, n, ntau, n_matsubara, beta, mu, wf, tb.Wf, tb.Wb, F_dev, hip_stream);
+  try {   // host tables: no exception may cross the C interface
+    const Tables& tb = tables_for(ntau, n_matsubara, beta);
+    std::vector<double> wf(n_matsubara);
+    for (int j = 0; j < n_matsubara; ++j) wf[j] = (2.0 * j + 1.0) * M_PI / beta;
+    return dyson_create(out, n, ntau, n_matsubara, beta, mu, wf, tb.Wf, tb.Wb, F_dev, hip_stream);
+  } catch (const std::bad_alloc&) {
+    return dfail(THCSOX_ENOMEM, "host allocation failed");
+  }
 }
 
 int thcsox_dyson_plan_sampled(thcsox_dyson_t* out, int n, int ntau, int nfreq, double beta,
@@ -703,17 +709,21 @@ int thcsox_dyson_plan_sampled(thcsox_dyson_t* out, int n, int ntau, int nfreq, d
   for (int j = 0; j < nfreq; ++j)
     if (freq_n_host[j] < 0 || (j > 0 && freq_n_host[j] <= freq_n_host[j - 1]))
       return dfail(THCSOX_EINVAL, "freq_n must be ascending and >= 0");
-  std::vector<double> Wf(Wf_host, Wf_host + (size_t)2 * nfreq * ntau);
-  std::vector<double> Wb(Wb_host, Wb_host + (size_t)(ntau + 1) * 2 * nfreq);
-  for (double v : Wf)
-    if (!std::isfinite(v)) return dfail(THCSOX_EINVAL, "Wf has a non-finite entry");
-  for (double v : Wb)
-    if (!std::isfinite(v)) return dfail(THCSOX_EINVAL, "Wb has a non-finite entry");
-  // the plan's last table row gives gamma = -G(beta^-) directly
-  for (size_t j = (size_t)ntau * 2 * nfreq; j < Wb.size(); ++j) Wb[j] = -Wb[j];
-  std::vector<double> wf(nfreq);
-  for (int j = 0; j < nfreq; ++j) wf[j] = (2.0 * freq_n_host[j] + 1.0) * M_PI / beta;
-  return dyson_create(out, n, ntau, nfreq, beta, mu, wf, Wf, Wb, F_dev, hip_stream);
+  try {   // host copies of the tables: no exception may cross the C interface
+    std::vector<double> Wf(Wf_host, Wf_host + (size_t)2 * nfreq * ntau);
+    std::vector<double> Wb(Wb_host, Wb_host + (size_t)(ntau + 1) * 2 * nfreq);
+    for (double v : Wf)
+      if (!std::isfinite(v)) return dfail(THCSOX_EINVAL, "Wf has a non-finite entry");
+    for (double v : Wb)
+      if (!std::isfinite(v)) return dfail(THCSOX_EINVAL, "Wb has a non-finite entry");
+    // the plan's last table row gives gamma = -G(beta^-) directly
+    for (size_t j = (size_t)ntau * 2 * nfreq; j < Wb.size(); ++j) Wb[j] = -Wb[j];
+    std::vector<double> wf(nfreq);
+    for (int j = 0; j < nfreq; ++j) wf[j] = (2.0 * freq_n_host[j] + 1.0) * M_PI / beta;
+    return dyson_create(out, n, ntau, nfreq, beta, mu, wf, Wf, Wb, F_dev, hip_stream);
+  } catch (const std::bad_alloc&) {
+    return dfail(THCSOX_ENOMEM, "host allocation failed");
+  }
 }
 
 int thcsox_dyson_step(thcsox_dyson_t d, const double* Sigma_dev, double* G_dev, double* gamma_dev) {

@@ -334,12 +334,8 @@ std::vector<int> matsubara_points(const Basis& B, int L) {
 
 using namespace thcsox;
 
-extern "C" {
-
-int thcsox_ir_create(thcsox_ir_t* out, double beta, double wmax, double eps) {
-  clear_error();
-  if (out == nullptr) return set_error(THCSOX_EINVAL, "out is NULL");
-  *out = nullptr;
+namespace {
+int ir_create(thcsox_ir_t* out, double beta, double wmax, double eps) {
   if (!(beta > 0.0) || !(wmax > 0.0) || !(eps >= 1e-13 && eps < 1.0) || !(beta * wmax <= 1e7))
     return set_error(THCSOX_EINVAL, "need beta > 0, wmax > 0, beta wmax <= 1e7, 1e-13 <= eps < 1");
   Basis B;
@@ -416,6 +412,21 @@ int thcsox_ir_create(thcsox_ir_t* out, double beta, double wmax, double eps) {
   }
   *out = g;
   return 0;
+}
+}  // namespace
+
+extern "C" {
+
+int thcsox_ir_create(thcsox_ir_t* out, double beta, double wmax, double eps) {
+  clear_error();
+  if (out == nullptr) return set_error(THCSOX_EINVAL, "out is NULL");
+  *out = nullptr;
+  // host vectors throughout: no exception may cross the C interface
+  try {
+    return ir_create(out, beta, wmax, eps);
+  } catch (const std::bad_alloc&) {
+    return set_error(THCSOX_ENOMEM, "host allocation failed");
+  }
 }
 
 int thcsox_ir_sizes(thcsox_ir_t g, int* ntau, int* nfreq) {

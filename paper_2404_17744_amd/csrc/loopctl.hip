@@ -3,6 +3,7 @@
 // self-energy residual r = Sigma_out - Sigma_in.  Device arrays of doubles; the
 // (depth + 1)^2 DIIS system is solved on the host.
 #include <hip/hip_runtime.h>
+#include <new>
 
 #include <algorithm>
 #include <cmath>
@@ -172,7 +173,7 @@ int thcsox_mix(int64_t len, double alpha, const double* sigma_out, double* sigma
   return 0;
 }
 
-int thcsox_diis_create(thcsox_diis_t* out, int64_t len, int depth, void* hip_stream) {
+static int thcsox_diis_create_impl(thcsox_diis_t* out, int64_t len, int depth, void* hip_stream) {
   clear_error();
   if (out == nullptr) return lfail(THCSOX_EINVAL, "out is NULL");
   *out = nullptr;
@@ -205,7 +206,15 @@ int thcsox_diis_create(thcsox_diis_t* out, int64_t len, int depth, void* hip_str
   return 0;
 }
 
-int thcsox_diis_step(thcsox_diis_t d, const double* sigma_in, const double* sigma_out,
+int thcsox_diis_create(thcsox_diis_t* out, int64_t len, int depth, void* hip_stream) {
+  try {   // host containers: no exception may cross the C interface
+    return thcsox_diis_create_impl(out, len, depth, hip_stream);
+  } catch (const std::bad_alloc&) {
+    return lfail(THCSOX_ENOMEM, "host allocation failed");
+  }
+}
+
+static int thcsox_diis_step_impl(thcsox_diis_t d, const double* sigma_in, const double* sigma_out,
                      double* sigma_next, int* n_used_out) {
   clear_error();
   if (d == nullptr || sigma_in == nullptr || sigma_out == nullptr || sigma_next == nullptr)
@@ -262,6 +271,15 @@ int thcsox_diis_step(thcsox_diis_t d, const double* sigma_in, const double* sigm
   LTRY(hipStreamSynchronize(s));
   if (n_used_out) *n_used_out = k;
   return 0;
+}
+
+int thcsox_diis_step(thcsox_diis_t d, const double* sigma_in, const double* sigma_out,
+                     double* sigma_next, int* n_used_out) {
+  try {   // host containers: no exception may cross the C interface
+    return thcsox_diis_step_impl(d, sigma_in, sigma_out, sigma_next, n_used_out);
+  } catch (const std::bad_alloc&) {
+    return lfail(THCSOX_ENOMEM, "host allocation failed");
+  }
 }
 
 int thcsox_diis_destroy(thcsox_diis_t d) {

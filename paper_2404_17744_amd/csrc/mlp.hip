@@ -10,6 +10,7 @@
 // Weights, activations and accumulation are FP32; the GEMMs run on FP32 matrix
 // cores.  Parameters are one packed array: W1, b1, W2, b2, W3, b3.
 #include <hip/hip_runtime.h>
+#include <new>
 
 #include <cmath>
 #include <string>
@@ -321,7 +322,7 @@ int backward(thcsox_mlp_s* q, const float* x, const float* t, int B) {
 
 extern "C" {
 
-int thcsox_mlp_create(thcsox_mlp_t* out, int m, int hidden, int max_batch,
+static int thcsox_mlp_create_impl(thcsox_mlp_t* out, int m, int hidden, int max_batch,
                       const float* params_host, void* hip_stream) {
   clear_error();
   if (out == nullptr || params_host == nullptr) return set_error(THCSOX_EINVAL, "NULL argument");
@@ -356,6 +357,15 @@ int thcsox_mlp_create(thcsox_mlp_t* out, int m, int hidden, int max_batch,
   }
   *out = q;
   return 0;
+}
+
+int thcsox_mlp_create(thcsox_mlp_t* out, int m, int hidden, int max_batch,
+                      const float* params_host, void* hip_stream) {
+  try {   // host containers: no exception may cross the C interface
+    return thcsox_mlp_create_impl(out, m, hidden, max_batch, params_host, hip_stream);
+  } catch (const std::bad_alloc&) {
+    return set_error(THCSOX_ENOMEM, "host allocation failed");
+  }
 }
 
 int thcsox_mlp_forward(thcsox_mlp_t q, const float* x_dev, float* y_dev, int batch) {

@@ -667,7 +667,12 @@ int thcsox_energy_basis(thcsox_plan_t p, const double* G_dev, const double* Sigm
   // g = C G with the rows of C reversed, sigma = C Sigma: the trace kernel pairs
   // index k of its first operand with index m-1-k of the second, so it meets
   // g_l with sigma_l
-  std::vector<double> c2((size_t)(2 * mm));
+  std::vector<double> c2;
+  try {   // no exception may cross the C interface
+    c2.resize((size_t)(2 * mm));
+  } catch (const std::bad_alloc&) {
+    return fail(THCSOX_ENOMEM, "host allocation failed");
+  }
   for (int l = 0; l < m; ++l)
     for (int k = 0; k < m; ++k) {
       c2[(size_t)(m - 1 - l) * m + k] = coef_host[(size_t)l * m + k];
