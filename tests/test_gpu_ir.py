@@ -1,5 +1,5 @@
 """GPU parity on the IR sampling grids (beta = 1000, Lambda = 1e5, the paper's
-production grid): the library's grids and tables drive the Dyson step, the SOX
+production grid, and beta = 100, Lambda = 1e4): the library's grids and tables drive the Dyson step, the SOX
 evaluation and the energy; the oracle runs the same steps on its own grids.
 
 The two grids are the same to the accuracy an FP64 singular value expansion
@@ -19,20 +19,22 @@ from oracle import sox as osox
 from paper_2404_17744_amd import synth, thcsox
 
 pytestmark = pytest.mark.gpu
-BETA, WMAX = 1000.0, 100.0
 
 
-@pytest.fixture(scope="module")
-def grids():
-    g = thcsox.thcsox_ir_grid(BETA, WMAX, 1e-10)
-    b = oir.IRBasis(BETA, WMAX, 1e-10)
+@pytest.fixture(scope="module", params=[(1000.0, 100.0), (100.0, 100.0)],
+                ids=["beta1000_L1e5", "beta100_L1e4"])
+def grids(request):
+    beta, wmax = request.param
+    g = thcsox.thcsox_ir_grid(beta, wmax, 1e-10)
+    b = oir.IRBasis(beta, wmax, 1e-10)
     tau_o, nf_o = b.tau_points(), b.matsubara_points()
     Wf_o, Wb_o = oir.transforms(b, tau_o, nf_o)
-    return g, dict(b=b, tau=tau_o, nf=nf_o, Wf=Wf_o, Wb=Wb_o)
+    return g, dict(b=b, tau=tau_o, nf=nf_o, Wf=Wf_o, Wb=Wb_o, beta=beta)
 
 
 def test_ir_dyson_sigma0_is_g0(dev, grids):
-    g, _ = grids
+    g, o = grids
+    BETA = o["beta"]
     s = synth.make_system(12, 48, seed=4)
     print(f"case IR dyson sigma=0 n12 L{len(g['tau'])} nf{len(g['freq_n'])}", flush=True)
     F = torch.from_numpy(s.F).to(dev)
@@ -51,6 +53,7 @@ def test_ir_dyson_sigma0_is_g0(dev, grids):
 
 def test_ir_dyson_step_vs_oracle(dev, grids):
     g, o = grids
+    BETA = o["beta"]
     s = synth.make_system(16, 64, seed=5)
     print("case IR dyson pole-sum sigma n16 seed 5", flush=True)
     S_lib = synth.pole_sigma(16, g["tau"], BETA, seed=6)
@@ -73,6 +76,7 @@ def test_ir_dyson_step_vs_oracle(dev, grids):
 @pytest.mark.parametrize("precision", ["fp64", "fp16x2"])
 def test_ir_sox_energy_vs_oracle(dev, grids, precision):
     g, o = grids
+    BETA = o["beta"]
     s = synth.make_system(20, 80, seed=7, lam=0.2)
     print(f"case IR SOX energy n20 naux80 seed 7 {precision}", flush=True)
     G_lib = synth.g0_tau(s, g["tau"], BETA)
