@@ -77,6 +77,26 @@ def test_dyson_step_pivoting_ragged_panels(dev):
     assert _rel(gam.cpu().numpy(), gam_ref) < 1e-10
 
 
+@pytest.mark.parametrize("n", [1153, 2305])
+def test_dyson_narrow_panels(dev, n):
+    """Past n = 1152 an n x 8 panel of a frequency's matrix no longer fits LDS, so
+    the inversion takes 4-column (n = 1153) and 2-column (n = 2305) panels, the
+    last one a single column; a large random Sigma forces row interchanges."""
+    s = synth.make_system(n, 8, seed=31)
+    tau, w = synth.cheb_tau_grid(4, 100.0)
+    rng = np.random.default_rng(32)
+    S = 40.0 * np.abs(s.F).max() * rng.standard_normal((4, n, n))
+    print(f"case dyson n{n} ntau4 nw2 random Sigma", flush=True)
+    Tm = otr.cheb_to_matsubara(4, 2, 100.0)
+    G_ref, gam_ref, _ = otr.loop_step(s.F, s.mu, 100.0, S, Tm)
+    d = thcsox.Dyson(torch.from_numpy(s.F).to(dev), s.mu, tau, 100.0, 2)
+    G, gam = d.step(torch.from_numpy(S).to(dev))
+    d.close()
+    eg, eh = _rel(G.cpu().numpy(), G_ref), _rel(gam.cpu().numpy(), gam_ref)
+    print(f"  G rel {eg:.2e}  gamma rel {eh:.2e}")
+    assert eg < 1e-10 and eh < 1e-10
+
+
 def test_dyson_nonfinite_sigma_is_an_error(dev):
     s = synth.make_system(12, 40, seed=3)
     tau, w = synth.cheb_tau_grid(8, 100.0)
