@@ -78,9 +78,11 @@ typedef struct thcsox_plan_s* thcsox_plan_t;
  *   X_dev[n][naux], V_dev[naux][naux] : THC factors (V symmetric).  Copied:
  *                    the caller may free them when this call returns.
  *   precision      : one of THCSOX_FP64 .. THCSOX_FP16X2.
- *   workspace_limit: upper bound in bytes on everything the plan allocates
- *                    (0 = no bound).  The number of tau points processed per
- *                    batch shrinks to fit; THCSOX_ENOMEM if one does not fit.
+ *   workspace_limit: upper bound in bytes on everything the plan allocates,
+ *                    the temporaries of building U (freed before this call
+ *                    returns) included (0 = no bound).  The number of tau
+ *                    points processed per batch shrinks to fit; THCSOX_ENOMEM
+ *                    if one does not fit.
  *   hip_stream     : hipStream_t to queue work on (NULL = null stream).
  * Synchronises the stream before returning.  The plan owns all its memory. */
 int thcsox_plan(thcsox_plan_t* out, int n, int naux, int ntau, double beta,

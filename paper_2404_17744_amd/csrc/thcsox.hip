@@ -498,10 +498,16 @@ int thcsox_plan(thcsox_plan_t* out, int n, int naux, int ntau, double beta,
     double cap = 2.0e9;
     if (workspace_limit > 0) {
       // what the plan keeps besides the batch buffers, plus 1 MiB of slack
+      // the U build's temporaries (Khatri-Rao chunk, and its FP64 result in the split
+      // modes) are allocated last and freed after the build, so they count too
+      const double per_q = 8.0 * n * naux;
+      const double qb = std::max(1.0, std::min((double)n, std::floor((double)(size_t(256) << 20) / per_q)));
+      const double temps = qb * per_q * (precision == THCSOX_FP64 ? 1.0 : 2.0);
       const double fixed = 8.0 * ((double)n * naux + 7.0 * ntau + 2.0) +
                            (double)p->np * p->esize * naux * n * ldk +
                            (p->np > 1 ? 4.0 : (double)p->esize) * n * naux * ldk +
-                           (p->dpart_f32 ? 4.0 : 8.0) * p->vsplit * (double)naux * naux + (1 << 20);
+                           (p->dpart_f32 ? 4.0 : 8.0) * p->vsplit * (double)naux * naux +
+                           temps + (1 << 20);
       cap = std::min(cap, (double)workspace_limit - fixed);
     }
     p->tb = (int)std::max(1.0, std::min({16.0, (double)ntau, std::floor(cap / per_tau)}));

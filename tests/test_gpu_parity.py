@@ -112,6 +112,41 @@ def test_tau_slices_compose(dev):
     plan.close()
 
 
+def test_workspace_limit_shrinks_the_tau_batch(dev):
+    """A workspace limit below what the default tau batch needs makes the plan
+    take fewer tau points per batch; the FP64 result is bit-identical (batching
+    only groups independent tau points)."""
+    s = synth.make_system(70, 150, seed=3)
+    tau, w = synth.cheb_tau_grid(8, 100.0)
+    G = synth.g0_tau(s, tau, 100.0)
+    X = torch.from_numpy(s.X).to(dev); V = torch.from_numpy(s.V).to(dev)
+    Gd = torch.from_numpy(G).to(dev)
+    print("case n70 naux150 ntau8 fp64 workspace limit", flush=True)
+    plan = thcsox.Plan(X, V, tau, w, 100.0, precision="fp64")
+    full, info = plan.sigma(Gd), plan.info()
+    torch.cuda.synchronize()
+    plan.close()
+    small = None
+    for frac in np.arange(1.4, 0.5, -0.02):
+        try:
+            p2 = thcsox.Plan(X, V, tau, w, 100.0, precision="fp64",
+                             workspace_limit=int(frac * info["bytes"]))
+        except thcsox.ThcsoxError as e:
+            assert e.code == -2     # ENOMEM: the limit is below what one tau point needs
+            continue
+        if p2.info()["tau_batch"] < info["tau_batch"]:
+            small = p2
+            break
+        p2.close()
+    assert small is not None, "no limit shrank the batch"
+    print(f"  tau batch {info['tau_batch']} -> {small.info()['tau_batch']}")
+    assert small.info()["bytes"] <= int(frac * info["bytes"])
+    got = small.sigma(Gd)
+    torch.cuda.synchronize()
+    small.close()
+    assert torch.equal(full, got)
+
+
 def test_errors(dev):
     s, tau, w, G, beta = synth.workload("sox_n8_naux32_ntau12", seed=0)
     X = torch.from_numpy(s.X).to(dev); V = torch.from_numpy(s.V).to(dev)
