@@ -13,6 +13,9 @@ literal six-index definition elsewhere).
   term carries G(tau) or takes it as G(beta - tau)); the other points match the
   oracle and nothing turns into NaN (a zero maximum sets no scale).  G = 0
   everywhere gives Sigma = 0 and E = 0 exactly.
+* The GF2 direct term on the same shapes (FP64, 1e-12), and the Dyson step at
+  n = 1, 2 and 9 against the oracle's transforms and inversion (1e-10, as the
+  other Dyson tests).
 
 Bars as in the other parity tests: 1e-12 of max |Sigma| in FP64 (these sums have
 at most a few hundred terms), 2e-6 on the split paths; energies to the same
@@ -25,8 +28,10 @@ import numpy as np
 import pytest
 import torch
 
+from oracle import direct as od
 from oracle import energy as oenergy
 from oracle import sox as osox
+from oracle import transforms as otr
 from paper_2404_17744_amd import synth, thcsox
 
 pytestmark = pytest.mark.gpu
@@ -105,3 +110,46 @@ def test_zero_g_everywhere(dev, precision):
     G[:] = 0.0
     S, E, _ = _gpu(dev, X, V, G, tau, w, precision)
     assert not S.any() and E == 0.0
+
+
+# the GF2 direct term (FP64 in every plan precision) on the same shapes
+@pytest.mark.parametrize("shape", SHAPES, ids=[f"n{a}_naux{b}_ntau{c}" for a, b, c in SHAPES])
+def test_direct_edge_shapes(dev, shape):
+    n, naux, ntau = shape
+    print(f"case direct n{n} naux{naux} ntau{ntau} general", flush=True)
+    X, V, G, tau, w = _inputs(n, naux, ntau, False, seed=40 + n + naux)
+    ref = osox.sigma_all_tau(od.sigma_direct_thc, G, X, V)
+    plan = thcsox.Plan(torch.from_numpy(X).to(dev), torch.from_numpy(V).to(dev), tau, w, BETA,
+                       precision="fp64")
+    S = plan.sigma_direct(torch.from_numpy(G).to(dev))
+    torch.cuda.synchronize()
+    S = S.cpu().numpy()
+    plan.close()
+    err = float(np.abs(S - ref).max() / np.abs(ref).max())
+    print(f"  rel err {err:.2e}", flush=True)
+    assert err <= 1e-12
+
+
+# the Dyson step: a single orbital, two, and n = 9 (one 8-column panel and a
+# 1-column one); a random Sigma 20 times the spread of F forces row interchanges
+@pytest.mark.parametrize("n", [1, 2, 9])
+def test_dyson_edge_sizes(dev, n):
+    ntau, nw = 8, 16
+    rng = np.random.default_rng(60 + n)
+    A = rng.standard_normal((n, n))
+    F = 0.5 * (A + A.T)
+    mu = 0.05
+    tau, _ = synth.cheb_tau_grid(ntau, BETA)
+    S = 20.0 * max(1.0, np.abs(F).max()) * rng.standard_normal((ntau, n, n))
+    print(f"case dyson n{n} ntau{ntau} nw{nw} random Sigma", flush=True)
+    Tm = otr.cheb_to_matsubara(ntau, nw, BETA)
+    G_ref, gam_ref, _ = otr.loop_step(F, mu, BETA, S, Tm)
+    d = thcsox.Dyson(torch.from_numpy(F).to(dev), mu, tau, BETA, nw)
+    G, gam = d.step(torch.from_numpy(S).to(dev))
+    torch.cuda.synchronize()
+    G, gam = G.cpu().numpy(), gam.cpu().numpy()
+    d.close()
+    eg = float(np.abs(G - G_ref).max() / np.abs(G_ref).max())
+    ea = float(np.abs(gam - gam_ref).max() / np.abs(gam_ref).max())
+    print(f"  G rel err {eg:.2e}  gamma rel err {ea:.2e}", flush=True)
+    assert eg < 1e-10 and ea < 1e-10
