@@ -13,6 +13,8 @@
   to the MP2-exchange limit elsewhere).
 * Planted slips (a dropped conjugate/sign in the transform, the parity factor
   of the energy form) are caught.
+* Re-expansion at other tau points (``evaluate_at``) gives a single pole's
+  closed form between the sampling points and near both ends.
 """
 import numpy as np
 import pytest
@@ -142,3 +144,24 @@ def test_dyson_step_sampled_reproduces_g0():
     assert np.abs(G - G0).max() <= 1e-7
     occ = 0.5 * (1.0 - np.tanh(500.0 * (s.eps - s.mu)))      # Fermi function, no overflow
     assert abs(np.trace(gamma) - occ.sum()) <= 1e-6
+
+
+@pytest.mark.parametrize("frac", [-0.7, -0.01, 0.004, 0.3])
+def test_evaluate_at_reproduces_single_pole(grid, frac):
+    """Re-expanding sampled data at other tau points: a single pole sampled on
+    the IR points and evaluated at points between them (and near both ends)
+    gives the closed form -K(tau, xi); a pole pair in a matrix-valued F keeps
+    each element apart."""
+    b, tau = grid[0], grid[1]
+    beta, xi = b.beta, frac * b.wmax
+    tau_new = np.concatenate([[1e-6 * beta, 0.5 * beta, beta * (1 - 1e-6)],
+                              0.5 * (tau[:-1] + tau[1:])[::7]])
+    got = ir.evaluate_at(b, tau, -np.array([_kt(t, xi, beta) for t in tau]), tau_new)
+    ex = -np.array([_kt(t, xi, beta) for t in tau_new])
+    assert np.abs(got - ex).max() <= 1e-8
+    F = np.array([[[-_kt(t, xi, beta), 0.0], [0.5 * _kt(t, -xi, beta), -_kt(t, 2 * xi, beta)]]
+                  for t in tau])
+    got = ir.evaluate_at(b, tau, F, tau_new)
+    assert got.shape == (len(tau_new), 2, 2)
+    assert np.abs(got[:, 0, 1]).max() <= 1e-12
+    assert np.abs(got[:, 1, 0] - 0.5 * np.array([_kt(t, -xi, beta) for t in tau_new])).max() <= 1e-8
