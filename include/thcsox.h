@@ -77,7 +77,10 @@ typedef struct thcsox_plan_s* thcsox_plan_t;
  *   wq_host[ntau]  : quadrature weights on [0, beta] used by thcsox_energy.
  *   X_dev[n][naux], V_dev[naux][naux] : THC factors (V symmetric).  Copied:
  *                    the caller may free them when this call returns.
- *   precision      : one of THCSOX_FP64 .. THCSOX_FP16X2.
+ *   precision      : one of THCSOX_FP64 .. THCSOX_FP16X2.  The fused kernels
+ *                    address one tile's rows of U with 32-bit buffer offsets,
+ *                    which bounds n: n <= 2047 (FP64), 1440 (FP32), 1664
+ *                    (BF16X3), 2880 (FP16X2); larger n is THCSOX_EINVAL.
  *   workspace_limit: upper bound in bytes on everything the plan allocates,
  *                    the temporaries of building U (freed before this call
  *                    returns) included (0 = no bound).  The number of tau

@@ -412,6 +412,29 @@ int thcsox_plan(thcsox_plan_t* out, int n, int naux, int ntau, double beta,
   if (!(beta > 0.0) || !std::isfinite(beta)) return fail(THCSOX_EINVAL, "beta must be > 0");
   if (precision < THCSOX_FP64 || precision > THCSOX_FP16X2)
     return fail(THCSOX_EINVAL, "unknown precision " + std::to_string(precision));
+  {
+    // The fused kernels address one tile's rows of U with 32-bit buffer offsets
+    // (tile rows x n x ldk elements; their launchers check the same bound).
+    // Refuse larger n here, before anything is allocated.
+    int TR = 0, TP = 0;
+    fused_tile(precision, &TR, &TP);
+    auto fits = [&](int64_t nn) {
+      const int64_t l = precision == THCSOX_FP16X2 ? (nn + 63) / 64 * 64 : (nn + 31) / 32 * 32;
+      const int64_t es = precision == THCSOX_FP16X2 ? 2 : 8;
+      // in double: exact near the bound, and no wrap-around for huge n
+      return (double)std::max(TR, TP) * (double)nn * (double)l * (double)es <= 2147483647.0;
+    };
+    if (!fits(n)) {
+      int64_t lo = 1, hi = n;   // fits(lo), !fits(hi)
+      while (hi - lo > 1) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        (fits(mid) ? lo : hi) = mid;
+      }
+      return fail(THCSOX_EINVAL, "n = " + std::to_string(n) +
+                                     " is beyond the 32-bit buffer offsets of the fused "
+                                     "kernels in this precision (n <= " + std::to_string(lo) + ")");
+    }
+  }
   if (tau_host == nullptr || wq_host == nullptr)
     return fail(THCSOX_EINVAL, "tau_host and wq_host are required");
   {
