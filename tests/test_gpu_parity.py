@@ -112,6 +112,31 @@ def test_tau_slices_compose(dev):
     plan.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3", "fp16x2"])
+def test_tau_slices_split_mirror_pairs(dev, precision):
+    """Slices [0,3), [3,4), [4,8) of an 8-point grid: point k's mirror 7-k (whose
+    G(beta - tau) and per-point scale it needs) lies in another slice for most k.
+    Each point is computed from its own and its mirror's G alone, so the slices
+    fill the same result, bit for bit, as one full call, in every precision, on
+    the symmetric path and with it switched off."""
+    s = synth.make_system(70, 150, seed=3)
+    tau, w = synth.cheb_tau_grid(8, 100.0)
+    G = synth.g0_tau(s, tau, 100.0)
+    print(f"case n70 naux150 ntau8 slices {precision}", flush=True)
+    X = torch.from_numpy(s.X).to(dev); V = torch.from_numpy(s.V).to(dev)
+    Gd = torch.from_numpy(G).to(dev)
+    plan = thcsox.Plan(X, V, tau, w, 100.0, precision=precision)
+    for sym in ("auto", "off"):
+        plan.set_symmetry(sym)
+        full = plan.sigma(Gd)
+        part = torch.zeros_like(full)
+        for k0, k1 in ((4, 8), (0, 3), (3, 4)):
+            plan.sigma(Gd, k0, k1, out=part)
+        torch.cuda.synchronize()
+        assert torch.equal(full, part), (sym, (full - part).abs().max().item())
+    plan.close()
+
+
 def test_workspace_limit_shrinks_the_tau_batch(dev):
     """A workspace limit below what the default tau batch needs makes the plan
     take fewer tau points per batch; the FP64 result is bit-identical (batching
