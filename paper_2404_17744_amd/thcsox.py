@@ -332,16 +332,15 @@ class Dyson:
         self.stream = stream if stream is not None else torch.cuda.current_stream(F.device)
         Fc = F.contiguous().to(torch.float64)
         if grid is None:
-            self.handle = thcsox_dyson_plan(self.n, self.ntau, n_matsubara, float(beta),
-                                            float(mu), np.asarray(tau), Fc.data_ptr(),
-                                            self.stream.cuda_stream)
+            self.handle = _ordered(self.stream, thcsox_dyson_plan, self.n, self.ntau, n_matsubara,
+                                   float(beta), float(mu), np.asarray(tau), Fc.data_ptr(),
+                                   self.stream.cuda_stream)
         else:
             if not np.array_equal(np.asarray(tau, dtype=np.float64), grid["tau"]):
                 raise ValueError("tau must be the grid's sampling points")
-            self.handle = thcsox_dyson_plan_sampled(self.n, self.ntau, len(grid["freq_n"]),
-                                                    float(beta), float(mu), grid["freq_n"],
-                                                    grid["Wf"], grid["Wb"], Fc.data_ptr(),
-                                                    self.stream.cuda_stream)
+            self.handle = _ordered(self.stream, thcsox_dyson_plan_sampled, self.n, self.ntau,
+                                   len(grid["freq_n"]), float(beta), float(mu), grid["freq_n"],
+                                   grid["Wf"], grid["Wb"], Fc.data_ptr(), self.stream.cuda_stream)
 
     def step(self, Sigma, G_out=None, gamma_out=None):
         import torch
@@ -352,7 +351,8 @@ class Dyson:
         _dev64(Sigma, "Sigma", (self.n, self.n), self.ntau, exact=True)
         _dev64(G_out, "G_out", (self.n, self.n), self.ntau, exact=True)
         _dev64(gamma_out, "gamma_out", (self.n,), self.n, exact=True)
-        thcsox_dyson_step(self.handle, Sigma.data_ptr(), G_out.data_ptr(), gamma_out.data_ptr())
+        _ordered(self.stream, thcsox_dyson_step, self.handle, Sigma.data_ptr(), G_out.data_ptr(),
+                 gamma_out.data_ptr())
         return G_out, gamma_out
 
     def step_mu(self, Sigma, nelec: float, mu: float, tol: float = 1e-8, G_out=None,
@@ -367,12 +367,13 @@ class Dyson:
         _dev64(Sigma, "Sigma", (self.n, self.n), self.ntau, exact=True)
         _dev64(G_out, "G_out", (self.n, self.n), self.ntau, exact=True)
         _dev64(gamma_out, "gamma_out", (self.n,), self.n, exact=True)
-        mu, ev = thcsox_dyson_step_mu(self.handle, Sigma.data_ptr(), float(nelec), float(tol),
-                                      float(mu), G_out.data_ptr(), gamma_out.data_ptr())
+        mu, ev = _ordered(self.stream, thcsox_dyson_step_mu, self.handle, Sigma.data_ptr(),
+                          float(nelec), float(tol), float(mu), G_out.data_ptr(),
+                          gamma_out.data_ptr())
         return G_out, gamma_out, mu, ev
 
     def onebody(self, gamma) -> float:
-        return thcsox_dyson_onebody(self.handle, gamma.data_ptr())
+        return _ordered(self.stream, thcsox_dyson_onebody, self.handle, gamma.data_ptr())
 
     def close(self) -> None:
         if getattr(self, "handle", None):
@@ -433,7 +434,8 @@ class MLP:
         if out is None:
             out = torch.empty_like(x)
         _dev64(out, "out", (self.m,), x.shape[0], exact=True, f32=True)
-        _check(lib().thcsox_mlp_forward(self.handle, x.data_ptr(), out.data_ptr(), x.shape[0]))
+        _check(_ordered(self.stream, lib().thcsox_mlp_forward, self.handle, x.data_ptr(),
+                        out.data_ptr(), x.shape[0]))
         return out
 
     def gradients(self, x, t):
@@ -441,16 +443,17 @@ class MLP:
         _dev64(t, "t", (self.m,), x.shape[0], exact=True, f32=True)
         g = np.empty(self.nparam, dtype=np.float32)
         loss = ctypes.c_double()
-        _check(lib().thcsox_mlp_gradients(self.handle, x.data_ptr(), t.data_ptr(), x.shape[0],
-                                          g.ctypes.data_as(ctypes.c_void_p), ctypes.byref(loss)))
+        _check(_ordered(self.stream, lib().thcsox_mlp_gradients, self.handle, x.data_ptr(),
+                        t.data_ptr(), x.shape[0], g.ctypes.data_as(ctypes.c_void_p),
+                        ctypes.byref(loss)))
         return loss.value, self._unpack(g)
 
     def train_step(self, x, t, lr: float, want_loss: bool = True):
         _dev64(x, "x", (self.m,), x.shape[0], exact=True, f32=True)
         _dev64(t, "t", (self.m,), x.shape[0], exact=True, f32=True)
         loss = ctypes.c_double()
-        _check(lib().thcsox_mlp_train_step(self.handle, x.data_ptr(), t.data_ptr(), x.shape[0],
-                                           lr, ctypes.byref(loss) if want_loss else None))
+        _check(_ordered(self.stream, lib().thcsox_mlp_train_step, self.handle, x.data_ptr(),
+                        t.data_ptr(), x.shape[0], lr, ctypes.byref(loss) if want_loss else None))
         return loss.value if want_loss else None
 
     def params(self) -> dict:
@@ -468,6 +471,21 @@ class MLP:
             self.close()
         except Exception:
             pass
+
+
+def _ordered(stream, fn, *args):
+    """Run a library call that queues work on `stream` after the work already on
+    torch's current stream (the call's inputs, outputs just allocated and zeroed
+    there), and make the current stream's later work wait for it."""
+    import torch
+    cur = torch.cuda.current_stream(stream.device)
+    if cur == stream:
+        return fn(*args)
+    stream.wait_stream(cur)
+    try:
+        return fn(*args)
+    finally:
+        cur.wait_stream(stream)
 
 
 def _dev64(t, name: str, tail: tuple, lead: int, exact: bool = False, f32: bool = False):
@@ -501,9 +519,9 @@ class Plan:
         self.stream = stream if stream is not None else torch.cuda.current_stream(X.device)
         Xc = X.contiguous().to(torch.float64)
         Vc = V.contiguous().to(torch.float64)
-        self.handle = thcsox_plan(self.n, self.naux, self.ntau, float(beta), np.asarray(tau),
-                                  np.asarray(w), Xc.data_ptr(), Vc.data_ptr(), precision,
-                                  workspace_limit, self.stream.cuda_stream)
+        self.handle = _ordered(self.stream, thcsox_plan, self.n, self.naux, self.ntau,
+                               float(beta), np.asarray(tau), np.asarray(w), Xc.data_ptr(),
+                               Vc.data_ptr(), precision, workspace_limit, self.stream.cuda_stream)
         self.precision = precision
 
     def sigma(self, G, k_begin: int = 0, k_end: int | None = None, thc: bool = False,
@@ -520,8 +538,8 @@ class Plan:
                                   device=self.device)
         if thc:
             _dev64(out_thc, "out_thc", aa, k_end)
-        thcsox_sigma_sox(self.handle, G.data_ptr(), out.data_ptr(),
-                         out_thc.data_ptr() if thc else None, k_begin, k_end)
+        _ordered(self.stream, thcsox_sigma_sox, self.handle, G.data_ptr(), out.data_ptr(),
+                 out_thc.data_ptr() if thc else None, k_begin, k_end)
         return (out, out_thc) if thc else out
 
     def sigma_direct(self, G, k_begin: int = 0, k_end: int | None = None, out=None,
@@ -534,14 +552,14 @@ class Plan:
         if out is None:
             out = torch.zeros((self.ntau, self.n, self.n), dtype=torch.float64, device=self.device)
         _dev64(out, "out", (self.n, self.n), k_end)
-        _check(lib().thcsox_sigma_direct(self.handle, G.data_ptr(), out.data_ptr(), k_begin, k_end,
-                                         1 if accumulate else 0))
+        _check(_ordered(self.stream, lib().thcsox_sigma_direct, self.handle, G.data_ptr(),
+                        out.data_ptr(), k_begin, k_end, 1 if accumulate else 0))
         return out
 
     def energy(self, G, Sigma) -> float:
         _dev64(G, "G", (self.n, self.n), self.ntau, exact=True)
         _dev64(Sigma, "Sigma", (self.n, self.n), self.ntau, exact=True)
-        return thcsox_energy(self.handle, G.data_ptr(), Sigma.data_ptr())
+        return _ordered(self.stream, thcsox_energy, self.handle, G.data_ptr(), Sigma.data_ptr())
 
     def energy_basis(self, G, Sigma, grid: dict) -> float:
         """The energy on an IR grid (thcsox_ir_grid): the basis-coefficient form."""
@@ -549,8 +567,8 @@ class Plan:
         _dev64(Sigma, "Sigma", (self.n, self.n), self.ntau, exact=True)
         if np.shape(grid["coef"]) != (self.ntau, self.ntau) or len(grid["sign"]) != self.ntau:
             raise ValueError("the grid's basis size differs from the plan's tau count")
-        return thcsox_energy_basis(self.handle, G.data_ptr(), Sigma.data_ptr(), grid["coef"],
-                                   grid["sign"])
+        return _ordered(self.stream, thcsox_energy_basis, self.handle, G.data_ptr(),
+                        Sigma.data_ptr(), grid["coef"], grid["sign"])
 
     def backproject(self, Sigma_thc, k_begin: int = 0, k_end: int | None = None, out=None):
         import torch
@@ -559,7 +577,8 @@ class Plan:
         if out is None:
             out = torch.zeros((self.ntau, self.n, self.n), dtype=torch.float64, device=self.device)
         _dev64(out, "out", (self.n, self.n), k_end)
-        thcsox_backproject(self.handle, Sigma_thc.data_ptr(), out.data_ptr(), k_begin, k_end)
+        _ordered(self.stream, thcsox_backproject, self.handle, Sigma_thc.data_ptr(), out.data_ptr(),
+                 k_begin, k_end)
         return out
 
     def info(self) -> dict:
@@ -598,8 +617,8 @@ def mix(alpha: float, sigma_out, sigma_io, stream=None) -> None:
     _dev64(sigma_io, "sigma_io", tuple(sigma_io.shape[1:]), sigma_io.shape[0], exact=True)
     _dev64(sigma_out, "sigma_out", tuple(sigma_io.shape[1:]), sigma_io.shape[0], exact=True)
     st = stream if stream is not None else torch.cuda.current_stream(sigma_io.device)
-    thcsox_mix(sigma_io.numel(), float(alpha), sigma_out.data_ptr(), sigma_io.data_ptr(),
-               st.cuda_stream)
+    _ordered(st, thcsox_mix, sigma_io.numel(), float(alpha), sigma_out.data_ptr(),
+             sigma_io.data_ptr(), st.cuda_stream)
 
 
 class Diis:
@@ -616,8 +635,8 @@ class Diis:
         for name, t in (("sigma_in", sigma_in), ("sigma_out", sigma_out),
                         ("sigma_next", sigma_next)):
             _dev64(t, name, self.shape[1:], self.shape[0], exact=True)
-        return thcsox_diis_step(self.handle, sigma_in.data_ptr(), sigma_out.data_ptr(),
-                                sigma_next.data_ptr())
+        return _ordered(self.stream, thcsox_diis_step, self.handle, sigma_in.data_ptr(),
+                        sigma_out.data_ptr(), sigma_next.data_ptr())
 
     def close(self) -> None:
         if getattr(self, "handle", None):

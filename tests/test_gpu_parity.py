@@ -198,3 +198,45 @@ def test_errors(dev):
         thcsox.thcsox_sigma_sox(plan.handle, Gd.data_ptr(), Gd.data_ptr(), None, 0, 12)
     assert e.value.code == -1
     plan.close()
+
+
+def test_plan_and_dyson_on_a_side_stream(dev):
+    """A plan and a Dyson plan queued on their own stream (default priority),
+    called from code on the default stream that has just made the inputs and
+    (inside the wrappers) the outputs, behind a queue of unrelated matrix
+    products: the wrappers order each call after the current stream's work and
+    the current stream after the call, so every result equals that of the same
+    objects on the default stream, bit for bit."""
+    s = synth.make_system(70, 150, seed=3)
+    tau, w = synth.cheb_tau_grid(8, 100.0)
+    G0 = synth.g0_tau(s, tau, 100.0)
+    print("case n70 naux150 ntau8 side stream fp16x2 + Dyson", flush=True)
+    X = torch.from_numpy(s.X).to(dev); V = torch.from_numpy(s.V).to(dev)
+    F = torch.from_numpy(s.F).to(dev)
+    Gh = torch.from_numpy(G0).to(dev)
+    ref = thcsox.Plan(X, V, tau, w, 100.0, precision="fp16x2")
+    S_ref = ref.sigma(Gh)
+    E_ref = ref.energy(Gh, S_ref)
+    D_ref = ref.sigma_direct(Gh)
+    dref = thcsox.Dyson(F, s.mu, tau, 100.0, 64)
+    Gd_ref, gam_ref = dref.step(S_ref)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream(dev)
+    p = thcsox.Plan(X, V, tau, w, 100.0, precision="fp16x2", stream=side)
+    d = thcsox.Dyson(F, s.mu, tau, 100.0, 64, stream=side)
+    A = torch.randn(2048, 2048, device=dev)
+    for rep in range(3):
+        for _ in range(8):                      # keep the default stream busy
+            A = torch.tanh(A @ A * 1e-3)
+        G = (Gh * 2.0) * 0.5 + A[0, 0] * 0.0    # made on the default stream, after the products
+        S = p.sigma(G)
+        E = p.energy(G, S)
+        Sd = p.sigma_direct(G)
+        Gd, gam = d.step(S)
+        assert torch.equal(S, S_ref), rep
+        assert E == E_ref, rep
+        assert torch.equal(Sd, D_ref), rep
+        assert torch.equal(Gd, Gd_ref) and torch.equal(gam, gam_ref), rep
+    torch.cuda.synchronize()
+    for o in (p, d, ref, dref):
+        o.close()
