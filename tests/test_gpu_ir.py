@@ -73,7 +73,7 @@ def test_ir_dyson_step_vs_oracle(dev, grids):
     assert abs(np.trace(gamma2.cpu().numpy()) - s.n_occ) <= 1e-6
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp16x2"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3", "fp16x2"])
 def test_ir_sox_energy_vs_oracle(dev, grids, precision):
     g, o = grids
     BETA = o["beta"]
