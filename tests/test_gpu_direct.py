@@ -41,7 +41,7 @@ def test_direct_general_g_ragged(dev):
     assert torch.equal(S, S2)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp16x2"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3", "fp16x2"])
 def test_direct_and_full_gf2_energy(dev, precision):
     """G0 of the n=90, naux=400 system (12 tau): Sigma^dir (FP64 in every plan
     precision), its energy, and the full second-order energy with SOX."""
@@ -87,7 +87,7 @@ def test_direct_fullsize_sampled(dev):
         assert _rel(S[k].cpu().numpy(), ref) <= 1e-11, k
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp16x2"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3", "fp16x2"])
 def test_single_spin_orbital_direct_cancels_sox(dev, precision):
     """n = 1 (one v, a k row padded to the full stage width, v ranges left empty),
     naux = 37 (one ragged tile): the SOX term against the oracle, and the direct
