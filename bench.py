@@ -94,16 +94,40 @@ def measured_traffic(precision, workload, symmetry, info):
     return float(kv["traffic_bytes_per_launch"])
 
 
+def host_details():
+    """CPU model, logical CPUs this process may use, and the BLAS behind NumPy."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count()
+    blas, threads = "unknown", None
+    try:
+        from threadpoolctl import threadpool_info
+        for t in threadpool_info():
+            if t.get("user_api") == "blas":
+                blas = f"{t.get('internal_api')} {t.get('version')} ({t.get('architecture')})"
+                threads = t.get("num_threads")
+                break
+    except Exception:
+        pass
+    return {"cpu_model": model, "nproc": nproc, "blas": blas, "blas_threads": threads}
+
+
 def cpu_baseline(s, G, taus):
     """The FP64 oracle (the paper's sequence) on a few tau points, host cores."""
     import numpy as np
     from oracle import sox as osox
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([t.get("num_threads", 1) for t in threadpool_info()
-                       if t.get("user_api") == "blas"] or [1])
-    except Exception:
-        threads = os.cpu_count()
+    host = host_details()
+    threads = host["blas_threads"] or host["nproc"]
     t0 = time.time()
     U = osox.precontract_u(s.X, s.V)
     t_u = time.time() - t0
@@ -113,7 +137,7 @@ def cpu_baseline(s, G, taus):
         osox.sigma_thc_paper(s.X, s.V, G[k], G[m - 1 - k], U=U)
     dt = time.time() - t0
     return {"value": len(taus) / dt, "unit": "tau-points/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "host": host,
             "sample": f"{len(taus)} of {m} tau points (k={list(taus)}) of the same workload, "
                       f"FP64 NumPy, {dt:.1f} s; U precontraction excluded ({t_u:.1f} s)"}
 
@@ -129,6 +153,8 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=1)
     ap.add_argument("--cpu-taus", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-seed-sweep", action="store_true",
+                    help="skip the energy check of the other seeds with stored oracle values")
     ap.add_argument("--symmetry", default="auto", choices=["auto", "off"])
     ap.add_argument("--no-direct", action="store_true",
                     help="skip the GF2 direct-term measurement beside the SOX one")
@@ -226,6 +252,29 @@ def main():
         Sm = S_mixed.cpu().numpy()
         errs = [abs(Sm[k, t, r] - v) for k, t, r, v in g["samples"]]
         accuracy["sigma_sampled_rel_err_vs_oracle"] = max(errs) / g["sigma_absmax"]
+
+    # the same workload at the other seeds that have stored oracle values
+    # (untimed: one evaluation each in the headline precision)
+    per_seed = {}
+    if ksel is None and not args.no_seed_sweep:
+        for sd in range(5):
+            path = os.path.join(ROOT, "tests", "golden", f"oracle_{args.workload}_seed{sd}.json")
+            if not os.path.exists(path):
+                continue
+            if sd == args.seed:
+                Es = E_mixed
+            else:
+                s2, tau2, w2, G2, beta2 = synth.workload(args.workload, seed=sd)
+                X2, V2 = torch.from_numpy(s2.X).to(dev), torch.from_numpy(s2.V).to(dev)
+                G2d = torch.from_numpy(G2).to(dev)
+                p2 = thcsox.Plan(X2, V2, tau2, w2, beta2, precision=args.precision)
+                p2.set_symmetry(args.symmetry)
+                Es = p2.energy(G2d, p2.sigma(G2d))
+                p2.close()
+                del X2, V2, G2d
+            with open(path) as f:
+                per_seed[str(sd)] = Es - json.load(f)["E_sox"]
+        accuracy["energy_err_vs_fp64_oracle_Ha_per_seed"] = per_seed
 
     out = {
         "metric": METRIC,

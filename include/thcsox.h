@@ -47,8 +47,11 @@ extern "C" {
  *            product kept, FP32 accumulation.
  *   FP16X2 : every operand scaled by a power of two and split into two
  *            half-precision terms, three products per product, FP32 accumulation.
- * In every mode the sum over the orbital index v that forms D_PR is
- * accumulated in FP64 and G is scaled per tau point by a power of two. */
+ * In every mode G is scaled per tau point by a power of two.  The sum over the
+ * orbital index v that forms D_PR is accumulated in FP64 by the FP64 mode; the
+ * other modes sum at most 8 consecutive v in FP32, then add those partial sums
+ * in FP64 (FP32 partial tiles when a v range holds at most 8 v, summed over
+ * the ranges in FP64). */
 enum {
   THCSOX_FP64 = 0,
   THCSOX_FP32 = 1,
@@ -271,7 +274,6 @@ int thcsox_dyson_step(thcsox_dyson_t d, const double* Sigma_dev, double* G_dev,
 int thcsox_dyson_step_mu(thcsox_dyson_t d, const double* Sigma_dev, double nelec, double tol,
                          double* mu_io, double* G_dev, double* gamma_dev, int* evals_out);
 
-/* E1 = Tr[F gamma] = sum_pq F_pq gamma_qp in FP64 (host scalar). */
 /* A Dyson plan on caller-given sampling grids (e.g. the IR grids of
  * thcsox_ir_create) instead of the Chebyshev grid: ntau tau points, and nfreq
  * fermionic frequencies w_j = (2 freq_n[j] + 1) pi / beta, freq_n ascending,
@@ -286,6 +288,7 @@ int thcsox_dyson_plan_sampled(thcsox_dyson_t* out, int n, int ntau, int nfreq, d
                               double mu, const int* freq_n_host, const double* Wf_host,
                               const double* Wb_host, const double* F_dev, void* hip_stream);
 
+/* E1 = Tr[F gamma] = sum_pq F_pq gamma_qp in FP64 (host scalar). */
 int thcsox_dyson_onebody(thcsox_dyson_t d, const double* gamma_dev, double* E1_host);
 
 int thcsox_dyson_destroy(thcsox_dyson_t d);

@@ -33,24 +33,8 @@ constexpr int NXCD = 8;      // accelerator complex dies of an MI355X
 template <int M> struct FusedCfg;
 template <> struct FusedCfg<MODE_F64> { static constexpr int WTI = 2, WTJ = 2, BAND = 1; };
 template <> struct FusedCfg<MODE_F32> { static constexpr int WTI = 4, WTJ = 3, BAND = 1; };
-#ifndef THCSOX_BF_ROWS
-#define THCSOX_BF_ROWS 3
-#endif
-#ifndef THCSOX_BF_COLS
-#define THCSOX_BF_COLS 3
-#endif
-template <> struct FusedCfg<MODE_BF16X3> {
-  static constexpr int WTI = THCSOX_BF_ROWS, WTJ = THCSOX_BF_COLS, BAND = 4;
-};
-#ifndef THCSOX_WT_ROWS
-#define THCSOX_WT_ROWS 4
-#endif
-#ifndef THCSOX_WT_COLS
-#define THCSOX_WT_COLS 3
-#endif
-template <> struct FusedCfg<MODE_F16X2> {
-  static constexpr int WTI = THCSOX_WT_ROWS, WTJ = THCSOX_WT_COLS, BAND = 4;
-};
+template <> struct FusedCfg<MODE_BF16X3> { static constexpr int WTI = 3, WTJ = 3, BAND = 4; };
+// (the fp16x2 mode has its own kernel, fused_f16.hip)
 
 template <int M, bool AF32>
 __global__ __launch_bounds__(NT) void fused_kernel(FusedArgs f) {
@@ -286,13 +270,7 @@ void fused_tile(int mode, int* rows, int* cols) {
     case MODE_F64: tile_of<MODE_F64>(rows, cols); break;
     case MODE_F32: tile_of<MODE_F32>(rows, cols); break;
     case MODE_BF16X3: tile_of<MODE_BF16X3>(rows, cols); break;
-    default:
-#ifdef THCSOX_F16_V1
-      tile_of<MODE_F16X2>(rows, cols);
-#else
-      fused_f16_tile(rows, cols);
-#endif
-      break;
+    default: fused_f16_tile(rows, cols); break;
   }
 }
 
@@ -314,13 +292,7 @@ hipError_t sox_fused(int mode, const FusedArgs& f, hipStream_t s) {
       if (f.a_f32) fused_kernel<MODE_BF16X3, true><<<grid, NT, 0, s>>>(f);
       else fused_kernel<MODE_BF16X3, false><<<grid, NT, 0, s>>>(f);
       break;
-    case MODE_F16X2:
-#ifndef THCSOX_F16_V1
-      if (f.a_f32) return sox_fused_f16(f, s);
-#endif
-      if (f.a_f32) fused_kernel<MODE_F16X2, true><<<grid, NT, 0, s>>>(f);
-      else fused_kernel<MODE_F16X2, false><<<grid, NT, 0, s>>>(f);
-      break;
+    case MODE_F16X2: return sox_fused_f16(f, s);   // FP32 A split on the fly
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

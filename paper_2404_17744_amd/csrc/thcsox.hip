@@ -526,7 +526,8 @@ int thcsox_plan(thcsox_plan_t* out, int n, int naux, int ntau, double beta,
       const double per_q = 8.0 * n * naux;
       const double qb = std::max(1.0, std::min((double)n, std::floor((double)(size_t(256) << 20) / per_q)));
       const double temps = qb * per_q * (precision == THCSOX_FP64 ? 1.0 : 2.0);
-      const double fixed = 8.0 * ((double)n * naux + 7.0 * ntau + 2.0) +
+      // (X, V and the per-tau scalars in FP64, U, A, the partial tiles)
+      const double fixed = 8.0 * ((double)n * naux + (double)naux * naux + 7.0 * ntau + 2.0) +
                            (double)p->np * p->esize * naux * n * ldk +
                            (p->np > 1 ? 4.0 : (double)p->esize) * n * naux * ldk +
                            (p->dpart_f32 ? 4.0 : 8.0) * p->vsplit * (double)naux * naux +
@@ -650,9 +651,13 @@ int thcsox_sigma_direct(thcsox_plan_t p, const double* G_dev, double* Sigma_dev,
   const char* s0 = reinterpret_cast<const char*>(Sigma_dev);
   if (s0 < g0 + gbytes && g0 < s0 + gbytes) return fail(THCSOX_EINVAL, "Sigma aliases G");
   if (p->dbuf == nullptr) {
-    // three naux^2 blocks per tau point, about 1 GB per batch at most
+    // three naux^2 blocks per tau point, about 1 GB per batch at most, and no
+    // more than what the workspace limit leaves (alloc refuses one point that
+    // does not fit with THCSOX_ENOMEM)
     const double per_tau = 3.0 * 8.0 * (double)p->naux * p->naux;
-    p->tbd = (int)std::max(1.0, std::min((double)p->tb, std::floor(1.0e9 / per_tau)));
+    double cap = 1.0e9;
+    if (p->limit) cap = std::min(cap, (double)p->limit - (double)p->bytes - 256.0);
+    p->tbd = (int)std::max(1.0, std::min((double)p->tb, std::floor(cap / per_tau)));
     TRY(p->alloc(&p->dbuf, (size_t)3 * p->tbd * p->naux * p->naux));
   }
   for (int k = k_begin; k < k_end; k += p->tbd)

@@ -80,6 +80,9 @@ def main() -> None:
     S_next = torch.empty_like(G)
     diis = thcsox.Diis(S_out, depth=a.diis) if a.diis > 0 else None
     mu = s.mu
+    # the start: G0 and its density matrix from a Dyson step with Sigma = 0, so
+    # that every energy pairs E_1 = Tr[F gamma] and E_2 of the same G
+    G, gamma = dyson.step(S_in, G_out=G)
     E_prev, iters = None, []
     for it in range(a.iters):
         torch.cuda.synchronize()
@@ -88,6 +91,8 @@ def main() -> None:
         if a.terms == "gf2":
             plan.sigma_direct(G, out=S_out, accumulate=True)   # direct + SOX
         E_2 = plan.energy(G, S_out) if grid is None else plan.energy_basis(G, S_out, grid)
+        E1 = dyson.onebody(gamma)   # the density matrix of the G that Sigma came from
+        nelec = float(np.trace(gamma.cpu().numpy()))   # host diagnostic
         t2 = time.time()
         used = 1
         if it == 0 or (diis is None and a.damping == 0.0):
@@ -102,9 +107,7 @@ def main() -> None:
             G, gamma, mu, solves = dyson.step_mu(S_in, s.n_occ, mu, tol=a.mu_tol, G_out=G)
         else:
             G, gamma = dyson.step(S_in, G_out=G)
-        E1 = dyson.onebody(gamma)
         t3 = time.time()
-        nelec = float(np.trace(gamma.cpu().numpy()))   # host diagnostic
         E = E1 + E_2
         row = {"iter": it + 1, "E_total": E, "E_2": E_2, "E_onebody": E1,
                "dE": None if E_prev is None else E - E_prev,

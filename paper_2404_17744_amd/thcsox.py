@@ -16,12 +16,6 @@ import numpy as np
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libthcsox.so")
 
 
-def use_library(path: str) -> None:
-    """Load libthcsox from another path (before first use), e.g. a variant build."""
-    global LIB_PATH, _lib
-    LIB_PATH = path
-    _lib = None
-
 THCSOX_FP64, THCSOX_FP32, THCSOX_BF16X3, THCSOX_FP16X2 = 0, 1, 2, 3
 PRECISIONS = {"fp64": THCSOX_FP64, "fp32": THCSOX_FP32, "bf16x3": THCSOX_BF16X3,
               "fp16x2": THCSOX_FP16X2}

@@ -3,8 +3,10 @@ production grid, and beta = 100, Lambda = 1e4): the library's grids and tables d
 evaluation and the energy; the oracle runs the same steps on its own grids.
 
 The two grids are the same to the accuracy an FP64 singular value expansion
-fixes them (tau points ~1e-8 relative, identical frequency sets; checked on the
-CPU), so results are compared as functions: the oracle's fitted result is
+fixes them (tau points ~1e-8 relative; the frequency sets agree except for up
+to four points where a sign change of the highest basis functions' transform
+is decided at their noise level, either choice being a valid sampling point;
+checked on the CPU), so results are compared as functions: the oracle's fitted result is
 evaluated at the library's tau points, and energies (integrals) directly.
 Bars: the transforms are accurate to ~1e-8 (eps = 1e-10 times the fit's
 condition number, a few hundred), so 1e-7 absolute on G, 1e-8 relative on

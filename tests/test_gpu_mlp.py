@@ -67,6 +67,36 @@ def test_mlp_adam_step_matches_oracle(dev):
         assert np.abs(step - step_ref).max() < 2e-6, k
 
 
+def test_mlp_adam_four_steps_match_oracle(dev):
+    """Four training steps in a row: the moment accumulation and the bias
+    correction at t >= 2.  Each step's gradients are read back from the GPU at
+    the GPU's current parameters and fed to the oracle's Adam, so the check
+    isolates the update rule from the FP32 gradient rounding.  The first two
+    steps are long (lr 0.05) so that the parameters move and later gradients
+    differ from the first; the moments then mix gradients of both signs."""
+    p32, x, t = _case()
+    print("case mlp adam x4 m64 H128 B300", flush=True)
+    net = thcsox.MLP(64, 128, p32, max_batch=512)
+    xd, td = torch.from_numpy(x).to(dev), torch.from_numpy(t).to(dev)
+    p64 = {k: v.astype(np.float64) for k, v in p32.items()}
+    state = {}
+    for step in range(4):
+        before = net.params()
+        _, g = net.gradients(xd, td)
+        lr = 0.05 if step < 2 else 1e-3
+        net.train_step(xd, td, lr)
+        after = net.params()
+        omlp.adam_step(p64, {k: v.astype(np.float64) for k, v in g.items()}, state, lr=lr)
+        for k in p64:
+            # compare this step's update, taken from the same starting point
+            step_gpu = after[k].astype(np.float64) - before[k]
+            step_ref = p64[k] - before[k]
+            assert np.abs(step_gpu - step_ref).max() < 2e-6 * max(1.0, lr / 1e-3), (step, k)
+            p64[k] = after[k].astype(np.float64)   # follow the GPU's FP32 parameters
+    assert state["t"] == 4
+    net.close()
+
+
 def test_pair_gather_scatter_roundtrip(dev):
     m, A = 8, 40
     rng = np.random.default_rng(0)

@@ -137,39 +137,62 @@ def test_tau_slices_split_mirror_pairs(dev, precision):
     plan.close()
 
 
-def test_workspace_limit_shrinks_the_tau_batch(dev):
+@pytest.mark.parametrize("n,naux", [(70, 150), (40, 600)])
+def test_workspace_limit_shrinks_the_tau_batch(dev, n, naux):
     """A workspace limit below what the default tau batch needs makes the plan
     take fewer tau points per batch; the FP64 result is bit-identical (batching
-    only groups independent tau points)."""
-    s = synth.make_system(70, 150, seed=3)
+    only groups independent tau points).  Over a sweep of limits, ENOMEM may
+    only come below every limit that worked (at naux = 600 the core matrix V
+    is wider than the plan's slack, so a plan that left V out of its sizing
+    would fail in a window above a working limit).  The lazily allocated
+    direct-term buffers also take what the limit leaves: a limit with room for
+    one tau point of them must work."""
+    s = synth.make_system(n, naux, seed=3)
     tau, w = synth.cheb_tau_grid(8, 100.0)
     G = synth.g0_tau(s, tau, 100.0)
     X = torch.from_numpy(s.X).to(dev); V = torch.from_numpy(s.V).to(dev)
     Gd = torch.from_numpy(G).to(dev)
-    print("case n70 naux150 ntau8 fp64 workspace limit", flush=True)
+    print(f"case n{n} naux{naux} ntau8 fp64 workspace limit", flush=True)
     plan = thcsox.Plan(X, V, tau, w, 100.0, precision="fp64")
     full, info = plan.sigma(Gd), plan.info()
+    dfull = plan.sigma_direct(Gd)
     torch.cuda.synchronize()
     plan.close()
     small = None
-    for frac in np.arange(1.4, 0.5, -0.02):
+    worked, failed = [], []
+    for frac in np.arange(1.4, 0.3, -0.01):
+        lim = int(frac * info["bytes"])
         try:
-            p2 = thcsox.Plan(X, V, tau, w, 100.0, precision="fp64",
-                             workspace_limit=int(frac * info["bytes"]))
+            p2 = thcsox.Plan(X, V, tau, w, 100.0, precision="fp64", workspace_limit=lim)
         except thcsox.ThcsoxError as e:
             assert e.code == -2     # ENOMEM: the limit is below what one tau point needs
+            failed.append(lim)
             continue
-        if p2.info()["tau_batch"] < info["tau_batch"]:
+        worked.append(lim)
+        assert p2.info()["bytes"] <= lim
+        if small is None and p2.info()["tau_batch"] < info["tau_batch"]:
             small = p2
-            break
-        p2.close()
+        else:
+            p2.close()
     assert small is not None, "no limit shrank the batch"
-    print(f"  tau batch {info['tau_batch']} -> {small.info()['tau_batch']}")
-    assert small.info()["bytes"] <= int(frac * info["bytes"])
+    assert not failed or max(failed) < min(worked), (min(worked), max(failed))
+    print(f"  tau batch {info['tau_batch']} -> {small.info()['tau_batch']}; "
+          f"smallest working limit {min(worked)}")
     got = small.sigma(Gd)
     torch.cuda.synchronize()
     small.close()
     assert torch.equal(full, got)
+    # room for the plan (with its U-build temporaries, a few MB here) and about
+    # three tau points of the direct term's three naux^2 blocks: fewer than the
+    # eight the batch would take without the limit
+    lim = info["bytes"] + (16 << 20) + int(1.5 * 3 * 8 * naux * naux)
+    p3 = thcsox.Plan(X, V, tau, w, 100.0, precision="fp64", workspace_limit=lim)
+    assert p3.info()["tau_batch"] == info["tau_batch"]
+    dgot = p3.sigma_direct(Gd)
+    torch.cuda.synchronize()
+    assert p3.info()["bytes"] <= lim
+    p3.close()
+    assert torch.equal(dfull, dgot)
 
 
 def test_errors(dev):

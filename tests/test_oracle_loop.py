@@ -74,3 +74,37 @@ def test_adam_first_step_is_signed_lr():
     st = {}
     omlp.adam_step(p, g, st, lr=0.01)
     assert np.allclose(p["w"], np.array([1.0, -2.0, 3.0]) - 0.01 * g["w"] / (np.abs(g["w"]) + 1e-8))
+
+
+def test_adam_three_steps_hand_derived():
+    """Three Adam steps written out by hand (b1 = 0.9, b2 = 0.999, eps -> 0).
+
+    Constant gradient g for two steps: m_t = (1 - b1^t) g and v_t = (1 - b2^t) g^2,
+    so the bias-corrected step is exactly -lr sign(g) both times.  Then the
+    gradient flips to -g: m_3 = b1 m_2 - (1 - b1) g = (0.9 * 0.19 - 0.1) g = 0.071 g,
+    mhat = 0.071 g / (1 - 0.9^3) = (0.071 / 0.271) g, and v_3 = (1 - b2^3) g^2 gives
+    vhat = g^2: the momentum still points along g, so the third step is
+    -lr (0.071 / 0.271) sign(g), about a quarter of the first.  A second entry
+    changes magnitude instead (g = 1, then 3): m_2 = 0.9 * 0.1 + 0.1 * 3 = 0.39,
+    v_2 = 0.999 * 0.001 + 0.001 * 9 = 0.009999, so the second step is
+    -lr (0.39 / 0.19) / sqrt(0.009999 / 0.001999).
+    """
+    lr = 0.01
+    p = {"w": np.array([2.0, -1.0, 0.5])}
+    st = {}
+    gs = [np.array([0.25, -3.0, 1.0]), np.array([0.25, -3.0, 3.0]), np.array([-0.25, 3.0, 3.0])]
+    hist = [p["w"].copy()]
+    for g in gs:
+        omlp.adam_step(p, {"w": g}, st, lr=lr, eps=0.0)
+        hist.append(p["w"].copy())
+    steps = np.diff(np.array(hist), axis=0)
+    # entries 0 and 1: constant gradient, then a sign flip
+    for e, sg in ((0, 1.0), (1, -1.0)):
+        assert abs(steps[0, e] - (-lr * sg)) < 1e-15
+        assert abs(steps[1, e] - (-lr * sg)) < 1e-15
+        assert abs(steps[2, e] - (-lr * sg * 0.071 / 0.271)) < 1e-15
+    # entry 2: magnitude change at step 2
+    assert abs(steps[0, 2] - (-lr)) < 1e-15
+    want2 = -lr * (0.39 / 0.19) / np.sqrt(0.009999 / 0.001999)
+    assert abs(steps[1, 2] - want2) < 1e-14
+    assert st["t"] == 3
