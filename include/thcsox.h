@@ -138,6 +138,26 @@ int thcsox_symmetric_flags(thcsox_plan_t p, int* flags_host);
 int thcsox_energy(thcsox_plan_t p, const double* G_dev, const double* Sigma_dev,
                   double* E_host);
 
+/* Allocation-free variant of thcsox_energy, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  No plan: the quadrature weights come as a device
+ * array.  Computes the same E with the same kernels and summation order as
+ * thcsox_energy (bit-identical for the same inputs and weights):
+ *   G_dev, Sigma_dev : [ntau][n][n] device arrays (inputs, caller-owned).
+ *   w_dev[ntau]      : device array of quadrature weights (input).
+ *   E_dev            : one device double (output); written on the stream.
+ *   hip_stream       : stream of the current device (NULL: the null stream).
+ * The per-tau traces go to a fixed device scratch of at most 4096 doubles
+ * that each GPU holds for the life of the process; ntau > 4096 gives
+ * THCSOX_EINVAL.  Calls no allocator and does not synchronise (asynchronous;
+ * the caller synchronises before reading E_dev).  Every call on one GPU shares
+ * that scratch, so calls that overlap in time on one GPU (on different
+ * streams, or from different threads) race; calls ordered on one stream are
+ * safe.  THCSOX_ENOTDEV for a host pointer, THCSOX_EINVAL for a stream of
+ * another device. */
+int thcsox_energy_noalloc(const double* G_dev, const double* Sigma_dev, const double* w_dev,
+                          int n, int ntau, double* E_dev, void* hip_stream);
+
 /* The same energy on a grid whose quadrature is a basis expansion (the IR
  * sampling grid of thcsox_ir_create): with coefficients g = C G(tau),
  * sigma = C Sigma(tau) (C: coef_host [ntau][ntau], row l maps the tau values to

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -70,6 +71,40 @@ size_t elem_size(int mode) {
   }
 }
 int n_planes(int mode) { return mode == MODE_BF16X3 ? 3 : mode == MODE_F16X2 ? 2 : 1; }
+
+// Device scratch of the allocation-free energy entry point: the per-tau traces
+// Tr[G(beta - tau_k) Sigma(tau_k)].  Each GPU holds its own copy for the life of
+// the process.  In host code the name stands for the host-side shadow only; the
+// device address comes from hipGetSymbolAddress (scratch_on_current_device).
+constexpr int NOALLOC_MAX_NTAU = 4096;
+static __device__ __align__(256) double scratch[NOALLOC_MAX_NTAU];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[MAX_DEVICES] = {};
+
+// The device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+int scratch_on_current_device(double** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess)
+    return fail(THCSOX_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(THCSOX_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr) {
+      (void)hipGetLastError();
+      return fail(THCSOX_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") +
+                                      hipGetErrorString(e));
+    }
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return 0;
+}
 
 }  // namespace
 
@@ -677,6 +712,35 @@ int thcsox_energy(thcsox_plan_t p, const double* G_dev, const double* Sigma_dev,
   HIP_TRY(energy_final(p->tr, p->w, p->m, p->E, s));
   HIP_TRY(hipMemcpyAsync(E_host, p->E, sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
+  return 0;
+}
+
+int thcsox_energy_noalloc(const double* G_dev, const double* Sigma_dev, const double* w_dev,
+                          int n, int ntau, double* E_dev, void* hip_stream) {
+  clear_error();
+  if (n <= 0 || ntau <= 0) return fail(THCSOX_EINVAL, "n and ntau must be positive");
+  if (ntau > NOALLOC_MAX_NTAU)
+    return fail(THCSOX_EINVAL, "ntau = " + std::to_string(ntau) +
+                                   " exceeds the allocation-free scratch (at most " +
+                                   std::to_string(NOALLOC_MAX_NTAU) + " tau points)");
+  TRY(check_dev(G_dev, "G_dev"));
+  TRY(check_dev(Sigma_dev, "Sigma_dev"));
+  TRY(check_dev(w_dev, "w_dev"));
+  TRY(check_dev(E_dev, "E_dev"));
+  const hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if (s != nullptr) {
+    // the scratch address belongs to the current device; so must the stream
+    int cur = -1;
+    hipDevice_t sd = -1;
+    HIP_TRY(hipGetDevice(&cur));
+    HIP_TRY(hipStreamGetDevice(s, &sd));
+    if (sd != cur) return fail(THCSOX_EINVAL, "hip_stream belongs to another device");
+  }
+  double* tr = nullptr;
+  TRY(scratch_on_current_device(&tr));
+  // every tr[k], k < ntau, is written before it is read: nothing to clear
+  HIP_TRY(energy_partials(G_dev, Sigma_dev, n, ntau, tr, s));
+  HIP_TRY(energy_final(tr, w_dev, ntau, E_dev, s));
   return 0;
 }
 

@@ -32,7 +32,8 @@ EXPORTS = ("thcsox_plan", "thcsox_sigma_sox", "thcsox_energy", "thcsox_destroy",
            "thcsox_symmetric_flags", "thcsox_dyson_step_mu", "thcsox_mix",
            "thcsox_diis_create", "thcsox_diis_step", "thcsox_diis_destroy",
            "thcsox_sigma_direct", "thcsox_energy_basis", "thcsox_dyson_plan_sampled",
-           "thcsox_ir_create", "thcsox_ir_sizes", "thcsox_ir_get", "thcsox_ir_destroy")
+           "thcsox_ir_create", "thcsox_ir_sizes", "thcsox_ir_get", "thcsox_ir_destroy",
+           "thcsox_energy_noalloc")
 SYMMETRY = {"auto": 0, "off": 1}
 STAGES = ("project", "a_stage", "fused", "back")
 
@@ -71,6 +72,8 @@ def lib() -> ctypes.CDLL:
         L.thcsox_sigma_sox.restype = i
         L.thcsox_energy.argtypes = [vp, vp, vp, ctypes.POINTER(d)]
         L.thcsox_energy.restype = i
+        L.thcsox_energy_noalloc.argtypes = [vp, vp, vp, i, i, vp, vp]
+        L.thcsox_energy_noalloc.restype = i
         L.thcsox_destroy.argtypes = [vp]
         L.thcsox_destroy.restype = i
         L.thcsox_last_error.argtypes = []
@@ -176,6 +179,11 @@ def thcsox_energy(plan, G_dev: int, Sigma_dev: int) -> float:
     e = ctypes.c_double()
     _check(lib().thcsox_energy(plan, G_dev, Sigma_dev, ctypes.byref(e)))
     return e.value
+
+
+def thcsox_energy_noalloc(G_dev: int, Sigma_dev: int, w_dev: int, n: int, ntau: int,
+                          E_dev: int, hip_stream: int = 0) -> None:
+    _check(lib().thcsox_energy_noalloc(G_dev, Sigma_dev, w_dev, n, ntau, E_dev, hip_stream))
 
 
 def thcsox_destroy(plan) -> None:
