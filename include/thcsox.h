@@ -190,6 +190,42 @@ int thcsox_energy_basis(thcsox_plan_t p, const double* G_dev, const double* Sigm
 int thcsox_sigma_direct(thcsox_plan_t p, const double* G_dev, double* Sigma_dev, int k_begin,
                         int k_end, int accumulate);
 
+/* The statically screened interaction on the THC grid, for the screened
+ * exchange terms below.  The paper names second-order screened exchange (one
+ * screened interaction line) and G3W2 (two) as contractions of the SOX type
+ * (closing paragraph of Sec. "THC-scGF2: algorithm and implementation details";
+ * Sec. "Conclusions and future work") and prints no formula.  Reading used:
+ * the polarization is the direct term's bubble and the line is screened in the
+ * random-phase series at zero bosonic frequency,
+ *     Pi(tau)_QS = Gt_QS Gbt_SQ,   Pi0 = sum_k w_k Pi(tau_k)  (the plan's weights),
+ *     W = (1 + V Pi0)^-1 V  (= V - V Pi0 V + V Pi0 V Pi0 V - ...)
+ * (Pi0 is positive semidefinite for an independent-particle G, so W <= V).
+ *   G_dev  : [ntau][n][n] device array (all tau points are used).
+ *   W_dev  : [naux][naux] device array (output, caller-owned).
+ * FP64 in every plan precision; 1 + V Pi0 is inverted by blocked Gauss-Jordan
+ * elimination with partial pivoting (naux <= 9216, else THCSOX_EINVAL).  The
+ * first call allocates 5 naux^2 doubles and the direct term's batch buffers
+ * (kept by the plan).  THCSOX_ENONFINITE for a singular 1 + V Pi0.
+ * Synchronises the plan's stream. */
+int thcsox_static_screening(thcsox_plan_t p, const double* G_dev, double* W_dev);
+
+/* Exchange self-energies with instantaneous screened lines of core W (e.g. from
+ * thcsox_static_screening).  With Sigma[Va; Vc] the SOX sequence of
+ * thcsox_sigma_sox with core Va on the line (pr|qs) (its U enters A) and core
+ * Vc on the line (tu|vw) (its U enters C):
+ *   THCSOX_SOSEX : Sigma = (Sigma[V; W] + Sigma[W; V]) / 2   (one line screened,
+ *                  both placements; the symmetric-D path does not apply)
+ *   THCSOX_G3W2  : Sigma = Sigma[W; W]                         (both lines screened)
+ * for k in [k_begin, k_end), in the plan's precision (the U of W is built in
+ * FP64 at every call and stored like the plan's U; the first call allocates
+ * its planes).  G_dev, Sigma_dev: [ntau][n][n] device arrays (Sigma must not
+ * alias G); W_dev: [naux][naux] device array, symmetric.  The energy is
+ * thcsox_energy of the result.  Synchronises the plan's stream once (the U
+ * build), then runs asynchronously. */
+enum { THCSOX_SOSEX = 0, THCSOX_G3W2 = 1 };
+int thcsox_sigma_screened(thcsox_plan_t p, const double* G_dev, const double* W_dev, int kind,
+                          double* Sigma_dev, int k_begin, int k_end);
+
 /* Back-projection alone (the last equation of the THC sequence):
  *     Sigma_tr = sum_PR X_tR Sig_RP X_rP       for k in [k_begin, k_end)
  *   Sigma_thc_dev[ntau][naux][naux] (read), Sigma_dev[ntau][n][n] (written).

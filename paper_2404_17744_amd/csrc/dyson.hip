@@ -483,7 +483,50 @@ __global__ __launch_bounds__(NT) void trace_ab(const double* A, const double* B,
 
 int dfail(int code, const std::string& m) { return set_error(code, m); }
 
+__global__ __launch_bounds__(NT) void real_to_complex(const double* __restrict__ M, int64_t nn,
+                                                      double2* __restrict__ Am) {
+  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < nn; e += (int64_t)gridDim.x * NT)
+    Am[e] = make_double2(M[e], 0.0);
+}
+
+// Minv[i][j] = Re of the eliminated matrix at column perm[j] (one matrix)
+__global__ __launch_bounds__(NT) void extract_real_inv(const double2* __restrict__ Am,
+                                                       const int* __restrict__ perm, int n,
+                                                       double* __restrict__ Minv) {
+  const int64_t nn = (int64_t)n * n;
+  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < nn; e += (int64_t)gridDim.x * NT) {
+    const int64_t i = e / n, j = e % n;
+    Minv[e] = Am[i * n + perm[j]].x;
+  }
+}
+
 }  // namespace
+
+namespace thcsox {
+hipError_t gj_inverse_real(const double* M, int n, double* Minv, double2* Am, int* piv, int* perm,
+                           int* flag, hipStream_t s) {
+  if (n <= 0 || n > GJ_LDS) return hipErrorInvalidValue;
+  const int64_t nn = (int64_t)n * n;
+  const unsigned bx = (unsigned)std::min<int64_t>(1024, (nn + NT - 1) / NT);
+  real_to_complex<<<bx, NT, 0, s>>>(M, nn, Am);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if ((e = hipMemsetAsync(flag, 0, sizeof(int), s)) != hipSuccess) return e;
+  int bw = GJ_B;
+  while (bw > 1 && (int64_t)bw * n > GJ_LDS) bw /= 2;
+  for (int k = 0; k < n; k += bw) {
+    const int w = std::min(bw, n - k);
+    gje_panel<<<1, NT, 0, s>>>(Am, n, k, w, piv, flag);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    gje_trail<<<dim3((unsigned)((n + GJ_TCB - 1) / GJ_TCB), 1), NT, 0, s>>>(Am, n, k, w);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  gje_perm<<<1, NT, 0, s>>>(piv, n, 1, perm);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  extract_real_inv<<<bx, NT, 0, s>>>(Am, perm, n, Minv);
+  return hipGetLastError();
+}
+}  // namespace thcsox
 
 struct thcsox_dyson_s {
   int n = 0, m = 0, nw = 0, panel = GJ_B;

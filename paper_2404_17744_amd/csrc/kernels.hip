@@ -208,7 +208,8 @@ template <typename T>
 __global__ __launch_bounds__(NT) void dreduce_kernel(DReduceArgs a) {
   __shared__ double t[DT][DT + 1];
   const double f = pow2_scale(a.amax_gt) * pow2_scale(a.amax_gx) * pow2_scale(a.amax_gb) *
-                   pow2_scale(a.amax_a) * pow2_scale(a.amax_u) * pow2_scale(a.amax_u);
+                   pow2_scale(a.amax_a) * pow2_scale(a.amax_u) *
+                   pow2_scale(a.amax_u2 != nullptr ? a.amax_u2 : a.amax_u);
   const double inv = 1.0 / f;   // exact: a power of two
   const int64_t nn = (int64_t)a.naux * a.naux;
   const bool sym = a.sym != nullptr && *a.sym != 0;
@@ -318,9 +319,41 @@ __global__ void energy_final_kernel(const double* tr, const double* w, int m, do
   }
 }
 
+__global__ __launch_bounds__(NT) void weighted_block_sum_kernel(const double* __restrict__ Pi,
+                                                                const double* __restrict__ w,
+                                                                int nb, int64_t len,
+                                                                double* __restrict__ Pi0,
+                                                                int accumulate) {
+  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < len; e += (int64_t)gridDim.x * NT) {
+    double acc = accumulate ? Pi0[e] : 0.0;
+    for (int b = 0; b < nb; ++b) acc = fma(w[b], Pi[(int64_t)b * len + e], acc);
+    Pi0[e] = acc;
+  }
+}
+
+__global__ __launch_bounds__(NT) void add_identity_kernel(double* A, int n) {
+  const int i = blockIdx.x * NT + threadIdx.x;
+  if (i < n) A[(int64_t)i * n + i] += 1.0;
+}
+
 inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
 }  // namespace
+
+hipError_t weighted_block_sum(const double* Pi, const double* w, int nb, int64_t len,
+                              double* Pi0, int accumulate, hipStream_t s) {
+  if (len <= 0) return hipSuccess;
+  const int64_t b = (len + NT - 1) / NT;
+  weighted_block_sum_kernel<<<(unsigned)(b > 4096 ? 4096 : b), NT, 0, s>>>(Pi, w, nb, len, Pi0,
+                                                                          accumulate);
+  return hipGetLastError();
+}
+
+hipError_t add_identity(double* A, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  add_identity_kernel<<<cdiv(n, NT), NT, 0, s>>>(A, n);
+  return hipGetLastError();
+}
 
 hipError_t gemm64(const Gemm64Args& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;

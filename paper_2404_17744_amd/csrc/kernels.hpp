@@ -96,6 +96,8 @@ struct DReduceArgs {
   const unsigned long long* amax_gt; const unsigned long long* amax_gx;
   const unsigned long long* amax_gb; const unsigned long long* amax_a;
   const unsigned long long* amax_u;
+  // the U of the C product when it differs from the A product's (two cores); null: amax_u
+  const unsigned long long* amax_u2;
   const int* sym;
 };
 hipError_t dreduce(const DReduceArgs& a, hipStream_t s);
@@ -110,6 +112,20 @@ hipError_t sym_flags(const unsigned long long* asym, const unsigned long long* a
 // KR[(q - q0)*n + s][Q] = X[q][Q] * X[s][Q] for q in [q0, q1).
 hipError_t khatri_rao(const double* X, int n, int naux, int q0, int q1, double* KR,
                       hipStream_t s);
+
+// Inverse of one real n x n matrix (row-major, n <= 9216) by the Dyson step's
+// blocked Gauss-Jordan elimination with partial pivoting on a complex copy.
+// Work: Am [n n] double2, piv and perm [n] ints, flag [1] int, set to 1 for a
+// zero or non-finite pivot (read it after synchronising).
+hipError_t gj_inverse_real(const double* M, int n, double* Minv, double2* Am, int* piv, int* perm,
+                           int* flag, hipStream_t s);
+
+// Pi0[e] (+)= sum_b w[b] Pi[b][e] over nb blocks of len elements, b in order
+// (accumulate = 0: Pi0 is overwritten).
+hipError_t weighted_block_sum(const double* Pi, const double* w, int nb, int64_t len,
+                              double* Pi0, int accumulate, hipStream_t s);
+// A[i][i] += 1 for i < n (row-major n x n).
+hipError_t add_identity(double* A, int n, hipStream_t s);
 
 // tr[k] = sum_pq G[m-1-k][q][p] Sigma[k][p][q]; then E = -1/2 sum_k w[k] tr[k].
 hipError_t energy_partials(const double* G, const double* S, int n, int m, double* tr,

@@ -123,6 +123,16 @@ struct thcsox_plan_s {
   double* ecoef = nullptr;  // basis energy: [2][ntau][ntau] (rows reversed, then as given)
   double* esign = nullptr;  // basis energy: [ntau]
   int tbd = 0;              // tau points per direct-term batch
+  // screened exchange (allocated on first use): the second U (from the screened
+  // core W, same layout and precision as U) and its max |.|, the static
+  // polarization Pi0, 1 + V Pi0 and its inverse, and the Gauss-Jordan work
+  void* Uw = nullptr;
+  unsigned long long* amax_w = nullptr;
+  double* Pi0 = nullptr;
+  double* Mscr = nullptr;
+  double* Minv = nullptr;
+  double2* Am = nullptr;
+  int* gj = nullptr;        // [2 naux + 1]: pivots, permutation, flag
   double* w = nullptr;      // [m]
   void* U = nullptr;        // planes of [naux][n][ldk]
   int64_t u_plane = 0;
@@ -213,9 +223,10 @@ namespace {
     if (rc_ != 0) return rc_; \
   } while (0)
 
-// U_Pqs = sum_Q V_PQ X_qQ X_sQ in FP64, chunked over q, stored in the plan's
-// operand planes.  Split modes first take max|U| (pass 0), then store (pass 1).
-int build_u(thcsox_plan_s* p, const double* V) {
+// U_Pqs = sum_Q V_PQ X_qQ X_sQ in FP64, chunked over q, stored in the operand
+// planes Uout (the plan's U, or the second U of a screened core).  Split modes
+// first take max|U| into *amax_slot (pass 0), then store (pass 1).
+int build_u(thcsox_plan_s* p, const double* V, void* Uout, unsigned long long* amax_slot) {
   const int n = p->n, naux = p->naux, ldk = p->ldk;
   const hipStream_t s = p->stream;
   size_t per_q = (size_t)n * naux * sizeof(double);
@@ -224,7 +235,7 @@ int build_u(thcsox_plan_s* p, const double* V) {
   TRY(p->alloc(&KR, (size_t)qb * n * naux));
   double* Uc = nullptr;
   if (p->mode != MODE_F64) TRY(p->alloc(&Uc, (size_t)qb * n * naux));
-  HIP_TRY(fill_u64(p->amax, 1, 0ull, s));
+  HIP_TRY(fill_u64(amax_slot, 1, 0ull, s));
   const int passes = p->mode == MODE_F64 ? 1 : 2;
   for (int pass = 0; pass < passes; ++pass) {
     for (int q0 = 0; q0 < n; q0 += qb) {
@@ -235,7 +246,7 @@ int build_u(thcsox_plan_s* p, const double* V) {
       g.A = V; g.a_i = naux; g.a_k = 1;
       g.B = KR; g.b_k = 1; g.b_j = naux;
       if (p->mode == MODE_F64) {
-        g.C = static_cast<double*>(p->U) + (int64_t)q0 * ldk;
+        g.C = static_cast<double*>(Uout) + (int64_t)q0 * ldk;
         g.c_i = (int64_t)n * ldk; g.c_j = 1; g.cj_in = n; g.cj_out = ldk;
       } else {
         g.C = Uc; g.c_i = (int64_t)qc * n; g.c_j = 1; g.cj_in = (int64_t)qc * n; g.cj_out = 0;
@@ -243,14 +254,14 @@ int build_u(thcsox_plan_s* p, const double* V) {
       HIP_TRY(gemm64(g, s));
       if (p->mode == MODE_F64) continue;
       if (pass == 0) {
-        HIP_TRY(absmax64(Uc, (int64_t)naux * qc * n, 0, 1, p->amax + 0, s));
+        HIP_TRY(absmax64(Uc, (int64_t)naux * qc * n, 0, 1, amax_slot, s));
       } else {
         SplitArgs a{};
         a.rows1 = naux; a.rows2 = qc; a.cols = n; a.ldk = ldk;
         a.src = Uc; a.src_f32 = false; a.s1 = (int64_t)qc * n; a.s2 = n; a.sc = 1;
-        a.dst = static_cast<char*>(p->U) + (size_t)q0 * ldk * p->esize;
+        a.dst = static_cast<char*>(Uout) + (size_t)q0 * ldk * p->esize;
         a.d1 = (int64_t)n * ldk; a.d2 = ldk; a.d_plane = p->u_plane;
-        a.amax = p->amax + 0;
+        a.amax = amax_slot;
         HIP_TRY(split_planes(p->mode, a, s));
       }
     }
@@ -270,7 +281,7 @@ int build_u(thcsox_plan_s* p, const double* V) {
 // Sigma[b] = X Sig_thc[b] X^T for nb tau points at once (FP64 matrix cores);
 // Sig_thc[b] = St + b * st_stride, Sigma[b] = Sig + b * n * n (beta_out = 1: Sigma[b] +=).
 int backproject_batch(thcsox_plan_s* p, const double* St, int64_t st_stride, double* Sig,
-                      int nb, double beta_out = 0.0) {
+                      int nb, double beta_out = 0.0, double alpha_out = 1.0) {
   const int n = p->n, naux = p->naux;
   const hipStream_t s = p->stream;
   Gemm64Args b{};
@@ -283,15 +294,26 @@ int backproject_batch(thcsox_plan_s* p, const double* St, int64_t st_stride, dou
   b.A = p->T1; b.a_i = naux; b.a_k = 1; b.a_b = (int64_t)n * naux;
   b.B = p->X; b.b_k = 1; b.b_j = naux; b.b_b = 0;
   b.C = Sig; b.c_i = n; b.c_j = 1; b.cj_in = n; b.cj_out = 0; b.c_b = (int64_t)n * n;
+  b.alpha = alpha_out;
   b.beta = beta_out;   // 1: add to what Sig holds
   HIP_TRY(gemm64(b, s));
   return 0;
 }
 
-// Tau points k0 <= k < k1 (k1 - k0 <= tb): Sigma[k] (and Sig_thc[k]) from G.
+// The core matrices of the two interaction lines of the exchange diagram, as
+// their U planes: UA on the line (pr|qs) (enters A), UC on (tu|vw) (enters C).
+// SOX has the plan's U on both; the symmetric-D path needs UA == UC.
+struct Cores {
+  const void* UA; const unsigned long long* amaxA;
+  const void* UC; const unsigned long long* amaxC;
+};
+
+// Tau points k0 <= k < k1 (k1 - k0 <= tb): Sigma[k] (and Sig_thc[k]) from G,
+// Sigma[k] = alpha_out X Sig_thc X^T + beta_out Sigma[k].
 // Needs the per-tau max |G[k]| and the symmetry flags of every k (set by the caller).
 int sigma_batch(thcsox_plan_s* p, const double* G, double* Sigma, double* Sthc_out, int k0,
-                int k1) {
+                int k1, const Cores& cores, double alpha_out = 1.0, double beta_out = 0.0) {
+  const bool same_core = cores.UA == cores.UC;
   const int n = p->n, naux = p->naux, ldk = p->ldk, m = p->m, mode = p->mode;
   const int nb = k1 - k0;
   const hipStream_t s = p->stream;
@@ -334,12 +356,12 @@ int sigma_batch(thcsox_plan_s* p, const double* G, double* Sigma, double* Sthc_o
   const bool split_a = (mode == MODE_BF16X3 || mode == MODE_F16X2);
   for (int b = 0; b < nb; ++b) {
     const int k = k0 + b, kb = m - 1 - k;
-    const int* sym = p->sym_mode == THCSOX_SYM_AUTO ? p->symflag + k : nullptr;
+    const int* sym = same_core && p->sym_mode == THCSOX_SYM_AUTO ? p->symflag + k : nullptr;
     // A[v][P][q] = sum_s U[P][q][s] G(beta - tau)[s][v]: rows (P,q) of U against rows v of Gb
     HIP_TRY(p->mark(THCSOX_STAGE_A, true));
     GemmKArgs ga{};
     ga.M = naux * n; ga.N = n; ga.kpad = ldk; ga.alpha = 1.0;
-    ga.A = p->U; ga.lda = ldk; ga.a_plane = p->u_plane;
+    ga.A = cores.UA; ga.lda = ldk; ga.a_plane = p->u_plane;
     ga.B = static_cast<const char*>(p->Gb) + (size_t)b * n * ldk * es;
     ga.ldb = ldk; ga.b_plane = p->gb_plane;
     ga.ci_in = n; ga.ci_out = ldk; ga.c_j = (int64_t)naux * ldk;
@@ -358,7 +380,7 @@ int sigma_batch(thcsox_plan_s* p, const double* G, double* Sigma, double* Sthc_o
     f.Gt = static_cast<const char*>(p->Gt) + (size_t)b * naux * ldk * es;
     f.GXt = static_cast<const char*>(p->GX) + (size_t)b * naux * ldk * es;
     f.g_plane = p->g_plane;
-    f.U = p->U; f.u_plane = p->u_plane;
+    f.U = cores.UC; f.u_plane = p->u_plane;
     f.A = split_a ? static_cast<const void*>(p->A32) : p->A; f.a_plane = p->a_plane;
     f.a_f32 = split_a; f.amax_a = split_a ? p->am_a() + k : nullptr;
     f.Dpart = p->Dpart; f.dpart_f32 = p->dpart_f32;
@@ -374,7 +396,8 @@ int sigma_batch(thcsox_plan_s* p, const double* G, double* Sigma, double* Sthc_o
     d.s_ld = naux;
     d.amax_gt = p->am_gt() + k; d.amax_gx = p->am_gx() + k; d.amax_gb = p->am_g() + kb;
     d.amax_a = split_a ? p->am_a() + k : nullptr;
-    d.amax_u = (mode == MODE_F64) ? nullptr : p->amax;
+    d.amax_u = (mode == MODE_F64) ? nullptr : cores.amaxA;
+    d.amax_u2 = (mode == MODE_F64) ? nullptr : cores.amaxC;
     d.sym = sym;
     HIP_TRY(dreduce(d, s));
     HIP_TRY(p->mark(THCSOX_STAGE_BACK, false));
@@ -382,22 +405,20 @@ int sigma_batch(thcsox_plan_s* p, const double* G, double* Sigma, double* Sthc_o
 
   HIP_TRY(p->mark(THCSOX_STAGE_BACK, true));
   const double* St = Sthc_out ? Sthc_out + (int64_t)k0 * aa : p->Sthc;
-  TRY(backproject_batch(p, St, aa, Sigma + (int64_t)k0 * nn, nb));
+  TRY(backproject_batch(p, St, aa, Sigma + (int64_t)k0 * nn, nb, beta_out, alpha_out));
   HIP_TRY(p->mark(THCSOX_STAGE_BACK, false));
   return 0;
 }
 
-// GF2 direct (bubble) term for tau points k0 <= k < k1 (k1 - k0 <= tbd), FP64:
-//   Gt = X^T G[k] X, Gbt = X^T G[m-1-k] X, Pi = Gt o Gbt^T, W = V Pi V,
-//   Sigma[k] = X (W o Gt) X^T.
-int direct_batch(thcsox_plan_s* p, const double* G, double* Sigma, int k0, int k1,
-                 bool accumulate) {
+// Gt = X^T G[k] X into the direct-term buffer A and Gbt = X^T G[m-1-k] X into
+// buffer B for k0 <= k < k1 (k1 - k0 <= tbd), then Pi = Gt o Gbt^T into buffer C.
+int bubble_batch(thcsox_plan_s* p, const double* G, int k0, int k1) {
   const int n = p->n, naux = p->naux, m = p->m, nb = k1 - k0;
   const hipStream_t s = p->stream;
   const int64_t nn = (int64_t)n * n, aa = (int64_t)naux * naux;
-  double* bufA = p->dbuf;                          // Gt
-  double* bufB = p->dbuf + (int64_t)p->tbd * aa;   // Gbt, then V Pi
-  double* bufC = bufB + (int64_t)p->tbd * aa;      // Pi, then W, then W o Gt
+  double* bufA = p->dbuf;
+  double* bufB = p->dbuf + (int64_t)p->tbd * aa;
+  double* bufC = bufB + (int64_t)p->tbd * aa;
   // T = X^T G for the batch (into Gt64, [nb][naux][n]) and Gt = T X; the same
   // for the mirrored points, walking G backwards
   for (int mirror = 0; mirror < 2; ++mirror) {
@@ -415,6 +436,21 @@ int direct_batch(thcsox_plan_s* p, const double* G, double* Sigma, int k0, int k
     HIP_TRY(gemm64(g, s));
   }
   HIP_TRY(bubble_pi(bufA, bufB, bufC, naux, nb, s));
+  return 0;
+}
+
+// GF2 direct (bubble) term for tau points k0 <= k < k1 (k1 - k0 <= tbd), FP64:
+//   Gt = X^T G[k] X, Gbt = X^T G[m-1-k] X, Pi = Gt o Gbt^T, W = V Pi V,
+//   Sigma[k] = X (W o Gt) X^T.
+int direct_batch(thcsox_plan_s* p, const double* G, double* Sigma, int k0, int k1,
+                 bool accumulate) {
+  const int n = p->n, naux = p->naux, nb = k1 - k0;
+  const hipStream_t s = p->stream;
+  const int64_t nn = (int64_t)n * n, aa = (int64_t)naux * naux;
+  double* bufA = p->dbuf;                          // Gt
+  double* bufB = p->dbuf + (int64_t)p->tbd * aa;   // Gbt, then V Pi
+  double* bufC = bufB + (int64_t)p->tbd * aa;      // Pi, then W, then W o Gt
+  TRY(bubble_batch(p, G, k0, k1));
   // W = (V Pi) V
   Gemm64Args g{};
   g.M = naux; g.N = naux; g.K = naux; g.batch = nb; g.alpha = 1.0; g.beta = 0.0;
@@ -428,6 +464,35 @@ int direct_batch(thcsox_plan_s* p, const double* G, double* Sigma, int k0, int k
   HIP_TRY(gemm64(g, s));
   HIP_TRY(hadamard64(bufC, bufA, bufC, (int64_t)nb * aa, s));
   return backproject_batch(p, bufC, aa, Sigma + (int64_t)k0 * nn, nb, accumulate ? 1.0 : 0.0);
+}
+
+// The direct term's three batch buffers of naux^2 per tau point (also the
+// screened exchange's polarization batches), allocated on first use: about
+// 1 GB per batch at most, and no more than what the workspace limit leaves
+// (alloc refuses one point that does not fit with THCSOX_ENOMEM).
+int ensure_direct_buffers(thcsox_plan_s* p) {
+  if (p->dbuf != nullptr) return 0;
+  const double per_tau = 3.0 * 8.0 * (double)p->naux * p->naux;
+  double cap = 1.0e9;
+  if (p->limit) cap = std::min(cap, (double)p->limit - (double)p->bytes - 256.0);
+  p->tbd = (int)std::max(1.0, std::min((double)p->tb, std::floor(cap / per_tau)));
+  return p->alloc(&p->dbuf, (size_t)3 * p->tbd * p->naux * p->naux);
+}
+
+// Per-call preparation of G for the exchange contractions: max |G[k]| of every
+// tau point (the power-of-two scales) and, under THCSOX_SYM_AUTO, the flags of
+// the symmetric-D path.
+int prepare_g(thcsox_plan_s* p, const double* G_dev) {
+  const hipStream_t s = p->stream;
+  const int64_t nn = (int64_t)p->n * p->n;
+  HIP_TRY(fill_u64(p->am_g(), p->m, 0ull, s));
+  HIP_TRY(absmax64(G_dev, nn, nn, p->m, p->am_g(), s));
+  if (p->sym_mode == THCSOX_SYM_AUTO) {
+    HIP_TRY(asym64(G_dev, p->n, p->m, p->am_asym(), s));
+    HIP_TRY(sym_flags(p->am_asym(), p->am_g(), p->m,
+                      p->mode == MODE_F64 ? SYM_RTOL_F64 : SYM_RTOL_MIXED, p->symflag, s));
+  }
+  return 0;
 }
 
 }  // namespace
@@ -625,7 +690,7 @@ int thcsox_plan(thcsox_plan_t* out, int n, int naux, int ntau, double beta,
   if ((e = hipMemcpyAsync(p->V, V_dev, sizeof(double) * (size_t)naux * naux,
                           hipMemcpyDeviceToDevice, s)))
     return hip_bail(e, "copy V");
-  if ((rc = build_u(p, V_dev))) return bail(rc);
+  if ((rc = build_u(p, V_dev, p->U, p->amax))) return bail(rc);
   if ((e = hipStreamSynchronize(s))) return hip_bail(e, "plan synchronise");
   *out = p;
   return 0;
@@ -644,17 +709,10 @@ int thcsox_sigma_sox(thcsox_plan_t p, const double* G_dev, double* Sigma_dev,
   const char* g0 = reinterpret_cast<const char*>(G_dev);
   const char* s0 = reinterpret_cast<const char*>(Sigma_dev);
   if (s0 < g0 + gbytes && g0 < s0 + gbytes) return fail(THCSOX_EINVAL, "Sigma aliases G");
-  const hipStream_t s = p->stream;
-  const int64_t nn = (int64_t)p->n * p->n;
-  HIP_TRY(fill_u64(p->am_g(), p->m, 0ull, s));
-  HIP_TRY(absmax64(G_dev, nn, nn, p->m, p->am_g(), s));
-  if (p->sym_mode == THCSOX_SYM_AUTO) {
-    HIP_TRY(asym64(G_dev, p->n, p->m, p->am_asym(), s));
-    HIP_TRY(sym_flags(p->am_asym(), p->am_g(), p->m,
-                      p->mode == MODE_F64 ? SYM_RTOL_F64 : SYM_RTOL_MIXED, p->symflag, s));
-  }
+  TRY(prepare_g(p, G_dev));
   for (int k = k_begin; k < k_end; k += p->tb)
-    TRY(sigma_batch(p, G_dev, Sigma_dev, Sigma_thc_dev, k, std::min(k_end, k + p->tb)));
+    TRY(sigma_batch(p, G_dev, Sigma_dev, Sigma_thc_dev, k, std::min(k_end, k + p->tb),
+                    Cores{p->U, p->amax, p->U, p->amax}));
   return 0;
 }
 
@@ -685,18 +743,95 @@ int thcsox_sigma_direct(thcsox_plan_t p, const double* G_dev, double* Sigma_dev,
   const char* g0 = reinterpret_cast<const char*>(G_dev);
   const char* s0 = reinterpret_cast<const char*>(Sigma_dev);
   if (s0 < g0 + gbytes && g0 < s0 + gbytes) return fail(THCSOX_EINVAL, "Sigma aliases G");
-  if (p->dbuf == nullptr) {
-    // three naux^2 blocks per tau point, about 1 GB per batch at most, and no
-    // more than what the workspace limit leaves (alloc refuses one point that
-    // does not fit with THCSOX_ENOMEM)
-    const double per_tau = 3.0 * 8.0 * (double)p->naux * p->naux;
-    double cap = 1.0e9;
-    if (p->limit) cap = std::min(cap, (double)p->limit - (double)p->bytes - 256.0);
-    p->tbd = (int)std::max(1.0, std::min((double)p->tb, std::floor(cap / per_tau)));
-    TRY(p->alloc(&p->dbuf, (size_t)3 * p->tbd * p->naux * p->naux));
-  }
+  TRY(ensure_direct_buffers(p));
   for (int k = k_begin; k < k_end; k += p->tbd)
     TRY(direct_batch(p, G_dev, Sigma_dev, k, std::min(k_end, k + p->tbd), accumulate != 0));
+  return 0;
+}
+
+int thcsox_static_screening(thcsox_plan_t p, const double* G_dev, double* W_dev) {
+  clear_error();
+  if (p == nullptr) return fail(THCSOX_EINVAL, "plan is NULL");
+  TRY(check_dev(G_dev, "G_dev"));
+  TRY(check_dev(W_dev, "W_dev"));
+  const int naux = p->naux, m = p->m;
+  if (naux > 9216) return fail(THCSOX_EINVAL, "naux > 9216 is beyond the screening solve");
+  const int64_t aa = (int64_t)naux * naux;
+  const hipStream_t s = p->stream;
+  TRY(ensure_direct_buffers(p));
+  if (p->Pi0 == nullptr) {
+    TRY(p->alloc(&p->Pi0, (size_t)aa));
+    TRY(p->alloc(&p->Mscr, (size_t)aa));
+    TRY(p->alloc(&p->Minv, (size_t)aa));
+    TRY(p->alloc(&p->Am, (size_t)aa));
+    TRY(p->alloc(&p->gj, (size_t)2 * naux + 1));
+  }
+  // Pi0 = sum_k w_k Pi(tau_k), batch by batch, in the order of k
+  const double* bufC = p->dbuf + 2 * (int64_t)p->tbd * aa;
+  for (int k0 = 0; k0 < m; k0 += p->tbd) {
+    const int k1 = std::min(m, k0 + p->tbd);
+    TRY(bubble_batch(p, G_dev, k0, k1));
+    HIP_TRY(weighted_block_sum(bufC, p->w + k0, k1 - k0, aa, p->Pi0, k0 > 0 ? 1 : 0, s));
+  }
+  // W = (1 + V Pi0)^-1 V
+  Gemm64Args g{};
+  g.M = naux; g.N = naux; g.K = naux; g.batch = 1; g.alpha = 1.0; g.beta = 0.0;
+  g.A = p->V; g.a_i = naux; g.a_k = 1;
+  g.B = p->Pi0; g.b_k = naux; g.b_j = 1;
+  g.C = p->Mscr; g.c_i = naux; g.c_j = 1; g.cj_in = naux; g.cj_out = 0;
+  HIP_TRY(gemm64(g, s));
+  HIP_TRY(add_identity(p->Mscr, naux, s));
+  int* piv = p->gj;
+  int* perm = p->gj + naux;
+  int* flag = p->gj + 2 * naux;
+  HIP_TRY(gj_inverse_real(p->Mscr, naux, p->Minv, p->Am, piv, perm, flag, s));
+  g.A = p->Minv; g.B = p->V; g.C = W_dev;
+  HIP_TRY(gemm64(g, s));
+  int hflag = 0;
+  HIP_TRY(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (hflag) return fail(THCSOX_ENONFINITE, "1 + V Pi0 is singular");
+  return 0;
+}
+
+int thcsox_sigma_screened(thcsox_plan_t p, const double* G_dev, const double* W_dev, int kind,
+                          double* Sigma_dev, int k_begin, int k_end) {
+  clear_error();
+  if (p == nullptr) return fail(THCSOX_EINVAL, "plan is NULL");
+  if (kind != THCSOX_SOSEX && kind != THCSOX_G3W2)
+    return fail(THCSOX_EINVAL, "unknown screened-exchange kind " + std::to_string(kind));
+  if (k_begin < 0 || k_end > p->m || k_begin >= k_end)
+    return fail(THCSOX_EINVAL, "need 0 <= k_begin < k_end <= ntau");
+  TRY(check_dev(G_dev, "G_dev"));
+  TRY(check_dev(W_dev, "W_dev"));
+  TRY(check_dev(Sigma_dev, "Sigma_dev"));
+  const size_t gbytes = sizeof(double) * (size_t)p->m * p->n * p->n;
+  const char* g0 = reinterpret_cast<const char*>(G_dev);
+  const char* s0 = reinterpret_cast<const char*>(Sigma_dev);
+  if (s0 < g0 + gbytes && g0 < s0 + gbytes) return fail(THCSOX_EINVAL, "Sigma aliases G");
+  const hipStream_t s = p->stream;
+  if (p->Uw == nullptr) {
+    char* tmp = nullptr;
+    TRY(p->alloc(&tmp, (size_t)p->np * p->esize * (size_t)p->u_plane));
+    p->Uw = tmp;
+    TRY(p->alloc(&p->amax_w, 1));
+    // the operand pads stay zero (every build writes only the first n of ldk columns)
+    HIP_TRY(hipMemsetAsync(p->Uw, 0, (size_t)p->np * p->esize * (size_t)p->u_plane, s));
+  }
+  TRY(build_u(p, W_dev, p->Uw, p->amax_w));
+  TRY(prepare_g(p, G_dev));
+  const Cores vw{p->U, p->amax, p->Uw, p->amax_w};
+  const Cores wv{p->Uw, p->amax_w, p->U, p->amax};
+  const Cores ww{p->Uw, p->amax_w, p->Uw, p->amax_w};
+  for (int k = k_begin; k < k_end; k += p->tb) {
+    const int k1 = std::min(k_end, k + p->tb);
+    if (kind == THCSOX_SOSEX) {
+      TRY(sigma_batch(p, G_dev, Sigma_dev, nullptr, k, k1, vw, 0.5, 0.0));
+      TRY(sigma_batch(p, G_dev, Sigma_dev, nullptr, k, k1, wv, 0.5, 1.0));
+    } else {
+      TRY(sigma_batch(p, G_dev, Sigma_dev, nullptr, k, k1, ww));
+    }
+  }
   return 0;
 }
 

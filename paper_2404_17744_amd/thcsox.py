@@ -33,7 +33,7 @@ EXPORTS = ("thcsox_plan", "thcsox_sigma_sox", "thcsox_energy", "thcsox_destroy",
            "thcsox_diis_create", "thcsox_diis_step", "thcsox_diis_destroy",
            "thcsox_sigma_direct", "thcsox_energy_basis", "thcsox_dyson_plan_sampled",
            "thcsox_ir_create", "thcsox_ir_sizes", "thcsox_ir_get", "thcsox_ir_destroy",
-           "thcsox_energy_noalloc")
+           "thcsox_energy_noalloc", "thcsox_static_screening", "thcsox_sigma_screened")
 SYMMETRY = {"auto": 0, "off": 1}
 STAGES = ("project", "a_stage", "fused", "back")
 
@@ -74,6 +74,10 @@ def lib() -> ctypes.CDLL:
         L.thcsox_energy.restype = i
         L.thcsox_energy_noalloc.argtypes = [vp, vp, vp, i, i, vp, vp]
         L.thcsox_energy_noalloc.restype = i
+        L.thcsox_static_screening.argtypes = [vp, vp, vp]
+        L.thcsox_static_screening.restype = i
+        L.thcsox_sigma_screened.argtypes = [vp, vp, vp, i, vp, i, i]
+        L.thcsox_sigma_screened.restype = i
         L.thcsox_destroy.argtypes = [vp]
         L.thcsox_destroy.restype = i
         L.thcsox_last_error.argtypes = []
@@ -184,6 +188,18 @@ def thcsox_energy(plan, G_dev: int, Sigma_dev: int) -> float:
 def thcsox_energy_noalloc(G_dev: int, Sigma_dev: int, w_dev: int, n: int, ntau: int,
                           E_dev: int, hip_stream: int = 0) -> None:
     _check(lib().thcsox_energy_noalloc(G_dev, Sigma_dev, w_dev, n, ntau, E_dev, hip_stream))
+
+
+SCREENED = {"sosex": 0, "g3w2": 1}
+
+
+def thcsox_static_screening(plan, G_dev: int, W_dev: int) -> None:
+    _check(lib().thcsox_static_screening(plan, G_dev, W_dev))
+
+
+def thcsox_sigma_screened(plan, G_dev: int, W_dev: int, kind: int, Sigma_dev: int,
+                          k_begin: int, k_end: int) -> None:
+    _check(lib().thcsox_sigma_screened(plan, G_dev, W_dev, kind, Sigma_dev, k_begin, k_end))
 
 
 def thcsox_destroy(plan) -> None:
@@ -556,6 +572,31 @@ class Plan:
         _dev64(out, "out", (self.n, self.n), k_end)
         _check(_ordered(self.stream, lib().thcsox_sigma_direct, self.handle, G.data_ptr(),
                         out.data_ptr(), k_begin, k_end, 1 if accumulate else 0))
+        return out
+
+    def static_screening(self, G, out=None):
+        """Statically screened core W = (1 + V Pi0)^-1 V [naux][naux] (FP64)."""
+        import torch
+        _dev64(G, "G", (self.n, self.n), self.ntau, exact=True)
+        if out is None:
+            out = torch.empty((self.naux, self.naux), dtype=torch.float64, device=self.device)
+        _dev64(out, "out", (self.naux,), self.naux, exact=True)
+        _check(_ordered(self.stream, lib().thcsox_static_screening, self.handle, G.data_ptr(),
+                        out.data_ptr()))
+        return out
+
+    def sigma_screened(self, G, W, kind: str = "sosex", k_begin: int = 0,
+                       k_end: int | None = None, out=None):
+        """Screened exchange self-energy ("sosex": one line screened, "g3w2": both)."""
+        import torch
+        k_end = self.ntau if k_end is None else k_end
+        _dev64(G, "G", (self.n, self.n), self.ntau, exact=True)
+        _dev64(W, "W", (self.naux,), self.naux, exact=True)
+        if out is None:
+            out = torch.zeros((self.ntau, self.n, self.n), dtype=torch.float64, device=self.device)
+        _dev64(out, "out", (self.n, self.n), k_end)
+        _check(_ordered(self.stream, lib().thcsox_sigma_screened, self.handle, G.data_ptr(),
+                        W.data_ptr(), SCREENED[kind], out.data_ptr(), k_begin, k_end))
         return out
 
     def energy(self, G, Sigma) -> float:
