@@ -1,4 +1,4 @@
-"""Parity at the full n=300 / naux=1800 / 100-tau size (seed 0), in the same
+"""Parity at the full n=300 / naux=1800 / 100-tau size (seeds 0-4), in the same
 launch configuration the throughput measurement uses (one plan, all tau points
 in one call), against stored FP64 oracle values written by
 tests/golden/make_oracle_golden.py (the paper's order of contractions, FP64,
@@ -7,7 +7,9 @@ every tau point).
 Bars: FP64 path 1e-10 relative on the sampled Sigma elements and 1e-8 Ha in
 energy; mixed paths 1e-6 Ha in energy and 1e-6 relative on the samples.
 Properties that hold at any size are checked too: Sigma(tau) is symmetric for
-symmetric inputs, and the mixed paths agree with the GPU FP64 path.
+symmetric inputs, and the mixed paths agree with the GPU FP64 path.  Seed 0 runs
+all four precisions; every other seed with stored oracle values runs the FP64
+path and the fp16x2 path the throughput measurement uses.
 """
 import json
 import os
@@ -83,3 +85,35 @@ def test_fullsize_vs_oracle(case, precision):
             d = (S - case["S64"]).abs().max().item() / case["S64"].abs().max().item()
             print(f"  vs GPU FP64 path: max rel {d:.2e}")
             assert d <= 1e-6
+
+
+def _seeds_with_golden():
+    out = []
+    for sd in range(1, 5):
+        if os.path.exists(os.path.join(os.path.dirname(__file__), "golden",
+                                       f"oracle_{NAME}_seed{sd}.json")):
+            out.append(sd)
+    return out
+
+
+@pytest.mark.parametrize("seed", _seeds_with_golden())
+def test_fullsize_other_seeds(dev, seed):
+    print(f"case {NAME} seed {seed} fp64 + fp16x2", flush=True)
+    s, tau, w, G, beta = synth.workload(NAME, seed=seed)
+    with open(os.path.join(os.path.dirname(__file__), "golden",
+                           f"oracle_{NAME}_seed{seed}.json")) as f:
+        gold = json.load(f)
+    print("  input digest", s.digest(), "golden", gold["input_digest"], flush=True)
+    X = torch.from_numpy(s.X).to(dev)
+    V = torch.from_numpy(s.V).to(dev)
+    Gd = torch.from_numpy(G).to(dev)
+    case = dict(X=X, V=V, G=Gd, tau=tau, w=w, beta=beta)
+    S64, E64, _ = _evaluate(case, "fp64")
+    S16, E16, _ = _evaluate(case, "fp16x2")
+    e64, e16 = _sample_err(S64, gold), _sample_err(S16, gold)
+    print(f"  fp64: dE {E64 - gold['E_sox']:.2e} sampled rel {e64:.2e}; "
+          f"fp16x2: dE {E16 - gold['E_sox']:.2e} sampled rel {e16:.2e}")
+    assert abs(E64 - gold["E_sox"]) <= 1e-8 and e64 <= 1e-10
+    assert abs(E16 - gold["E_sox"]) <= 1e-6 and e16 <= 1e-6
+    d = (S16 - S64).abs().max().item() / S64.abs().max().item()
+    assert d <= 1e-6
