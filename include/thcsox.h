@@ -407,10 +407,11 @@ int thcsox_mlp_destroy(thcsox_mlp_t q);
 
 /* Network inputs and outputs in the THC basis.  S is a THC-basis self-energy
  * [m][naux][naux] (FP64, device); a "pair" is the flat index R*naux + P.
- *   thcsox_pair_scale  : scale[k] = max_RP |S[k][R][P]| (1 if zero), FP64 [m].
- *   thcsox_pair_gather : x[b][k] = S[k][pairs[b]] / scale[k] (pairs NULL: all
- *                        naux^2 pairs in order), FP32 [npairs][m].
- *   thcsox_pair_scatter: S[k][p] = y[p][k] * scale[k] for all naux^2 pairs.
+ *   thcsox_pair_scale  : scale[p] = max_k |S[k][p]| (1 if zero), the pair's
+ *                        largest magnitude over tau, FP64 [naux^2].
+ *   thcsox_pair_gather : x[b][k] = S[k][pairs[b]] / scale[pairs[b]] (pairs NULL:
+ *                        all naux^2 pairs in order), FP32 [npairs][m].
+ *   thcsox_pair_scatter: S[k][p] = y[p][k] * scale[p] for all naux^2 pairs.
  * All asynchronous on hip_stream. */
 int thcsox_pair_scale(int m, int naux, const double* S_dev, double* scale_dev, void* hip_stream);
 int thcsox_pair_gather(int m, int naux, const double* S_dev, const double* scale_dev,

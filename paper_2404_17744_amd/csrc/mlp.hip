@@ -1,8 +1,8 @@
 // Residual MLP of the learned warm start: training and inference on the GPU.
 //
 // The network maps the tau-profile of one THC pair's first-iteration
-// self-energy (m values, normalised per tau point) to the profile of the
-// converged one:
+// self-energy (m values, divided by the pair's largest magnitude over tau) to
+// the profile of the converged one (divided by the same number):
 //     z1 = x W1^T + b1,  h1 = silu(z1)          W1: [H][m]
 //     z2 = h1 W2^T + b2, h2 = silu(z2)          W2: [H][H]
 //     y  = x + h2 W3^T + b3                     W3: [m][H]
@@ -175,22 +175,17 @@ __global__ void adam(float* p, const float* g, float* m1, float* m2, int64_t cou
   }
 }
 
-// scale[k] = max_e |S[k][e]| over the naux^2 pair entries (1 if all zero)
-__global__ void pair_scale_kernel(const double* S, int64_t aa, double* scale) {
-  __shared__ double red[NT];
-  const int k = blockIdx.x;
-  double mx = 0.0;
-  for (int64_t e = threadIdx.x; e < aa; e += NT) mx = fmax(mx, fabs(S[(int64_t)k * aa + e]));
-  red[threadIdx.x] = mx;
-  __syncthreads();
-  for (int o = NT / 2; o > 0; o >>= 1) {
-    if (threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
-    __syncthreads();
+// scale[e] = max_k |S[k][e]| over the m tau points of pair e (1 if all zero);
+// consecutive threads take consecutive pairs, so every read of a tau slice is coalesced
+__global__ void pair_scale_kernel(const double* S, int m, int64_t aa, double* scale) {
+  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < aa; e += (int64_t)gridDim.x * NT) {
+    double mx = 0.0;
+    for (int k = 0; k < m; ++k) mx = fmax(mx, fabs(S[(int64_t)k * aa + e]));
+    scale[e] = mx > 0.0 ? mx : 1.0;
   }
-  if (threadIdx.x == 0) scale[k] = red[0] > 0.0 ? red[0] : 1.0;
 }
 
-// x[b][k] = S[k][pair_b] / scale[k]; pair_b = pairs[b] (or b if pairs is null)
+// x[b][k] = S[k][pair_b] / scale[pair_b]; pair_b = pairs[b] (or b if pairs is null)
 __global__ void pair_gather_kernel(const double* S, int m, int64_t aa, const double* scale,
                                    const int64_t* pairs, int64_t npairs, float* x) {
   for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < npairs * m;
@@ -198,17 +193,17 @@ __global__ void pair_gather_kernel(const double* S, int m, int64_t aa, const dou
     const int64_t b = e / m;
     const int k = (int)(e % m);
     const int64_t pr = pairs ? pairs[b] : b;
-    x[e] = (pr >= 0 && pr < aa) ? (float)(S[(int64_t)k * aa + pr] / scale[k]) : 0.f;
+    x[e] = (pr >= 0 && pr < aa) ? (float)(S[(int64_t)k * aa + pr] / scale[pr]) : 0.f;
   }
 }
 
-// S[k][pair] = y[pair][k] * scale[k] for every pair
+// S[k][pair] = y[pair][k] * scale[pair] for every pair
 __global__ void pair_scatter_kernel(const float* y, int m, int64_t aa, const double* scale,
                                     double* S) {
   for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < aa * m; e += (int64_t)gridDim.x * NT) {
     const int k = (int)(e / aa);
     const int64_t pr = e % aa;
-    S[e] = (double)y[pr * m + k] * scale[k];
+    S[e] = (double)y[pr * m + k] * scale[pr];
   }
 }
 
@@ -435,8 +430,9 @@ int thcsox_pair_scale(int m, int naux, const double* S_dev, double* scale_dev, v
   clear_error();
   if (m <= 0 || naux <= 0 || S_dev == nullptr || scale_dev == nullptr)
     return set_error(THCSOX_EINVAL, "bad argument");
-  pair_scale_kernel<<<m, NT, 0, static_cast<hipStream_t>(hip_stream)>>>(
-      S_dev, (int64_t)naux * naux, scale_dev);
+  const int64_t aa = (int64_t)naux * naux;
+  pair_scale_kernel<<<blocks_for(aa), NT, 0, static_cast<hipStream_t>(hip_stream)>>>(
+      S_dev, m, aa, scale_dev);
   MTRY(hipGetLastError());
   return 0;
 }

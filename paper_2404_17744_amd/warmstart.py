@@ -55,8 +55,26 @@ class SCF:
 
     def run(self, Sigma_start=None, count_start=0):
         """Iterate from Dyson(Sigma_start) (Hartree-Fock start if None) until
-        |dE| < tol.  Returns (evaluations, energies, converged)."""
-        torch = self.torch
+        |dE| < tol.  Returns (evaluations, energies, converged).
+
+        A start that is unusable -- the Dyson step refuses it (a non-finite or
+        singular matrix) or the first energy from it is not finite -- falls back
+        to the Hartree-Fock start; the evaluations already spent stay counted
+        and ``self.fell_back`` records it."""
+        self.fell_back = False
+        if Sigma_start is None:
+            return self._iterate(None, count_start)
+        try:
+            evals, energies, ok = self._iterate(Sigma_start, count_start)
+            if energies and np.isfinite(energies[0]):
+                return evals, energies, ok
+        except thcsox.ThcsoxError:
+            evals, energies = count_start, []
+        self.fell_back = True
+        ev, E, ok = self._iterate(None, evals)
+        return ev, energies + E, ok
+
+    def _iterate(self, Sigma_start, count_start):
         S0 = self.S.zero_() if Sigma_start is None else Sigma_start
         G, gam = self.dyson.step(S0)
         energies, Sold = [], None
@@ -82,7 +100,7 @@ class SCF:
 
 
 def pair_profiles(Sthc, scale, pairs=None, out=None):
-    """x[b][k] = Sthc[k][pair_b] / scale[k] via thcsox_pair_gather."""
+    """x[b][k] = Sthc[k][pair_b] / scale[pair_b] via thcsox_pair_gather."""
     torch = __import__("torch")
     m, A = Sthc.shape[0], Sthc.shape[1]
     npairs = A * A if pairs is None else pairs.numel()
@@ -95,9 +113,10 @@ def pair_profiles(Sthc, scale, pairs=None, out=None):
 
 
 def pair_scale(Sthc):
+    """scale[p] = max_k |Sthc[k][p]|: each pair's largest magnitude over tau."""
     torch = __import__("torch")
     m, A = Sthc.shape[0], Sthc.shape[1]
-    scale = torch.empty(m, dtype=torch.float64, device=Sthc.device)
+    scale = torch.empty(A * A, dtype=torch.float64, device=Sthc.device)
     thcsox.thcsox_pair_scale(m, A, Sthc.data_ptr(), scale.data_ptr(),
                              torch.cuda.current_stream().cuda_stream)
     return scale
@@ -161,38 +180,70 @@ def train(x, t, hidden=512, epochs=30, batch=4096, lr=1e-3, seed=0, log=print):
 
 def warm_sigma(scf, net):
     """Predicted converged Sigma(tau) in the orbital basis for scf's system."""
+    return warm_sigmas([scf], net)[0]
+
+
+def warm_sigmas(scfs, net):
+    """Predicted converged Sigma(tau) for several systems at once: the first
+    SOX evaluation of each, then ONE network forward over the THC pairs of all
+    of them (a ragged batch: system i contributes its naux_i^2 pair profiles),
+    then the scatter back to each system's THC basis and the back-projection."""
     torch = __import__("torch")
-    scf.first_sigma_thc()
-    S1 = scf.Sthc
-    scale = pair_scale(S1)
-    x = pair_profiles(S1, scale)
+    xs, scales = [], []
+    for scf in scfs:
+        scf.first_sigma_thc()
+        scale = pair_scale(scf.Sthc)
+        xs.append(pair_profiles(scf.Sthc, scale))
+        scales.append(scale)
+    x = xs[0] if len(xs) == 1 else torch.cat(xs)
     y = net.forward(x)
-    pred = torch.empty_like(S1)
-    m, A = S1.shape[0], S1.shape[1]
-    thcsox.thcsox_pair_scatter(m, A, y.data_ptr(), scale.data_ptr(), pred.data_ptr(),
-                               torch.cuda.current_stream().cuda_stream)
-    return scf.plan.backproject(pred)
+    out, o = [], 0
+    for scf, scale in zip(scfs, scales):
+        m, A = scf.Sthc.shape[0], scf.Sthc.shape[1]
+        pred = torch.empty_like(scf.Sthc)
+        thcsox.thcsox_pair_scatter(m, A, y[o:o + A * A].data_ptr(), scale.data_ptr(),
+                                   pred.data_ptr(), torch.cuda.current_stream().cuda_stream)
+        o += A * A
+        out.append(scf.plan.backproject(pred))
+    return out
+
+
+def inference_net(net, max_batch=65536):
+    """A copy of a trained network sized for large inference batches."""
+    p = net.params()
+    return thcsox.MLP(net.m, net.H, p, max_batch=max_batch)
 
 
 def evaluate(seeds, lam, net, precision="fp16x2", damping=1.0, log=print, n_range=(40, 160)):
-    """Iterations (SOX evaluations) to |dE| < 1e-7 from the HF start and from
-    the warm start, and the wall time of each, for every system."""
+    """SOX evaluations to |dE| < 1e-7 from the Hartree-Fock start and from the
+    learned start, for every system, and the wall time of each.  The learned
+    starts of all systems are predicted as one ragged batch (warm_sigmas); the
+    warm wall time of a system is its own iteration time plus its share (by
+    pair count) of the batched first evaluations and inference."""
     torch = __import__("torch")
+    systems = [synth.warmstart_system(sd, lam, n_range) for sd in seeds]
+    scfs = [SCF(s, precision=precision, damping=damping) for s in systems]
     rows = []
-    for sd in seeds:
-        s = synth.warmstart_system(sd, lam, n_range)
-        scf = SCF(s, precision=precision, damping=damping)
+    for sd, s, scf in zip(seeds, systems, scfs):
         torch.cuda.synchronize(); t0 = time.time()
         ev_hf, E_hf, ok_hf = scf.run()
         torch.cuda.synchronize(); t1 = time.time()
-        Sw = warm_sigma(scf, net).clone()
+        rows.append({"seed": sd, "n": s.n, "hf_evals": ev_hf, "hf_converged": ok_hf,
+                     "E_hf": E_hf[-1], "hf_s": t1 - t0})
+    torch.cuda.synchronize(); t0 = time.time()
+    preds = warm_sigmas(scfs, net)
+    torch.cuda.synchronize(); t_pred = time.time() - t0
+    pairs = np.array([s.naux ** 2 for s in systems], dtype=float)
+    for r, s, scf, Sw in zip(rows, systems, scfs, preds):
+        torch.cuda.synchronize(); t0 = time.time()
         ev_w, E_w, ok_w = scf.run(Sigma_start=Sw, count_start=1)
-        torch.cuda.synchronize(); t2 = time.time()
-        rows.append({"seed": sd, "n": s.n, "hf_evals": ev_hf, "warm_evals": ev_w,
-                     "hf_converged": ok_hf, "warm_converged": ok_w, "E_hf": E_hf[-1],
-                     "E_warm": E_w[-1], "hf_s": t1 - t0, "warm_s": t2 - t1})
-        log(f"  eval {sd}: n={s.n} HF {ev_hf} evals ({t1 - t0:.2f} s)  warm {ev_w} evals "
-            f"({t2 - t1:.2f} s)  dE_final {E_w[-1] - E_hf[-1]:.2e}")
+        torch.cuda.synchronize(); t1 = time.time()
+        r.update({"warm_evals": ev_w, "warm_converged": ok_w, "E_warm": E_w[-1],
+                  "warm_fell_back": scf.fell_back,
+                  "warm_s": (t1 - t0) + t_pred * s.naux ** 2 / pairs.sum()})
+        log(f"  eval {r['seed']}: n={s.n} HF {r['hf_evals']} evals ({r['hf_s']:.2f} s)  "
+            f"warm {ev_w} evals ({r['warm_s']:.2f} s)  dE_final {E_w[-1] - r['E_hf']:.2e}")
+    for scf in scfs:
         scf.close()
     return rows
 
@@ -222,7 +273,9 @@ def main():
     t0 = time.time()
     net, losses = train(x, t, hidden=a.hidden, epochs=a.epochs)
     t_train = time.time() - t0
-    rows = evaluate(ev, a.lam, net, a.precision, a.damping, n_range=nr)
+    inet = inference_net(net)
+    rows = evaluate(ev, a.lam, inet, a.precision, a.damping, n_range=nr)
+    inet.close()
     hf = np.array([r["hf_evals"] for r in rows]); wm = np.array([r["warm_evals"] for r in rows])
     res = {"lam": a.lam, "damping": a.damping, "train_systems": len(tr), "eval_systems": len(ev),
            "n_range": list(nr), "train_loop_evals_mean": float(np.mean([r["evals"] for r in st])),
@@ -233,6 +286,9 @@ def main():
            "hf_time_mean_s": float(np.mean([r["hf_s"] for r in rows])),
            "warm_time_mean_s": float(np.mean([r["warm_s"] for r in rows])),
            "max_final_energy_diff": float(max(abs(r["E_warm"] - r["E_hf"]) for r in rows)),
+           "systems_saved": int(sum(r["warm_evals"] < r["hf_evals"] for r in rows)),
+           "systems_worse": int(sum(r["warm_evals"] > r["hf_evals"] for r in rows)),
+           "fell_back": int(sum(r["warm_fell_back"] for r in rows)),
            "all_converged": bool(all(r["hf_converged"] and r["warm_converged"] for r in rows)),
            "rows": rows}
     print(json.dumps({k: v for k, v in res.items() if k != "rows"}), flush=True)

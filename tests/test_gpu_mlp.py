@@ -101,12 +101,17 @@ def test_pair_gather_scatter_roundtrip(dev):
     m, A = 8, 40
     rng = np.random.default_rng(0)
     S = torch.from_numpy(rng.standard_normal((m, A, A))).to(dev)
+    S[:, 3, 7] = 0.0                                  # an all-zero pair keeps scale 1
     scale = warmstart.pair_scale(S)
-    np.testing.assert_allclose(scale.cpu().numpy(), np.abs(S.cpu().numpy()).reshape(m, -1).max(1))
+    Sn = S.cpu().numpy().reshape(m, -1)
+    ref_scale = np.abs(Sn).max(0)
+    ref_scale[ref_scale == 0] = 1.0
+    np.testing.assert_allclose(scale.cpu().numpy(), ref_scale)
     x = warmstart.pair_profiles(S, scale)
     assert x.shape == (A * A, m)
-    ref = (S.cpu().numpy().reshape(m, -1) / scale.cpu().numpy()[:, None]).T
+    ref = (Sn / ref_scale[None, :]).T
     assert np.abs(x.cpu().numpy() - ref).max() < 1e-7
+    assert np.abs(x.cpu().numpy()).max() <= 1.0
     back = torch.empty_like(S)
     thcsox.thcsox_pair_scatter(m, A, x.data_ptr(), scale.data_ptr(), back.data_ptr(),
                                torch.cuda.current_stream().cuda_stream)
