@@ -6,8 +6,9 @@ of the chemical potential") and the size-consistency appendix ("Case 2:
 optimized chemical potential": mu is chosen every iteration so that the average
 electron number stays fixed; damping and DIIS-type linear combinations of
 self-energies are allowed).  The paper uses frequency-dependent commutator DIIS
-from a companion paper; what is built here is plain Pulay DIIS on the
-self-energy residual (the paper's variant is not specified in this paper).
+from a companion paper and does not print it; two variants are built here:
+plain Pulay DIIS on the self-energy residual, and a commutator DIIS whose
+residual lives on the Matsubara grid (the reading below).
 
 * N(mu) = Tr gamma(mu), gamma = -G(beta^-) from one Dyson solve at mu with the
   given Sigma (N increases with mu).
@@ -18,6 +19,15 @@ self-energy residual (the paper's variant is not specified in this paper).
 * Pulay DIIS: residuals r_i = Sigma_out_i - Sigma_in_i of the last `depth`
   iterations; coefficients c minimise |sum_i c_i r_i|^2 subject to sum_i c_i = 1
   ((k+1) x (k+1) bordered system with B_ij = <r_i, r_j>); Sigma_next =
+  sum_i c_i Sigma_out_i.
+* Commutator DIIS (reading): at self-consistency G(i w) commutes with the
+  matrix it inverts, so with G_i = Dyson(Sigma_in_i) the frequency-dependent
+  error of iteration i is the commutator with the new self-energy,
+      e_i(i w_n) = [G_i(i w_n), F + Sigma_out_i(i w_n)]
+                 = G_i D_i - D_i G_i,    D_i = Sigma_out_i(i w_n) - Sigma_in_i(i w_n)
+  (the two forms agree because G_i commutes with F + Sigma_in_i), on the kept
+  frequencies n >= 0 (the n < 0 ones are complex conjugates); B_ij =
+  Re sum_n Tr[e_i(i w_n)^H e_j(i w_n)], the same bordered system, Sigma_next =
   sum_i c_i Sigma_out_i.
 """
 from __future__ import annotations
@@ -98,6 +108,37 @@ def diis_next(inputs: list, outputs: list) -> np.ndarray:
     for i in range(k):
         for j in range(k):
             B[i, j] = float(np.dot(res[i].ravel(), res[j].ravel()))
+    B[k, :k] = 1.0
+    B[:k, k] = 1.0
+    rhs = np.zeros(k + 1)
+    rhs[k] = 1.0
+    c = np.linalg.solve(B, rhs)[:k]
+    out = np.zeros_like(outputs[0])
+    for ci, o in zip(c, outputs):
+        out += ci * o
+    return out
+
+
+def commutator_residual(G_iw: np.ndarray, D_iw: np.ndarray) -> np.ndarray:
+    """e(i w_n) = G(i w_n) D(i w_n) - D(i w_n) G(i w_n) for every kept n."""
+    return np.matmul(G_iw, D_iw) - np.matmul(D_iw, G_iw)
+
+
+def commutator_residual_definition(G_iw: np.ndarray, F: np.ndarray,
+                                   Sout_iw: np.ndarray) -> np.ndarray:
+    """[G(i w_n), F + Sigma_out(i w_n)] written out (the defining form)."""
+    H = F[None, :, :] + Sout_iw
+    return np.matmul(G_iw, H) - np.matmul(H, G_iw)
+
+
+def cdiis_next(residuals: list, outputs: list) -> np.ndarray:
+    """Extrapolation with B_ij = Re sum Tr[e_i^H e_j] over the given history of
+    frequency-dependent residuals and output self-energies (tau)."""
+    k = len(residuals)
+    B = np.zeros((k + 1, k + 1))
+    for i in range(k):
+        for j in range(k):
+            B[i, j] = float(np.real(np.vdot(residuals[i].ravel(), residuals[j].ravel())))
     B[k, :k] = 1.0
     B[:k, k] = 1.0
     rhs = np.zeros(k + 1)
