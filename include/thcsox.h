@@ -377,6 +377,34 @@ int thcsox_diis_create(thcsox_diis_t* out, int64_t len, int depth, void* hip_str
 int thcsox_diis_step(thcsox_diis_t d, const double* sigma_in, const double* sigma_out,
                      double* sigma_next, int* n_used_out);
 
+/* Commutator DIIS (the paper's loop uses a frequency-dependent commutator DIIS
+ * from the algorithms paper it cites, Sec. "Computational details"; that
+ * paper's formula is not printed, reading used): with G_i = Dyson(Sigma_in_i),
+ * G_i(i w) commutes with the matrix it inverts, so the error of iteration i is
+ *     e_i(i w_n) = [G_i(i w_n), F + Sigma_out_i(i w_n)]
+ *                = G_i D_i - D_i G_i,   D_i = Sigma_out_i(i w_n) - Sigma_in_i(i w_n)
+ * on the plan's frequencies (n >= 0).  thcsox_dyson_commutator writes e for
+ * the G(i w) of the plan's last Dyson step (which must have been taken with
+ * Sigma_in_dev): e_dev [2][nfreq][n][n] (real parts, then imaginary parts),
+ * FP64 matrix cores, asynchronous.  The first call allocates 2 nfreq n^2
+ * doubles (kept by the plan).  THCSOX_EINVAL before the plan's first step. */
+int thcsox_dyson_commutator(thcsox_dyson_t d, const double* Sigma_in_dev,
+                            const double* Sigma_out_dev, double* e_dev);
+
+/* A DIIS history whose residuals the caller supplies (len_res doubles each,
+ * e.g. the commutator of thcsox_dyson_commutator, len_res = 2 nfreq n^2) next
+ * to the extrapolated vectors (len doubles, Sigma_out): thcsox_diis_step_res
+ * adds (residual, sigma_out) and writes sigma_next = sum_i c_i Sigma_out_i with
+ * c minimising |sum_i c_i e_i|^2 under sum_i c_i = 1 (B_ij = <e_i, e_j> over all
+ * real and imaginary parts, i.e. Re sum_n Tr[e_i^H e_j]), dropping the oldest
+ * entries while the bordered system is singular.  sigma_next may alias the
+ * inputs.  Synchronises the stream.  A history made by thcsox_diis_create
+ * refuses thcsox_diis_step_res and vice versa (THCSOX_EINVAL). */
+int thcsox_diis_create_res(thcsox_diis_t* out, int64_t len, int64_t len_res, int depth,
+                           void* hip_stream);
+int thcsox_diis_step_res(thcsox_diis_t d, const double* residual, const double* sigma_out,
+                         double* sigma_next, int* n_used_out);
+
 int thcsox_diis_destroy(thcsox_diis_t d);
 
 /* ---------------------------------------------------------------------------

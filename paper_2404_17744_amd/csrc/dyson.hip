@@ -545,6 +545,8 @@ struct thcsox_dyson_s {
   int* flag = nullptr;
   double* scal = nullptr;
   double* traces = nullptr;   // [2 nw]
+  double* Dw = nullptr;       // [2nw][n n], commutator DIIS: Sigma_out - Sigma_in in frequency
+  bool have_g = false;        // Gs holds the G(i w) of a completed step
   std::vector<double> gamma_row;   // the gamma row of Wb (host)
   std::vector<void*> allocs;
   ~thcsox_dyson_s() {
@@ -637,6 +639,7 @@ int dy_backward(thcsox_dyson_s* d, double* G_dev, double* gamma_dev) {
   const unsigned bx = (unsigned)std::min<int64_t>(64, (nn + NT - 1) / NT);
   extract_inv<<<dim3(bx, nw), NT, 0, s>>>(d->Am, d->perm, n, nw, d->Gs);
   DTRY(hipGetLastError());
+  d->have_g = true;
   // [G(tau_0) .. G(tau_{m-1}); gamma] = Wb . [Re G(i w); Im G(i w)]
   Gemm64Args g{};
   g.M = m + 1; g.N = (int)nn; g.K = 2 * nw; g.batch = 1; g.alpha = 1.0; g.beta = 0.0;
@@ -839,6 +842,59 @@ int thcsox_dyson_step_mu(thcsox_dyson_t d, const double* Sigma_dev, double nelec
   *mu_io = mu;
   if (evals_out) *evals_out = evals;
   return dy_backward(d, G_dev, gamma_dev);
+}
+
+int thcsox_dyson_commutator(thcsox_dyson_t d, const double* Sigma_in_dev,
+                            const double* Sigma_out_dev, double* e_dev) {
+  clear_error();
+  if (d == nullptr || Sigma_in_dev == nullptr || Sigma_out_dev == nullptr || e_dev == nullptr)
+    return dfail(THCSOX_EINVAL, "NULL argument");
+  for (const void* q : {(const void*)Sigma_in_dev, (const void*)Sigma_out_dev, (const void*)e_dev}) {
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, q) != hipSuccess ||
+        (a.type != hipMemoryTypeDevice && a.type != hipMemoryTypeManaged)) {
+      (void)hipGetLastError();
+      return dfail(THCSOX_ENOTDEV, "arrays must be device memory");
+    }
+  }
+  if (!d->have_g) return dfail(THCSOX_EINVAL, "no Dyson step has been taken on this plan");
+  const int n = d->n, nw = d->nw, m = d->m;
+  const int64_t nn = (int64_t)n * n;
+  const hipStream_t s = d->stream;
+  if (d->Dw == nullptr) {
+    int rc = dalloc(d, &d->Dw, (size_t)2 * nw * nn);
+    if (rc) return rc;
+  }
+  // D(i w) = Wf (Sigma_out - Sigma_in), as [Re; Im] rows
+  Gemm64Args g{};
+  g.M = 2 * nw; g.N = (int)nn; g.K = m; g.batch = 1; g.alpha = 1.0; g.beta = 0.0;
+  g.A = d->Wf; g.a_i = m; g.a_k = 1;
+  g.B = Sigma_out_dev; g.b_k = nn; g.b_j = 1;
+  g.C = d->Dw; g.c_i = nn; g.c_j = 1; g.cj_in = nn; g.cj_out = 0;
+  DTRY(gemm64(g, s));
+  g.B = Sigma_in_dev; g.alpha = -1.0; g.beta = 1.0;
+  DTRY(gemm64(g, s));
+  // e = G D - D G per frequency, G = Gr + i Gi from the last step (d->Gs), D = Dr + i Di:
+  //   Re e = Gr Dr - Gi Di - Dr Gr + Di Gi,  Im e = Gr Di + Gi Dr - Dr Gi - Di Gr
+  const double* Gr = d->Gs;
+  const double* Gi = d->Gs + (int64_t)nw * nn;
+  const double* Dr = d->Dw;
+  const double* Di = d->Dw + (int64_t)nw * nn;
+  double* er = e_dev;
+  double* ei = e_dev + (int64_t)nw * nn;
+  struct Term { const double* A; const double* B; double alpha; double* C; };
+  const Term terms[8] = {{Gr, Dr, 1.0, er}, {Gi, Di, -1.0, er}, {Dr, Gr, -1.0, er}, {Di, Gi, 1.0, er},
+                         {Gr, Di, 1.0, ei}, {Gi, Dr, 1.0, ei}, {Dr, Gi, -1.0, ei}, {Di, Gr, -1.0, ei}};
+  for (int t = 0; t < 8; ++t) {
+    Gemm64Args b{};
+    b.M = n; b.N = n; b.K = n; b.batch = nw; b.alpha = terms[t].alpha;
+    b.beta = (t == 0 || t == 4) ? 0.0 : 1.0;
+    b.A = terms[t].A; b.a_i = n; b.a_k = 1; b.a_b = nn;
+    b.B = terms[t].B; b.b_k = n; b.b_j = 1; b.b_b = nn;
+    b.C = terms[t].C; b.c_i = n; b.c_j = 1; b.cj_in = n; b.cj_out = 0; b.c_b = nn;
+    DTRY(gemm64(b, s));
+  }
+  return 0;
 }
 
 int thcsox_dyson_onebody(thcsox_dyson_t d, const double* gamma_dev, double* E1_host) {

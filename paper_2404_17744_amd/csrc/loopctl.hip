@@ -129,7 +129,9 @@ bool solve_bordered(const std::vector<double>& B, int k, std::vector<double>& c)
 }  // namespace
 
 struct thcsox_diis_s {
-  int64_t len = 0;
+  int64_t len = 0;     // doubles per extrapolated vector
+  int64_t len_e = 0;   // doubles per residual (len for the Pulay residual)
+  bool explicit_residual = false;   // residuals given by the caller (thcsox_diis_step_res)
   int depth = 0;
   hipStream_t stream = nullptr;
   std::vector<double*> in, res;   // ring of device arrays
@@ -147,7 +149,7 @@ struct thcsox_diis_s {
 
 namespace {
 int dot_dev(thcsox_diis_s* d, const double* x, const double* y, double* out) {
-  dot_partials<<<DOT_BLOCKS, NT, 0, d->stream>>>(d->len, x, y, d->part);
+  dot_partials<<<DOT_BLOCKS, NT, 0, d->stream>>>(d->len_e, x, y, d->part);
   LTRY(hipGetLastError());
   sum_partials<<<1, NT, 0, d->stream>>>(d->part, DOT_BLOCKS, d->scalar);
   LTRY(hipGetLastError());
@@ -173,13 +175,17 @@ int thcsox_mix(int64_t len, double alpha, const double* sigma_out, double* sigma
   return 0;
 }
 
-static int thcsox_diis_create_impl(thcsox_diis_t* out, int64_t len, int depth, void* hip_stream) {
+static int thcsox_diis_create_impl(thcsox_diis_t* out, int64_t len, int64_t len_e,
+                                   bool explicit_residual, int depth, void* hip_stream) {
   clear_error();
   if (out == nullptr) return lfail(THCSOX_EINVAL, "out is NULL");
   *out = nullptr;
-  if (len <= 0 || depth < 1) return lfail(THCSOX_EINVAL, "need len > 0 and depth >= 1");
+  if (len <= 0 || len_e <= 0 || depth < 1)
+    return lfail(THCSOX_EINVAL, "need len > 0, len_e > 0 and depth >= 1");
   auto* d = new thcsox_diis_s();
   d->len = len;
+  d->len_e = len_e;
+  d->explicit_residual = explicit_residual;
   d->depth = depth;
   d->stream = static_cast<hipStream_t>(hip_stream);
   d->dots.assign((size_t)depth * depth, 0.0);
@@ -194,7 +200,7 @@ static int thcsox_diis_create_impl(thcsox_diis_t* out, int64_t len, int depth, v
   bool ok = alloc(&d->part, DOT_BLOCKS) && alloc(&d->scalar, 1);
   for (int i = 0; ok && i < depth; ++i) {
     double *a = nullptr, *b = nullptr;
-    ok = alloc(&a, (size_t)len) && alloc(&b, (size_t)len);
+    ok = alloc(&a, (size_t)len) && alloc(&b, (size_t)len_e);
     if (a) d->in.push_back(a);
     if (b) d->res.push_back(b);
   }
@@ -208,23 +214,23 @@ static int thcsox_diis_create_impl(thcsox_diis_t* out, int64_t len, int depth, v
 
 int thcsox_diis_create(thcsox_diis_t* out, int64_t len, int depth, void* hip_stream) {
   try {   // host containers: no exception may cross the C interface
-    return thcsox_diis_create_impl(out, len, depth, hip_stream);
+    return thcsox_diis_create_impl(out, len, len, false, depth, hip_stream);
   } catch (const std::bad_alloc&) {
     return lfail(THCSOX_ENOMEM, "host allocation failed");
   }
 }
 
-static int thcsox_diis_step_impl(thcsox_diis_t d, const double* sigma_in, const double* sigma_out,
-                     double* sigma_next, int* n_used_out) {
-  clear_error();
-  if (d == nullptr || sigma_in == nullptr || sigma_out == nullptr || sigma_next == nullptr)
-    return lfail(THCSOX_EINVAL, "NULL argument");
-  if (sigma_next == sigma_out) return lfail(THCSOX_EINVAL, "sigma_next may not alias sigma_out");
-  if (!is_device(sigma_in) || !is_device(sigma_out) || !is_device(sigma_next))
-    return lfail(THCSOX_ENOTDEV, "arrays must be device memory");
-  const hipStream_t s = d->stream;
-  const unsigned gb = grid_for(d->len);
-  // the slot for the new entry: a free one, else the oldest
+int thcsox_diis_create_res(thcsox_diis_t* out, int64_t len, int64_t len_res, int depth,
+                           void* hip_stream) {
+  try {
+    return thcsox_diis_create_impl(out, len, len_res, true, depth, hip_stream);
+  } catch (const std::bad_alloc&) {
+    return lfail(THCSOX_ENOMEM, "host allocation failed");
+  }
+}
+
+// the slot for a new history entry: a free one, else the oldest
+static int take_slot(thcsox_diis_s* d) {
   int slot;
   if ((int)d->order.size() < d->depth) {
     slot = (int)d->order.size();
@@ -232,10 +238,56 @@ static int thcsox_diis_step_impl(thcsox_diis_t d, const double* sigma_in, const 
     slot = d->order.front();
     d->order.erase(d->order.begin());
   }
+  return slot;
+}
+
+static int diis_extrapolate(thcsox_diis_s* d, int slot, double* sigma_next, int* n_used_out);
+
+static int thcsox_diis_step_impl(thcsox_diis_t d, const double* sigma_in, const double* sigma_out,
+                     double* sigma_next, int* n_used_out) {
+  clear_error();
+  if (d == nullptr || sigma_in == nullptr || sigma_out == nullptr || sigma_next == nullptr)
+    return lfail(THCSOX_EINVAL, "NULL argument");
+  if (d->explicit_residual)
+    return lfail(THCSOX_EINVAL, "this history takes explicit residuals (thcsox_diis_step_res)");
+  if (sigma_next == sigma_out) return lfail(THCSOX_EINVAL, "sigma_next may not alias sigma_out");
+  if (!is_device(sigma_in) || !is_device(sigma_out) || !is_device(sigma_next))
+    return lfail(THCSOX_ENOTDEV, "arrays must be device memory");
+  const hipStream_t s = d->stream;
+  const unsigned gb = grid_for(d->len);
+  const int slot = take_slot(d);
   LTRY(hipMemcpyAsync(d->in[slot], sigma_in, sizeof(double) * d->len, hipMemcpyDeviceToDevice, s));
   sub_kernel<<<gb, NT, 0, s>>>(d->len, sigma_out, sigma_in, d->res[slot]);
   LTRY(hipGetLastError());
   d->order.push_back(slot);
+  return diis_extrapolate(d, slot, sigma_next, n_used_out);
+}
+
+static int thcsox_diis_step_res_impl(thcsox_diis_t d, const double* residual,
+                                     const double* sigma_out, double* sigma_next,
+                                     int* n_used_out) {
+  clear_error();
+  if (d == nullptr || residual == nullptr || sigma_out == nullptr || sigma_next == nullptr)
+    return lfail(THCSOX_EINVAL, "NULL argument");
+  if (!d->explicit_residual)
+    return lfail(THCSOX_EINVAL, "this history forms its own residuals (thcsox_diis_step)");
+  if (!is_device(residual) || !is_device(sigma_out) || !is_device(sigma_next))
+    return lfail(THCSOX_ENOTDEV, "arrays must be device memory");
+  const hipStream_t s = d->stream;
+  const int slot = take_slot(d);
+  // the history keeps Sigma_out itself (the ring named `in`) and the residual
+  LTRY(hipMemcpyAsync(d->in[slot], sigma_out, sizeof(double) * d->len, hipMemcpyDeviceToDevice, s));
+  LTRY(hipMemcpyAsync(d->res[slot], residual, sizeof(double) * d->len_e, hipMemcpyDeviceToDevice, s));
+  d->order.push_back(slot);
+  return diis_extrapolate(d, slot, sigma_next, n_used_out);
+}
+
+// New row of residual dot products for `slot`, coefficients over the newest
+// entries (the oldest dropped while the bordered system is singular), and
+// sigma_next = sum_i c_i Sigma_out_i.  Synchronises the stream.
+static int diis_extrapolate(thcsox_diis_s* d, int slot, double* sigma_next, int* n_used_out) {
+  const hipStream_t s = d->stream;
+  const unsigned gb = grid_for(d->len);
   // new row of residual dot products
   for (int o : d->order) {
     double v;
@@ -257,16 +309,19 @@ static int thcsox_diis_step_impl(thcsox_diis_t d, const double* sigma_in, const 
     if (solve_bordered(B, k, c)) break;
   }
   if (first == total) return lfail(THCSOX_ENONFINITE, "DIIS system is singular");
-  // sigma_next = sum_i c_i (in_i + res_i); sigma_next may alias sigma_in, whose
-  // copy is already in the history
+  // sigma_next = sum_i c_i Sigma_out_i: (in_i + res_i) for the Pulay residual,
+  // the stored Sigma_out_i for explicit residuals; sigma_next may alias the
+  // caller's inputs, whose copies are already in the history
   const int k = total - first;
   for (int i = 0; i < k; ++i) {
     const int o = d->order[first + i];
     if (i == 0) scale_kernel<<<gb, NT, 0, s>>>(d->len, c[i], d->in[o], sigma_next);
     else axpby_kernel<<<gb, NT, 0, s>>>(d->len, c[i], d->in[o], 1.0, sigma_next);
     LTRY(hipGetLastError());
-    axpby_kernel<<<gb, NT, 0, s>>>(d->len, c[i], d->res[o], 1.0, sigma_next);
-    LTRY(hipGetLastError());
+    if (!d->explicit_residual) {
+      axpby_kernel<<<gb, NT, 0, s>>>(d->len, c[i], d->res[o], 1.0, sigma_next);
+      LTRY(hipGetLastError());
+    }
   }
   LTRY(hipStreamSynchronize(s));
   if (n_used_out) *n_used_out = k;
@@ -277,6 +332,15 @@ int thcsox_diis_step(thcsox_diis_t d, const double* sigma_in, const double* sigm
                      double* sigma_next, int* n_used_out) {
   try {   // host containers: no exception may cross the C interface
     return thcsox_diis_step_impl(d, sigma_in, sigma_out, sigma_next, n_used_out);
+  } catch (const std::bad_alloc&) {
+    return lfail(THCSOX_ENOMEM, "host allocation failed");
+  }
+}
+
+int thcsox_diis_step_res(thcsox_diis_t d, const double* residual, const double* sigma_out,
+                         double* sigma_next, int* n_used_out) {
+  try {
+    return thcsox_diis_step_res_impl(d, residual, sigma_out, sigma_next, n_used_out);
   } catch (const std::bad_alloc&) {
     return lfail(THCSOX_ENOMEM, "host allocation failed");
   }

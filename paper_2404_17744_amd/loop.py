@@ -6,12 +6,15 @@
 
 Every step runs in libthcsox (SOX evaluation, energy, tau -> i omega transform,
 batched Dyson inversion, chemical-potential search, least-squares fit back to
-tau, one-body energy, damping, DIIS); torch only provides device buffers.
+tau, one-body energy, damping, DIIS and its commutator residual); torch only
+provides device buffers.
 Prints one JSON line per iteration and a summary line, e.g. for the paper-scale
 one-GPU share:
 
     python -m paper_2404_17744_amd.loop --workload sox_n1100_naux5500_ntau100 --iters 10
     python -m paper_2404_17744_amd.loop --workload sox_n300_naux1800_ntau100 --diis 6 --mu-search
+    python -m paper_2404_17744_amd.loop --workload sox_n300_naux1800_ntau100 --diis 6 \
+        --diis-kind commutator
 
 With --grid ir the loop runs on the IR sparse-sampling grids (tau points and
 Matsubara frequencies of the basis at --beta and Lambda = beta --wmax), with
@@ -41,7 +44,10 @@ def main() -> None:
                     help="self-energy: the SOX term, or full second order (direct + SOX)")
     ap.add_argument("--damping", type=float, default=0.0,
                     help="Sigma_in <- d Sigma_in + (1 - d) Sigma_out (0: none)")
-    ap.add_argument("--diis", type=int, default=0, help="Pulay DIIS depth on Sigma (0: none)")
+    ap.add_argument("--diis", type=int, default=0, help="DIIS depth on Sigma (0: none)")
+    ap.add_argument("--diis-kind", default="pulay", choices=["pulay", "commutator"],
+                    help="residual: Sigma_out - Sigma_in, or the frequency-dependent "
+                         "commutator [G(i w), F + Sigma_out(i w)]")
     ap.add_argument("--mu-search", action="store_true",
                     help="chemical potential that keeps n_occ electrons at every Dyson step")
     # above the transforms' accuracy in N (~1e-7 at 64 Chebyshev points, beta = 100):
@@ -78,7 +84,13 @@ def main() -> None:
     S_out = torch.zeros_like(G)    # Sigma^SOX of the current G
     S_in = torch.zeros_like(G)     # the Sigma fed to the Dyson step
     S_next = torch.empty_like(G)
-    diis = thcsox.Diis(S_out, depth=a.diis) if a.diis > 0 else None
+    diis, e_buf = None, None
+    if a.diis > 0 and a.diis_kind == "commutator":
+        nf = dyson.nfreq
+        e_buf = torch.empty((2, nf, s.n, s.n), dtype=torch.float64, device=dev)
+        diis = thcsox.Diis(S_out, depth=a.diis, residual_like=e_buf)
+    elif a.diis > 0:
+        diis = thcsox.Diis(S_out, depth=a.diis)
     mu = s.mu
     # the start: G0 and its density matrix from a Dyson step with Sigma = 0, so
     # that every energy pairs E_1 = Tr[F gamma] and E_2 of the same G
@@ -95,7 +107,12 @@ def main() -> None:
         nelec = float(np.trace(gamma.cpu().numpy()))   # host diagnostic
         t2 = time.time()
         used = 1
-        if it == 0 or (diis is None and a.damping == 0.0):
+        if e_buf is not None:
+            # the commutator of the G that S_out came from (the last Dyson step's)
+            dyson.commutator(S_in, S_out, out=e_buf)
+            used = diis.step_res(e_buf, S_out, S_next)
+            S_in, S_next = S_next, S_in
+        elif it == 0 or (diis is None and a.damping == 0.0):
             S_in.copy_(S_out)
         elif diis is not None:
             used = diis.step(S_in, S_out, S_next)
@@ -130,7 +147,7 @@ def main() -> None:
                       "grid": a.grid, "beta": beta,
                       "nfreq": len(grid["freq_n"]) if grid else a.matsubara,
                       "damping": a.damping,
-                      "diis": a.diis, "mu_search": a.mu_search, "iterations": len(iters),
+                      "diis": a.diis, "diis_kind": a.diis_kind, "mu_search": a.mu_search, "iterations": len(iters),
                       "converged": len(iters) > 1 and abs(iters[-1]["dE"]) < a.tol,
                       "E_total": iters[-1]["E_total"],
                       "generate_s": t_gen, "plan_s": t_plan,

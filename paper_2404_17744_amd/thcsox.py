@@ -33,7 +33,8 @@ EXPORTS = ("thcsox_plan", "thcsox_sigma_sox", "thcsox_energy", "thcsox_destroy",
            "thcsox_diis_create", "thcsox_diis_step", "thcsox_diis_destroy",
            "thcsox_sigma_direct", "thcsox_energy_basis", "thcsox_dyson_plan_sampled",
            "thcsox_ir_create", "thcsox_ir_sizes", "thcsox_ir_get", "thcsox_ir_destroy",
-           "thcsox_energy_noalloc", "thcsox_static_screening", "thcsox_sigma_screened")
+           "thcsox_energy_noalloc", "thcsox_static_screening", "thcsox_sigma_screened",
+           "thcsox_dyson_commutator", "thcsox_diis_create_res", "thcsox_diis_step_res")
 SYMMETRY = {"auto": 0, "off": 1}
 STAGES = ("project", "a_stage", "fused", "back")
 
@@ -128,6 +129,13 @@ def lib() -> ctypes.CDLL:
         L.thcsox_diis_step.restype = i
         L.thcsox_diis_destroy.argtypes = [vp]
         L.thcsox_diis_destroy.restype = i
+        L.thcsox_diis_create_res.argtypes = [ctypes.POINTER(vp), ctypes.c_int64, ctypes.c_int64,
+                                             i, vp]
+        L.thcsox_diis_create_res.restype = i
+        L.thcsox_diis_step_res.argtypes = [vp, vp, vp, vp, ctypes.POINTER(i)]
+        L.thcsox_diis_step_res.restype = i
+        L.thcsox_dyson_commutator.argtypes = [vp, vp, vp, vp]
+        L.thcsox_dyson_commutator.restype = i
         fp = ctypes.c_float
         L.thcsox_mlp_create.argtypes = [ctypes.POINTER(vp), i, i, i, vp, vp]
         L.thcsox_mlp_create.restype = i
@@ -336,6 +344,22 @@ def thcsox_diis_destroy(h) -> None:
     _check(lib().thcsox_diis_destroy(h))
 
 
+def thcsox_diis_create_res(length: int, length_res: int, depth: int, stream: int):
+    h = ctypes.c_void_p()
+    _check(lib().thcsox_diis_create_res(ctypes.byref(h), length, length_res, depth, stream))
+    return h
+
+
+def thcsox_diis_step_res(h, residual: int, sigma_out: int, sigma_next: int) -> int:
+    used = ctypes.c_int(0)
+    _check(lib().thcsox_diis_step_res(h, residual, sigma_out, sigma_next, ctypes.byref(used)))
+    return used.value
+
+
+def thcsox_dyson_commutator(d, Sigma_in_dev: int, Sigma_out_dev: int, e_dev: int) -> None:
+    _check(lib().thcsox_dyson_commutator(d, Sigma_in_dev, Sigma_out_dev, e_dev))
+
+
 class Dyson:
     """Owns one Dyson/transform plan; tensors are torch float64 device tensors."""
 
@@ -349,6 +373,7 @@ class Dyson:
         self.device = F.device
         self.stream = stream if stream is not None else torch.cuda.current_stream(F.device)
         Fc = F.contiguous().to(torch.float64)
+        self.nfreq = n_matsubara if grid is None else len(grid["freq_n"])
         if grid is None:
             self.handle = _ordered(self.stream, thcsox_dyson_plan, self.n, self.ntau, n_matsubara,
                                    float(beta), float(mu), np.asarray(tau), Fc.data_ptr(),
@@ -372,6 +397,20 @@ class Dyson:
         _ordered(self.stream, thcsox_dyson_step, self.handle, Sigma.data_ptr(), G_out.data_ptr(),
                  gamma_out.data_ptr())
         return G_out, gamma_out
+
+    def commutator(self, Sigma_in, Sigma_out, out=None):
+        """[G(i w), Sigma_out(i w) - Sigma_in(i w)] on the plan's frequencies for the
+        G of the last step (taken with Sigma_in): [2, nfreq, n, n] (Re, Im)."""
+        import torch
+        _dev64(Sigma_in, "Sigma_in", (self.n, self.n), self.ntau, exact=True)
+        _dev64(Sigma_out, "Sigma_out", (self.n, self.n), self.ntau, exact=True)
+        if out is None:
+            out = torch.empty((2, self.nfreq, self.n, self.n), dtype=torch.float64,
+                              device=self.device)
+        _dev64(out, "out", (self.nfreq, self.n, self.n), 2, exact=True)
+        _ordered(self.stream, thcsox_dyson_commutator, self.handle, Sigma_in.data_ptr(),
+                 Sigma_out.data_ptr(), out.data_ptr())
+        return out
 
     def step_mu(self, Sigma, nelec: float, mu: float, tol: float = 1e-8, G_out=None,
                 gamma_out=None):
@@ -665,13 +704,29 @@ def mix(alpha: float, sigma_out, sigma_io, stream=None) -> None:
 
 
 class Diis:
-    """Pulay DIIS over (Sigma_in, Sigma_out) pairs held on the device."""
+    """DIIS over a history held on the device: Pulay's (residual Sigma_out -
+    Sigma_in, `step`) or with caller-given residuals such as the commutator of
+    Dyson.commutator (`residual_like` given, `step_res`)."""
 
-    def __init__(self, like, depth: int = 6, stream=None):
+    def __init__(self, like, depth: int = 6, stream=None, residual_like=None):
         import torch
         self.stream = stream if stream is not None else torch.cuda.current_stream(like.device)
         self.shape = tuple(like.shape)
-        self.handle = thcsox_diis_create(like.numel(), depth, self.stream.cuda_stream)
+        if residual_like is None:
+            self.res_shape = None
+            self.handle = thcsox_diis_create(like.numel(), depth, self.stream.cuda_stream)
+        else:
+            self.res_shape = tuple(residual_like.shape)
+            self.handle = thcsox_diis_create_res(like.numel(), residual_like.numel(), depth,
+                                                 self.stream.cuda_stream)
+
+    def step_res(self, residual, sigma_out, sigma_next) -> int:
+        """Adds (residual, sigma_out); writes sum_i c_i Sigma_out_i into sigma_next."""
+        _dev64(residual, "residual", self.res_shape[1:], self.res_shape[0], exact=True)
+        for name, t in (("sigma_out", sigma_out), ("sigma_next", sigma_next)):
+            _dev64(t, name, self.shape[1:], self.shape[0], exact=True)
+        return _ordered(self.stream, thcsox_diis_step_res, self.handle, residual.data_ptr(),
+                        sigma_out.data_ptr(), sigma_next.data_ptr())
 
     def step(self, sigma_in, sigma_out, sigma_next) -> int:
         """Writes the extrapolated input into sigma_next; returns the entries used."""

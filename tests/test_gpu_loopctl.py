@@ -117,3 +117,123 @@ def test_diis_exact_on_linear_map_and_errors(dev):
     with pytest.raises(thcsox.ThcsoxError):
         dd.step_mu(torch.zeros((8, 6, 6), dtype=torch.float64, device=dev), 7.0, s.mu)
     dd.close()
+
+
+# Commutator DIIS: the residual e(i w) = [G(i w), Sigma_out(i w) - Sigma_in(i w)]
+# for the G of the last Dyson step, and the extrapolation over caller-given
+# residuals, against oracle/loopctl.py.
+def _sym_profiles(m, n, seed, scale):
+    rng = np.random.default_rng(seed)
+    S = scale * rng.standard_normal((m, n, n))
+    return S + S.transpose(0, 2, 1)
+
+
+@pytest.mark.parametrize("n,m,nw", [(12, 32, 128), (37, 24, 100)])
+def test_commutator_matches_oracle(dev, n, m, nw):
+    print(f"case commutator residual n{n} m{m} nw{nw}", flush=True)
+    s = synth.make_system(n, 3 * n, seed=3)
+    tau, _ = synth.cheb_tau_grid(m, BETA)
+    Tm = otr.cheb_to_matsubara(m, nw, BETA)
+    S_in = _sym_profiles(m, n, 1, 0.02)
+    S_out = _sym_profiles(m, n, 2, 0.02)
+    G_iw = otr.dyson(s.F, s.mu, otr.tau_to_matsubara(S_in, Tm), BETA)
+    ref = olc.commutator_residual(G_iw, otr.tau_to_matsubara(S_out - S_in, Tm))
+    d = thcsox.Dyson(torch.from_numpy(s.F).to(dev), s.mu, tau, BETA, nw)
+    Si, So = torch.from_numpy(S_in).to(dev), torch.from_numpy(S_out).to(dev)
+    with pytest.raises(thcsox.ThcsoxError):
+        d.commutator(Si, So)              # no G(i w) before the first step
+    d.step(Si)
+    e = d.commutator(Si, So).cpu().numpy()
+    d.close()
+    got = e[0] + 1j * e[1]
+    err = float(np.abs(got - ref).max() / np.abs(ref).max())
+    print(f"  rel err {err:.2e}")
+    assert err <= 1e-10
+
+
+def test_commutator_diis_matches_oracle(dev):
+    """Six steps over complex residuals, depth 3 (the history wraps): the
+    coefficients from B_ij = Re sum e_i^* e_j on the stacked (Re, Im) layout."""
+    rng = np.random.default_rng(11)
+    m, nw, n = 8, 20, 9
+    shape, rshape = (m, n, n), (2, nw, n, n)
+    like = torch.zeros(shape, dtype=torch.float64, device=dev)
+    diis = thcsox.Diis(like, depth=3, residual_like=torch.zeros(rshape, dtype=torch.float64,
+                                                                 device=dev))
+    nxt = torch.empty_like(like)
+    hist_e, hist_o = [], []
+    for it in range(6):
+        e = rng.standard_normal(rshape) * 0.5 ** it
+        o = rng.standard_normal(shape)
+        hist_e.append(e[0] + 1j * e[1])
+        hist_o.append(o)
+        used = diis.step_res(torch.from_numpy(e).to(dev), torch.from_numpy(o).to(dev), nxt)
+        ref = olc.cdiis_next(hist_e[-3:], hist_o[-3:])
+        assert used == min(it + 1, 3)
+        assert _rel(nxt.cpu().numpy(), ref) <= 1e-11, (it, _rel(nxt.cpu().numpy(), ref))
+    with pytest.raises(ValueError):
+        diis.step_res(like, like, nxt)    # residual of the wrong shape
+    diis.close()
+
+
+def _gpu_loop(dev, s, tau, w, nw, diis_kind):
+    """SOX loop at fixed mu from the Sigma = 0 start; returns (iterations, E)."""
+    m = len(tau)
+    plan = thcsox.Plan(torch.from_numpy(s.X).to(dev), torch.from_numpy(s.V).to(dev), tau, w,
+                       BETA, precision="fp64")
+    d = thcsox.Dyson(torch.from_numpy(s.F).to(dev), s.mu, tau, BETA, nw)
+    S_in = torch.zeros((m, s.n, s.n), dtype=torch.float64, device=dev)
+    S_out, S_next = torch.empty_like(S_in), torch.empty_like(S_in)
+    e = torch.empty((2, nw, s.n, s.n), dtype=torch.float64, device=dev)
+    diis = thcsox.Diis(S_in, depth=4, residual_like=e) if diis_kind else None
+    G, gam = d.step(S_in)
+    E_prev = None
+    try:
+        for it in range(60):
+            plan.sigma(G, out=S_out)
+            E = d.onebody(gam) + plan.energy(G, S_out)
+            if E_prev is not None and abs(E - E_prev) < 1e-9:
+                return it + 1, E
+            E_prev = E
+            if diis is not None:
+                d.commutator(S_in, S_out, out=e)
+                diis.step_res(e, S_out, S_next)
+                S_in, S_next = S_next, S_in
+            else:
+                S_in.copy_(S_out)
+            G, gam = d.step(S_in)
+    finally:
+        if diis is not None:
+            diis.close()
+        plan.close()
+        d.close()
+    raise AssertionError("no convergence in 60 iterations")
+
+
+def test_commutator_diis_loop(dev):
+    """The loop of the oracle's commutator-DIIS pin on the GPU (SOX at lambda =
+    0.3, n = 12, naux = 36, 32 tau points, 128 frequencies, fixed mu): plain
+    iteration and commutator DIIS(4) reach the oracle's fixed-point energy, the
+    DIIS run in fewer iterations."""
+    from oracle import energy as oen
+    print("case commutator DIIS loop n12 naux36 lam0.3", flush=True)
+    s = synth.make_system(12, 36, seed=5, lam=0.3)
+    m, nw = 32, 128
+    tau, w = synth.cheb_tau_grid(m, BETA)
+    Tm = otr.cheb_to_matsubara(m, nw, BETA)
+    U = osox.precontract_u(s.X, s.V)
+    S = np.zeros((m, 12, 12))
+    E_prev = None
+    for _ in range(60):                      # the oracle's plain iteration
+        G, gam, _ = otr.loop_step(s.F, s.mu, BETA, S, Tm)
+        S = np.stack([osox.sigma_thc_paper(s.X, s.V, G[k], G[m - 1 - k], U=U) for k in range(m)])
+        E_ref = float(np.sum(s.F * gam.T)) + oen.energy_tau(G, S, w)
+        if E_prev is not None and abs(E_ref - E_prev) < 1e-11:
+            break
+        E_prev = E_ref
+    it_plain, E_plain = _gpu_loop(dev, s, tau, w, nw, False)
+    it_cd, E_cd = _gpu_loop(dev, s, tau, w, nw, True)
+    print(f"  plain {it_plain} iterations E {E_plain:.12f}; commutator DIIS {it_cd} "
+          f"E {E_cd:.12f}; oracle fixed point {E_ref:.12f}")
+    assert abs(E_plain - E_ref) <= 1e-8 and abs(E_cd - E_ref) <= 1e-8
+    assert it_cd < it_plain
