@@ -2,22 +2,29 @@
 //
 //   A_Pqv = sum_s U_Pqs G_sv(beta - tau)
 //
-// as C(i, j) = alpha * sum_k Aop[i][k] Bop[j][k] with Aop the rows (P, q) of U
-// and Bop the rows v of G(beta - tau)^T, both K-major fp16 planes (x = x0 + x1,
-// products x1 y0 + x0 y1 + x0 y0 on the f16 matrix cores, FP32 accumulation).
-// The result is written in FP32, and max |C| is max-reduced for the scaling
-// that the fused stage applies when it splits A.
+// for one or more tau points ("sets") per launch, as C(i, j) = sum_k Uop[i][k]
+// Gop[j][k] with Uop the rows (P, q) of U and Gop the rows v of G(beta - tau)^T,
+// both K-major fp16 planes (x = x0 + x1, products x1 y0 + x0 y1 + x0 y0 on the
+// f16 matrix cores, FP32 accumulation).  The result is written in FP32 and max
+// |A| is max-reduced per set for the scaling that the fused stage applies when
+// it splits A.
 //
-// A workgroup of eight waves (two per SIMD) works on 128 rows of U at a time and
-// TN = 64 WBN columns (v), WBN <= 5; wave (wm, wn) holds 64 x 16 WBN of it.  The
-// grid is persistent (about one workgroup per compute unit): a workgroup walks
-// its row tiles with one continuous stream of stages, so the loads of the next
-// tile overlap the last stages and the stores of the current one.  Each 32-wide
-// k stage of both operands (U: 16 KiB, G: TN x 128 B) is loaded from memory
-// straight into one of two LDS buffers, one stage ahead of the matrix cores;
-// the fragments of the next stage are read while the second half of the
-// current stage's MFMAs run.  The MFMA takes the G fragment as its row operand, so a lane's output
-// elements run along i = (P, q): stores of 16 lanes cover 64 contiguous bytes.
+// Rows are walked in the padded row space of A, i = P ldk + q: a 128-row tile is
+// 512 contiguous bytes of one v panel, so every 128-byte line of A is written
+// whole by one workgroup (rows n <= q < ldk read U as zero and write zeros).
+// A workgroup of eight waves (two per SIMD) works on 128 rows at a time and TN =
+// 64 WBN columns (v), WBN <= 5; wave (wm, wn) holds 64 x 16 WBN of it.  The grid
+// is persistent (about one workgroup per compute unit): a workgroup walks its
+// row tiles with one continuous stream of stages, so the loads of the next tile
+// overlap the last stages and the stores of the current one.  The workgroups
+// that walk the same row tiles for different sets (or column blocks) are placed
+// on one XCD, so U is fetched from HBM about once per launch and served from
+// that XCD's L2 to the others.  Each 32-wide k stage of both operands (U: 16 KiB,
+// G: TN x 128 B) is loaded from memory straight into one of two LDS buffers, one
+// stage ahead of the matrix cores; the fragments of the next stage are read while
+// the second half of the current stage's MFMAs run.  The MFMA takes the G
+// fragment as its row operand, so a lane's output elements run along i: stores
+// of 16 lanes cover 64 contiguous bytes.
 #include <algorithm>
 
 #include "kernels.hpp"
@@ -47,49 +54,72 @@ __device__ __forceinline__ void a_vm_lds_barrier() {
 }
 
 template <int WBN>
-__device__ __forceinline__ void astage_body(const GemmKArgs& g, ABuf& b0, ABuf& b1) {
+__device__ __forceinline__ void astage_body(const AStageArgs& g, ABuf& b0, ABuf& b1) {
   constexpr int TN = 64 * WBN;
   static_assert(TN <= AMAXN, "at most 320 columns per workgroup");
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform in the wave
   const int wm = wave >> 2, wn = wave & 3;
-  // persistent: this workgroup owns column block jb_ and the row tiles
-  // tile0, tile0 + gridDim.y... (grid.x = column blocks, grid.y = row workers)
-  const int nib = (g.M + AM - 1) / AM;
-  const int j0 = blockIdx.x * TN;
-  const int first = blockIdx.y, stride = gridDim.y;
-  const int ntile = first < nib ? (nib - 1 - first) / stride + 1 : 0;
+  const int M = g.naux * g.ldk;                 // padded rows (checked < 2^31 on the host)
+  const int nib = (M + AM - 1) / AM;
+  // block -> (part x, row worker y), parts = (set, column block): the X parts of
+  // worker y are the blocks 8 (X (y / 8) + x) + y % 8, which share an XCD (blocks
+  // are dealt to the eight XCDs round-robin)
+  // (the integer divisions run on the vector unit: readfirstlane tells the
+  // compiler that the results are uniform, so the buffer resources stay scalar)
+  const int ncol = (g.n + TN - 1) / TN, X = g.nsets * ncol;
+  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+  const int x = __builtin_amdgcn_readfirstlane(slot % X);
+  const int first = __builtin_amdgcn_readfirstlane((slot / X) * 8 + xcd);
+  const int stride = __builtin_amdgcn_readfirstlane(gridDim.x / X);
+  const int set = __builtin_amdgcn_readfirstlane(x / ncol);
+  const int j0 = __builtin_amdgcn_readfirstlane((x % ncol) * TN);
+  const int ntile = __builtin_amdgcn_readfirstlane(first < nib ? (nib - 1 - first) / stride + 1 : 0);
   if (ntile == 0) return;
-  const int rows_j = min(TN, g.N - j0);
-  const int kst = g.kpad / AKC;
+  const int rows_j = min(TN, g.n - j0);
+  const int kst = g.ldk / AKC;
+  const int64_t ldk = g.ldk;
 
-  const _Float16* B = static_cast<const _Float16*>(g.B) + (int64_t)j0 * g.ldb;
+  const _Float16* B = static_cast<const _Float16*>(g.Gb) + set * g.gb_set + j0 * ldk;
   __amdgpu_buffer_rsrc_t rB[2];
 #pragma unroll
-  for (int p = 0; p < 2; ++p) rB[p] = make_rsrc(B + p * g.b_plane, (int64_t)TN * g.ldb * 2);
+  for (int p = 0; p < 2; ++p) rB[p] = make_rsrc(B + p * g.gb_plane, TN * ldk * 2);
   // memory-to-LDS slabs of 16 rows: U has 8 per plane (wave w moves slab w of
   // both planes), G has TN / 16 per plane, 8 WBN in all (wave w moves the
   // slabs w + 8 j, j < WBN, counted across the two planes)
   constexpr int GSP = TN / 16;               // G slabs per plane
   const int urow = wave * 16 + (lane >> 2);
-  const uint32_t du_in = (uint32_t)((urow * g.lda + 8 * lds_chunk(urow, lane & 3)) * 2);
   uint32_t dg[WBN];
 #pragma unroll
   for (int j = 0; j < WBN; ++j) {
     const int slab = (wave + ANW * j) % GSP;
     const int row = slab * 16 + (lane >> 2);
     const int c = lds_chunk(row, lane & 3);
-    dg[j] = row < rows_j ? (uint32_t)((row * g.ldb + 8 * c) * 2) : OOB;
+    dg[j] = row < rows_j ? (uint32_t)((row * ldk + 8 * c) * 2) : OOB;
   }
-  // stage (tile t of this workgroup, k chunk k) -> LDS buffer
-  auto dma = [&](ABuf& bf, int t, int k) {
+  // the U rows of the tile being fetched: this lane's row i = i0 + urow is U row
+  // P n + q (none for q >= n), addressed from the tile's first P
+  const _Float16* Ub = static_cast<const _Float16*>(g.U);
+  const int64_t urows = (int64_t)g.naux * g.n;
+  __amdgpu_buffer_rsrc_t rU[2];
+  uint32_t du = OOB;
+  auto set_tile = [&](int t) {
     const int i0 = (first + t * stride) * AM;
-    const _Float16* A = static_cast<const _Float16*>(g.A) + (int64_t)i0 * g.lda;
-    const uint32_t du = urow < g.M - i0 ? du_in : OOB;
+    const int P0 = __builtin_amdgcn_readfirstlane(i0 / g.ldk);
+    const int i = i0 + urow, P = i / g.ldk, q = i - P * g.ldk;
+    du = (P < g.naux && q < g.n)
+             ? (uint32_t)((((P - P0) * g.n + q) * ldk + 8 * lds_chunk(urow, lane & 3)) * 2)
+             : OOB;
+    const int64_t r0 = (int64_t)P0 * g.n;
+#pragma unroll
+    for (int p = 0; p < 2; ++p) rU[p] = make_rsrc(Ub + p * g.u_plane + r0 * ldk, (urows - r0) * ldk * 2);
+  };
+  // stage k of the current fetch tile -> LDS buffer
+  auto dma = [&](ABuf& bf, int k) {
 #pragma unroll
     for (int p = 0; p < 2; ++p)
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(
-          make_rsrc(A + p * g.a_plane, (int64_t)AM * g.lda * 2), &bf.u[p][wave * 16 * AKC], 16, du,
-          k * AKC * 2, 0, 0);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rU[p], &bf.u[p][wave * 16 * AKC], 16, du,
+                                               k * AKC * 2, 0, 0);
 #pragma unroll
     for (int j = 0; j < WBN; ++j) {
       const int s = wave + ANW * j, p = s / GSP, slab = s % GSP;
@@ -137,8 +167,9 @@ __device__ __forceinline__ void astage_body(const GemmKArgs& g, ABuf& b0, ABuf& 
     }
   };
 
-  double lmax = 0.0;
-  float* C = static_cast<float*>(g.C);
+  float lmax = 0.f;
+  float* C = g.A + set * g.a_set;
+  const int64_t c_j = (int64_t)g.naux * ldk;
   const int jb = j0 + wn * 16 * WBN + 4 * (lane >> 4);
   // write the finished tile t and clear the accumulators
   auto store_tile = [&](int t) {
@@ -146,17 +177,16 @@ __device__ __forceinline__ void astage_body(const GemmKArgs& g, ABuf& b0, ABuf& 
 #pragma unroll
     for (int ti = 0; ti < 4; ++ti) {
       const int i = ib + 16 * ti;
-      const bool ok = i < g.M;
-      const int64_t ibase = ((int64_t)i / g.ci_in) * g.ci_out + ((int64_t)i % g.ci_in);
+      const bool ok = i < M;
 #pragma unroll
       for (int tj = 0; tj < WBN; ++tj)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int j = jb + 16 * tj + r;
-          if (ok && j < g.N) {
-            const float v = (float)(g.alpha * (double)acc[tj][ti][r]);
-            C[ibase + (int64_t)j * g.c_j] = v;
-            lmax = fmax(lmax, fabs((double)v));
+          if (ok && j < g.n) {
+            const float v = acc[tj][ti][r];
+            C[i + (int64_t)j * c_j] = v;
+            lmax = fmaxf(lmax, fabsf(v));
           }
           acc[tj][ti][r] = 0.f;
         }
@@ -168,12 +198,13 @@ __device__ __forceinline__ void astage_body(const GemmKArgs& g, ABuf& b0, ABuf& 
   // kst is even, so every tile starts on buffer 0.  Past the end the loads repeat
   // the last stage (never used).
   int ft = 0, fk = 0;
+  set_tile(0);
   auto fetch_next = [&](ABuf& bf) {
-    dma(bf, ft, fk);
+    dma(bf, fk);
     const bool last = (ft == ntile - 1) && (fk == kst - 1);
     const bool wrap = (fk == kst - 1);
+    if (wrap && !last) set_tile(++ft);
     fk = last ? fk : (wrap ? 0 : fk + 1);
-    ft = last ? ft : (wrap ? ft + 1 : ft);
   };
   fetch_next(b0);
   fetch_next(b1);
@@ -196,13 +227,13 @@ __device__ __forceinline__ void astage_body(const GemmKArgs& g, ABuf& b0, ABuf& 
   }
   // the last (repeated) memory-to-LDS loads land before the workgroup may end
   __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  if (g.amax != nullptr) block_atomic_max<ANW>(lmax, g.amax);
+  if (g.amax != nullptr) block_atomic_max<ANW>((double)lmax, g.amax + set);
 }
 
 // one kernel per column count (the body is a device template)
 #define THCSOX_ASTAGE_KERNEL(W)                                                         \
   __global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(2, 2)))          \
-  void astage_f16_kernel_##W(GemmKArgs g) {                                            \
+  void astage_f16_kernel_##W(AStageArgs g) {                                            \
     __shared__ __attribute__((aligned(16))) ABuf b0;                                    \
     __shared__ __attribute__((aligned(16))) ABuf b1;                                    \
     astage_body<W>(g, b0, b1);                                                          \
@@ -216,28 +247,33 @@ THCSOX_ASTAGE_KERNEL(5)
 inline unsigned a_cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
 template <int WBN>
-hipError_t a_launch(void (*kernel)(GemmKArgs), const GemmKArgs& g, hipStream_t s) {
-  // persistent row workers: one per compute unit (the LDS holds one workgroup)
+hipError_t a_launch(void (*kernel)(AStageArgs), const AStageArgs& g, hipStream_t s) {
+  // persistent row workers, a multiple of eight (one per XCD in each group of
+  // eight), with all parts of a worker on one XCD: about one workgroup per
+  // compute unit (the LDS holds one)
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess)
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  const unsigned ncol = a_cdiv(g.N, 64 * WBN), nib = a_cdiv(g.M, AM);
-  const unsigned workers = std::max(1u, std::min(nib, (unsigned)std::max(1, cus) / ncol));
-  kernel<<<dim3(ncol, workers), ANT, 0, s>>>(g);
+  const unsigned X = a_cdiv(g.n, 64 * WBN) * (unsigned)g.nsets;
+  const unsigned nib = a_cdiv((int64_t)g.naux * g.ldk, AM);
+  unsigned workers = std::min(nib, (unsigned)std::max(1, cus) / X);
+  workers = std::max(8u, workers / 8 * 8);
+  kernel<<<X * workers, ANT, 0, s>>>(g);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t astage_f16(const GemmKArgs& g, hipStream_t s) {
-  if (g.M <= 0 || g.N <= 0) return hipSuccess;
-  if (g.kpad % (2 * AKC) != 0) return hipErrorInvalidValue;
-  // 32-bit buffer offsets inside one workgroup's rows
-  if ((int64_t)AM * g.lda * 2 > 0x7fffffffLL || (int64_t)320 * g.ldb * 2 > 0x7fffffffLL)
+hipError_t astage_f16(const AStageArgs& g, hipStream_t s) {
+  if (g.naux <= 0 || g.n <= 0 || g.nsets <= 0) return hipSuccess;
+  if (g.ldk % (2 * AKC) != 0 || g.ldk < g.n) return hipErrorInvalidValue;
+  // 32-bit row indices and buffer offsets inside one tile
+  if ((int64_t)g.naux * g.ldk + AM > 0x7fffffffLL ||
+      (int64_t)(AM + 2 * g.n) * g.ldk * 2 > 0x7fffffffLL || (int64_t)320 * g.ldk * 2 > 0x7fffffffLL)
     return hipErrorInvalidValue;
-  if (g.N <= 128) return a_launch<2>(astage_f16_kernel_2, g, s);
-  if (g.N <= 192) return a_launch<3>(astage_f16_kernel_3, g, s);
-  if (g.N <= 256) return a_launch<4>(astage_f16_kernel_4, g, s);
+  if (g.n <= 128) return a_launch<2>(astage_f16_kernel_2, g, s);
+  if (g.n <= 192) return a_launch<3>(astage_f16_kernel_3, g, s);
+  if (g.n <= 256) return a_launch<4>(astage_f16_kernel_4, g, s);
   return a_launch<5>(astage_f16_kernel_5, g, s);   // 320 columns per workgroup, more beyond
 }
 

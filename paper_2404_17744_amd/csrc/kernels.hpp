@@ -35,9 +35,19 @@ struct GemmKArgs {
   unsigned long long* amax;
 };
 hipError_t gemm_kmajor(int mode, bool out_f64, const GemmKArgs& g, hipStream_t s);
-// The same product for fp16x2 planes with FP32 output (the A stage of that
-// mode); kpad must be a multiple of 64.
-hipError_t astage_f16(const GemmKArgs& g, hipStream_t s);
+// The A stage of the fp16x2 mode for nsets tau points at once:
+//   A[set][v][P][q] = sum_s U[P][q][s] Gb[set][v][s]   (q < n; rows n <= q < ldk get 0)
+// U: fp16 planes [naux][n][ldk]; Gb: fp16 planes [set][n][ldk] (G(beta - tau)^T);
+// A: FP32 [set][n][naux][ldk]; amax[set] (may be NULL): max |A| of each set,
+// max-reduced as the bits of a non-negative double.  ldk must be a multiple of 64.
+struct AStageArgs {
+  int naux, n, ldk, nsets;
+  const void* U; int64_t u_plane;
+  const void* Gb; int64_t gb_plane, gb_set;
+  float* A; int64_t a_set;
+  unsigned long long* amax;
+};
+hipError_t astage_f16(const AStageArgs& a, hipStream_t s);
 
 // The fused B/C/D stage for one tau point (v split over grid.z):
 //   Dpart[z][R][P] = sum_{v in split z} (sum_q Gt[R][q] A[v][P][q]) (sum_w U[R][v][w] GXt[P][w])

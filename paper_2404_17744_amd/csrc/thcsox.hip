@@ -138,7 +138,8 @@ struct thcsox_plan_s {
   int64_t u_plane = 0;
   void* A = nullptr;        // planes of [n][naux][ldk]
   int64_t a_plane = 0;
-  float* A32 = nullptr;     // [n][naux][ldk], split modes only
+  float* A32 = nullptr;     // [a_sets][n][naux][ldk], split modes only
+  int a_sets = 1;           // tau points per A-stage launch (fp16x2: 2 while A is small)
   int tb = 1;               // tau points per projection / back-projection batch
   void* Gt = nullptr;       // planes of [tb][naux][ldk]
   void* GX = nullptr;
@@ -358,22 +359,34 @@ int sigma_batch(thcsox_plan_s* p, const double* G, double* Sigma, double* Sthc_o
     const int k = k0 + b, kb = m - 1 - k;
     const int* sym = same_core && p->sym_mode == THCSOX_SYM_AUTO ? p->symflag + k : nullptr;
     // A[v][P][q] = sum_s U[P][q][s] G(beta - tau)[s][v]: rows (P,q) of U against rows v of Gb
-    HIP_TRY(p->mark(THCSOX_STAGE_A, true));
-    GemmKArgs ga{};
-    ga.M = naux * n; ga.N = n; ga.kpad = ldk; ga.alpha = 1.0;
-    ga.A = cores.UA; ga.lda = ldk; ga.a_plane = p->u_plane;
-    ga.B = static_cast<const char*>(p->Gb) + (size_t)b * n * ldk * es;
-    ga.ldb = ldk; ga.b_plane = p->gb_plane;
-    ga.ci_in = n; ga.ci_out = ldk; ga.c_j = (int64_t)naux * ldk;
-    if (mode == MODE_F64 || mode == MODE_F32) {
-      ga.C = p->A; ga.amax = nullptr;
-      HIP_TRY(gemm_kmajor(mode, mode == MODE_F64, ga, s));
-    } else {
-      // FP32 A; the fused kernel splits it into planes with the scale from max|A|
-      ga.C = p->A32; ga.amax = p->am_a() + k;
-      HIP_TRY(mode == MODE_F16X2 ? astage_f16(ga, s) : gemm_kmajor(mode, false, ga, s));
+    // (fp16x2: for up to a_sets tau points at once, into A32 set b % a_sets)
+    const int aset = mode == MODE_F16X2 ? b % p->a_sets : 0;
+    if (aset == 0) {
+      HIP_TRY(p->mark(THCSOX_STAGE_A, true));
+      if (mode == MODE_F16X2) {
+        AStageArgs ast{};
+        ast.naux = naux; ast.n = n; ast.ldk = ldk; ast.nsets = std::min(p->a_sets, nb - b);
+        ast.U = cores.UA; ast.u_plane = p->u_plane;
+        ast.Gb = static_cast<const char*>(p->Gb) + (size_t)b * n * ldk * es;
+        ast.gb_plane = p->gb_plane; ast.gb_set = (int64_t)n * ldk;
+        ast.A = p->A32; ast.a_set = p->a_plane;
+        ast.amax = p->am_a() + k;
+        HIP_TRY(astage_f16(ast, s));
+      } else {
+        GemmKArgs ga{};
+        ga.M = naux * n; ga.N = n; ga.kpad = ldk; ga.alpha = 1.0;
+        ga.A = cores.UA; ga.lda = ldk; ga.a_plane = p->u_plane;
+        ga.B = static_cast<const char*>(p->Gb) + (size_t)b * n * ldk * es;
+        ga.ldb = ldk; ga.b_plane = p->gb_plane;
+        ga.ci_in = n; ga.ci_out = ldk; ga.c_j = (int64_t)naux * ldk;
+        // FP32 A in the bf16x3 mode: the fused kernel splits it into planes with
+        // the scale from max|A|
+        ga.C = split_a ? static_cast<void*>(p->A32) : p->A;
+        ga.amax = split_a ? p->am_a() + k : nullptr;
+        HIP_TRY(gemm_kmajor(mode, mode == MODE_F64, ga, s));
+      }
+      HIP_TRY(p->mark(THCSOX_STAGE_A, false));
     }
-    HIP_TRY(p->mark(THCSOX_STAGE_A, false));
 
     FusedArgs f{};
     f.n = n; f.naux = naux; f.ldk = ldk; f.vsplit = p->vsplit; f.vchunk = p->vchunk;
@@ -381,7 +394,8 @@ int sigma_batch(thcsox_plan_s* p, const double* G, double* Sigma, double* Sthc_o
     f.GXt = static_cast<const char*>(p->GX) + (size_t)b * naux * ldk * es;
     f.g_plane = p->g_plane;
     f.U = cores.UC; f.u_plane = p->u_plane;
-    f.A = split_a ? static_cast<const void*>(p->A32) : p->A; f.a_plane = p->a_plane;
+    f.A = split_a ? static_cast<const void*>(p->A32 + aset * p->a_plane) : p->A;
+    f.a_plane = p->a_plane;
     f.a_f32 = split_a; f.amax_a = split_a ? p->am_a() + k : nullptr;
     f.Dpart = p->Dpart; f.dpart_f32 = p->dpart_f32;
     f.sym = sym;
@@ -614,6 +628,9 @@ int thcsox_plan(thcsox_plan_t* out, int n, int naux, int ntau, double beta,
   const size_t es = p->esize, np = p->np;
   p->u_plane = (int64_t)naux * n * ldk;
   p->a_plane = (int64_t)n * naux * ldk;
+  // the fp16x2 A stage forms two tau points per launch (U read once for both)
+  // while their FP32 A arrays take at most 2 GB together
+  if (precision == THCSOX_FP16X2 && ntau > 1 && 8.0 * p->a_plane <= 2.0e9) p->a_sets = 2;
   {
     // tau batch of the projections and back-projection: up to 16 points within ~2 GB
     const double per_tau = 8.0 * (2.0 * naux * n + (double)naux * naux + (double)n * naux) +
@@ -629,7 +646,7 @@ int thcsox_plan(thcsox_plan_t* out, int n, int naux, int ntau, double beta,
       // (X, V and the per-tau scalars in FP64, U, A, the partial tiles)
       const double fixed = 8.0 * ((double)n * naux + (double)naux * naux + 7.0 * ntau + 2.0) +
                            (double)p->np * p->esize * naux * n * ldk +
-                           (p->np > 1 ? 4.0 : (double)p->esize) * n * naux * ldk +
+                           (p->np > 1 ? 4.0 * p->a_sets : (double)p->esize) * n * naux * ldk +
                            (p->dpart_f32 ? 4.0 : 8.0) * p->vsplit * (double)naux * naux +
                            temps + (1 << 20);
       cap = std::min(cap, (double)workspace_limit - fixed);
@@ -648,7 +665,7 @@ int thcsox_plan(thcsox_plan_t* out, int n, int naux, int ntau, double beta,
   if ((rc = p->alloc(&tmp, np * es * (size_t)p->u_plane))) return bail(rc);
   p->U = tmp;
   if (precision == THCSOX_BF16X3 || precision == THCSOX_FP16X2) {
-    if ((rc = p->alloc(&p->A32, (size_t)p->a_plane))) return bail(rc);
+    if ((rc = p->alloc(&p->A32, (size_t)p->a_sets * p->a_plane))) return bail(rc);
   } else {
     if ((rc = p->alloc(&tmp, np * es * (size_t)p->a_plane))) return bail(rc);
     p->A = tmp;
@@ -684,7 +701,7 @@ int thcsox_plan(thcsox_plan_t* out, int n, int naux, int ntau, double beta,
     return hip_bail(e, "zero A");
   if ((e = hipMemsetAsync(p->symflag, 0, sizeof(int) * (size_t)ntau, s)))
     return hip_bail(e, "zero flags");
-  if (p->A32 && (e = hipMemsetAsync(p->A32, 0, sizeof(float) * (size_t)p->a_plane, s)))
+  if (p->A32 && (e = hipMemsetAsync(p->A32, 0, sizeof(float) * p->a_sets * (size_t)p->a_plane, s)))
     return hip_bail(e, "zero A32");
   if ((rc = p->alloc(&p->V, (size_t)naux * naux))) return bail(rc);
   if ((e = hipMemcpyAsync(p->V, V_dev, sizeof(double) * (size_t)naux * naux,
