@@ -49,16 +49,23 @@ def main() -> None:
                     help="residual: Sigma_out - Sigma_in, or the frequency-dependent "
                          "commutator [G(i w), F + Sigma_out(i w)]")
     ap.add_argument("--mu-search", action="store_true",
-                    help="chemical potential that keeps n_occ electrons at every Dyson step")
-    # above the transforms' accuracy in N (~1e-7 at 64 Chebyshev points, beta = 100):
-    # in a gap N(mu) is flat to that level, and a tighter target drives mu to a gap edge
-    ap.add_argument("--mu-tol", type=float, default=1e-5)
+                    help="chemical potential that keeps n_occ electrons at every Dyson step "
+                         "(meant for --terms gf2: with the exchange term alone N(mu) falls "
+                         "across the gap and has several roots, so the search hops between them)")
+    # The target has to sit above the grid's accuracy in N: with Sigma != 0 the
+    # density fitted on 64 Chebyshev points at beta = 100 is off by up to ~5e-4
+    # (128 points, or the IR grid, bring it below 1e-7); in a gap N(mu) is nearly
+    # flat, so a tighter target moves mu far across the gap to absorb that error
+    ap.add_argument("--mu-tol", type=float, default=None,
+                    help="electron-number tolerance (default 1e-3 on the Chebyshev grid, "
+                         "1e-5 on the IR grid)")
     ap.add_argument("--grid", default="cheb", choices=["cheb", "ir"],
                     help="Chebyshev roots (the workload's grid) or IR sparse sampling")
     ap.add_argument("--beta", type=float, default=1000.0, help="inverse temperature (--grid ir)")
     ap.add_argument("--wmax", type=float, default=100.0, help="frequency window (--grid ir)")
     ap.add_argument("--ir-eps", type=float, default=1e-10, help="basis cut s_l / s_0 (--grid ir)")
     a = ap.parse_args()
+    mu_tol = a.mu_tol if a.mu_tol is not None else (1e-3 if a.grid == "cheb" else 1e-5)
 
     import torch
     dev = torch.device("cuda:0")
@@ -121,7 +128,7 @@ def main() -> None:
             thcsox.mix(a.damping, S_out, S_in)
         solves = 1
         if a.mu_search:
-            G, gamma, mu, solves = dyson.step_mu(S_in, s.n_occ, mu, tol=a.mu_tol, G_out=G)
+            G, gamma, mu, solves = dyson.step_mu(S_in, s.n_occ, mu, tol=mu_tol, G_out=G)
         else:
             G, gamma = dyson.step(S_in, G_out=G)
         t3 = time.time()

@@ -217,3 +217,38 @@ def test_commutator_diis_loop_reaches_the_plain_fixed_point():
     it_cd, E_cd = run(True)
     assert abs(E_plain - E_cd) <= 1e-8
     assert it_cd < it_plain, (it_cd, it_plain)
+
+
+def test_electron_number_across_the_gap_sox_alone_and_full_second_order():
+    """Why the chemical-potential search suits the full second-order loop and not
+    the exchange term alone (n = 16, lambda = 0.5, 32 tau points, fixed mu): at
+    the converged Sigma, N(mu) with Sigma held fixed rises across the one-body gap
+    for Sigma^dir + Sigma^SOX, one root, but falls for Sigma^SOX alone, whose
+    spectral weight is not of one sign; N(mu) = N_el then has several roots and
+    the search hops between them from one iteration to the next."""
+    from oracle import direct as odir, sox as osox
+    n, m, nw = 16, 32, 256
+    s = synth.make_system(n, 3 * n, seed=0, lam=0.5)
+    Tm = tr.cheb_to_matsubara(m, nw, BETA)
+    U = osox.precontract_u(s.X, s.V)
+    ev = np.sort(s.eps)
+    mus = np.linspace(ev[s.n_occ - 1] + 0.02, ev[s.n_occ] - 0.02, 9)
+    slopes = {}
+    for terms in ("sox", "gf2"):
+        S = np.zeros((m, n, n))
+        for _ in range(40):
+            G, _, _ = tr.loop_step(s.F, s.mu, BETA, S, Tm)
+            S_new = np.stack([osox.sigma_thc_paper(s.X, s.V, G[k], G[m - 1 - k], U=U)
+                              for k in range(m)])
+            if terms == "gf2":
+                S_new += np.stack([odir.sigma_direct_thc(s.X, s.V, G[k], G[m - 1 - k])
+                                   for k in range(m)])
+            done = np.abs(S_new - S).max() < 1e-10
+            S = S_new
+            if done:
+                break
+        assert done
+        S_iw = tr.tau_to_matsubara(S, Tm)
+        slopes[terms] = np.diff([loopctl.electron_number(s.F, mu, BETA, S_iw, Tm) for mu in mus])
+    assert np.all(slopes["gf2"] > 0.0)
+    assert np.all(slopes["sox"][1:-1] < 0.0)
