@@ -421,6 +421,16 @@ int thcsox_mlp_create(thcsox_mlp_t* out, int m, int hidden, int max_batch,
                       const float* params_host, void* hip_stream);
 /* Inference for any batch size (processed max_batch rows at a time); asynchronous. */
 int thcsox_mlp_forward(thcsox_mlp_t q, const float* x_dev, float* y_dev, int batch);
+/* Inference with bf16 weights, for any batch size, asynchronous: the network's
+ * parameters rounded to bf16 (nearest, ties to even; re-rounded after training
+ * steps), each layer's input (x, h1, h2) rounded to bf16, bf16 matrix cores
+ * with FP32 accumulation, bias, silu and the residual add on the exact FP32 x
+ * in FP32.  One fused kernel per 64 rows keeps the hidden activations in LDS
+ * (no max_batch limit, no activation buffers).  Needs m in {32, 64} and H in
+ * {128, 256, 512} (THCSOX_EINVAL otherwise); batch 0 does nothing (x and y
+ * may then be NULL); the first call allocates the bf16 parameter copy.  y may
+ * not alias x. */
+int thcsox_mlp_forward_bf16(thcsox_mlp_t q, const float* x_dev, float* y_dev, int64_t batch);
 /* Loss and its gradient with respect to every parameter (packed like params);
  * batch <= max_batch.  grads_host may be NULL.  Synchronises. */
 int thcsox_mlp_gradients(thcsox_mlp_t q, const float* x_dev, const float* target_dev, int batch,

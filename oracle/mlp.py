@@ -45,6 +45,29 @@ def forward(p: dict, x: np.ndarray):
     return out, (x, z1, h1, z2, h2)
 
 
+def bf16_round(a) -> np.ndarray:
+    """Nearest bf16 value of each element (returned as float64): the value is
+    first taken to FP32 (nearest), then its 32-bit pattern is rounded to the
+    top 16 bits, to nearest with ties to the even pattern (the bf16 format is
+    FP32 with the low 16 significand bits dropped).  Finite inputs only."""
+    f = np.asarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    lsb = (u >> 16) & 1
+    r = ((u + 0x7FFF + lsb) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def forward_bf16(p: dict, x: np.ndarray) -> np.ndarray:
+    """The network with bf16 weights and bf16 layer inputs: every weight matrix
+    and each layer's input (x, h1, h2) rounded by bf16_round, products summed
+    exactly (FP64 here), biases, silu and the residual add on the unrounded x
+    as in forward."""
+    W1, W2, W3 = (bf16_round(p[k]) for k in ("W1", "W2", "W3"))
+    h1 = silu(bf16_round(x) @ W1.T + p["b1"])
+    h2 = silu(bf16_round(h1) @ W2.T + p["b2"])
+    return x + (bf16_round(h2) @ W3.T + p["b3"])
+
+
 def loss_and_grads(p: dict, x: np.ndarray, target: np.ndarray):
     """Mean-squared loss and its exact gradients by the chain rule."""
     out, (x, z1, h1, z2, h2) = forward(p, x)

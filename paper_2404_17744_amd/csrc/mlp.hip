@@ -212,6 +212,114 @@ unsigned blocks_for(int64_t n) {
   return (unsigned)(b > 4096 ? 4096 : (b < 1 ? 1 : b));
 }
 
+// ---------------------------------------------------------------------------
+// Inference with bf16 weights: one fused kernel per 64 rows on the bf16 matrix
+// cores (16x16x32, FP32 accumulation); the hidden activations never leave LDS.
+// Each layer's input (x, h1, h2) is rounded to bf16 (nearest, ties to even);
+// bias, silu and the residual add on the exact FP32 x stay in FP32.
+//
+// Eight waves: in layers 1 and 2 wave w owns the hidden units [16 HT w,
+// 16 HT (w + 1)) of all 64 rows, taking the weight rows as the MFMA's first
+// operand and the activation rows (from LDS) as its second, so a lane's four
+// results are four consecutive hidden units of one row: one 8-byte LDS write of
+// the next layer's bf16 input.  Layer 3's m x 64 output tiles are dealt to the
+// waves in turn; a lane's results are four consecutive outputs of one row, one
+// 16-byte store.
+constexpr int IRB = 64;               // rows per workgroup
+constexpr int INW = 8, INTH = 64 * INW;
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ bf16x4 to_bf16x4(float a, float b, float c, float d) {
+  return bf16x4{(__bf16)a, (__bf16)b, (__bf16)c, (__bf16)d};
+}
+
+template <int HT, int MT>   // hidden width H = 128 HT, m = 16 MT
+__global__ __launch_bounds__(INTH) void mlp_infer_bf16_kernel(
+    const float* __restrict__ x, float* __restrict__ y, int64_t batch,
+    const __bf16* __restrict__ W1, const float* __restrict__ b1,
+    const __bf16* __restrict__ W2, const float* __restrict__ b2,
+    const __bf16* __restrict__ W3, const float* __restrict__ b3) {
+  constexpr int H = 128 * HT, m = 16 * MT;
+  constexpr int XLD = m + 8, HLD = H + 8;   // padded rows (in bf16): 16-lane reads hit distinct banks
+  __shared__ __attribute__((aligned(16))) __bf16 xs[IRB * XLD];
+  __shared__ __attribute__((aligned(16))) __bf16 hs[IRB * HLD];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t r0 = (int64_t)blockIdx.x * IRB;
+  const int rows = (int)(batch - r0 < IRB ? batch - r0 : IRB);
+  for (int e = tid; e < IRB * m / 4; e += INTH) {
+    const int r = e / (m / 4), c = 4 * (e % (m / 4));
+    const f4 v = r < rows ? *reinterpret_cast<const f4*>(x + (r0 + r) * m + c) : f4{0.f, 0.f, 0.f, 0.f};
+    *reinterpret_cast<bf16x4*>(&xs[r * XLD + c]) = to_bf16x4(v[0], v[1], v[2], v[3]);
+  }
+  __syncthreads();
+  const int fr = lane & 15, fk = 8 * (lane >> 4);   // fragment row, k offset
+  const int hid0 = 16 * HT * wave;
+  f4 acc[HT][4];
+  // one hidden layer: acc = W rows [hid0, hid0 + 16 HT) . act^T over K, act in LDS
+  auto layer = [&](const __bf16* __restrict__ W, const __bf16* act, int ld, int K) {
+#pragma unroll
+    for (int t = 0; t < HT; ++t)
+#pragma unroll
+      for (int p = 0; p < 4; ++p) acc[t][p] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 32) {
+      bf16x8 a[HT], b[4];
+#pragma unroll
+      for (int t = 0; t < HT; ++t)
+        a[t] = *reinterpret_cast<const bf16x8*>(W + (int64_t)(hid0 + 16 * t + fr) * K + k0 + fk);
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+        b[p] = *reinterpret_cast<const bf16x8*>(&act[(16 * p + fr) * ld + k0 + fk]);
+#pragma unroll
+      for (int t = 0; t < HT; ++t)
+#pragma unroll
+        for (int p = 0; p < 4; ++p) acc[t][p] = mfma1(a[t], b[p], acc[t][p]);
+    }
+  };
+  // h = bf16(silu(acc + bias)) into hs[row][hid]
+  auto to_hidden = [&](const float* __restrict__ bias) {
+#pragma unroll
+    for (int t = 0; t < HT; ++t) {
+      const int h = hid0 + 16 * t + 4 * (lane >> 4);
+      const f4 bv = *reinterpret_cast<const f4*>(bias + h);
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+        *reinterpret_cast<bf16x4*>(&hs[(16 * p + fr) * HLD + h]) =
+            to_bf16x4(silu(acc[t][p][0] + bv[0]), silu(acc[t][p][1] + bv[1]),
+                      silu(acc[t][p][2] + bv[2]), silu(acc[t][p][3] + bv[3]));
+    }
+  };
+  layer(W1, xs, XLD, m);
+  to_hidden(b1);
+  __syncthreads();
+  layer(W2, hs, HLD, H);
+  __syncthreads();   // every wave has read all of h1
+  to_hidden(b2);
+  __syncthreads();
+  // layer 3: tile q = (o, p) of the m x 64 output, o < MT, p < 4
+  for (int q = wave; q < MT * 4; q += INW) {
+    const int o = q / 4, p = q % 4;
+    f4 c = f4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < H; k0 += 32) {
+      const bf16x8 a = *reinterpret_cast<const bf16x8*>(W3 + (int64_t)(16 * o + fr) * H + k0 + fk);
+      const bf16x8 b = *reinterpret_cast<const bf16x8*>(&hs[(16 * p + fr) * HLD + k0 + fk]);
+      c = mfma1(a, b, c);
+    }
+    const int row = 16 * p + fr, out0 = 16 * o + 4 * (lane >> 4);
+    if (row < rows) {
+      const f4 xv = *reinterpret_cast<const f4*>(x + (r0 + row) * m + out0);
+      const f4 bv = *reinterpret_cast<const f4*>(b3 + out0);
+      *reinterpret_cast<f4*>(y + (r0 + row) * m + out0) = xv + (c + bv);
+    }
+  }
+}
+
+// FP32 -> bf16 (nearest, ties to even)
+__global__ void round_bf16_kernel(const float* src, __bf16* dst, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < n; e += (int64_t)gridDim.x * NT)
+    dst[e] = (__bf16)src[e];
+}
+
 }  // namespace
 
 struct thcsox_mlp_s {
@@ -223,6 +331,8 @@ struct thcsox_mlp_s {
   float *Z1 = nullptr, *H1 = nullptr, *Z2 = nullptr, *H2 = nullptr, *Y = nullptr, *D = nullptr;
   float *DH = nullptr, *DZ = nullptr;
   double *part = nullptr, *loss = nullptr;
+  __bf16* Pb = nullptr;      // bf16 copy of the parameters (inference), made on first use
+  int pb_step = -1;          // the training step it was rounded at
   int step = 0;
   std::vector<void*> allocs;
   ~thcsox_mlp_s() {
@@ -415,6 +525,50 @@ int thcsox_mlp_train_step(thcsox_mlp_t q, const float* x_dev, const float* targe
     MTRY(hipStreamSynchronize(q->stream));
     *loss_host = sse / ((double)batch * q->m);
   }
+  return 0;
+}
+
+int thcsox_mlp_forward_bf16(thcsox_mlp_t q, const float* x_dev, float* y_dev, int64_t batch) {
+  clear_error();
+  if (q == nullptr || batch < 0) return set_error(THCSOX_EINVAL, "bad argument");
+  const int HT = q->H / 128, MT = q->m / 16;
+  if (q->H % 128 != 0 || (HT != 1 && HT != 2 && HT != 4) || q->m % 16 != 0 ||
+      (MT != 2 && MT != 4))
+    return set_error(THCSOX_EINVAL, "bf16 inference needs m in {32, 64} and H in {128, 256, 512}");
+  if (batch == 0) return 0;
+  if (x_dev == nullptr || y_dev == nullptr) return set_error(THCSOX_EINVAL, "NULL argument");
+  if (q->Pb == nullptr) {
+    void* v = nullptr;
+    hipError_t e = hipMalloc(&v, sizeof(__bf16) * (size_t)q->np);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return set_error(THCSOX_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    }
+    q->allocs.push_back(v);
+    q->Pb = static_cast<__bf16*>(v);
+  }
+  if (q->pb_step != q->step) {
+    round_bf16_kernel<<<blocks_for(q->np), NT, 0, q->stream>>>(q->P, q->Pb, q->np);
+    MTRY(hipGetLastError());
+    q->pb_step = q->step;
+  }
+  const int64_t nblk = (batch + IRB - 1) / IRB;
+  if (nblk > 0x7fffffffLL) return set_error(THCSOX_EINVAL, "batch too large");
+  const __bf16 *W1 = q->Pb + q->oW1, *W2 = q->Pb + q->oW2, *W3 = q->Pb + q->oW3;
+  const float *b1 = q->P + q->ob1, *b2 = q->P + q->ob2, *b3 = q->P + q->ob3;
+  auto go = [&](auto kernel) {
+    kernel<<<(unsigned)nblk, INTH, 0, q->stream>>>(x_dev, y_dev, batch, W1, b1, W2, b2, W3, b3);
+  };
+  if (MT == 4) {
+    if (HT == 4) go(mlp_infer_bf16_kernel<4, 4>);
+    else if (HT == 2) go(mlp_infer_bf16_kernel<2, 4>);
+    else go(mlp_infer_bf16_kernel<1, 4>);
+  } else {
+    if (HT == 4) go(mlp_infer_bf16_kernel<4, 2>);
+    else if (HT == 2) go(mlp_infer_bf16_kernel<2, 2>);
+    else go(mlp_infer_bf16_kernel<1, 2>);
+  }
+  MTRY(hipGetLastError());
   return 0;
 }
 

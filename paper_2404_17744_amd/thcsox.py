@@ -26,7 +26,8 @@ EXPORTS = ("thcsox_plan", "thcsox_sigma_sox", "thcsox_energy", "thcsox_destroy",
            "thcsox_last_error", "thcsox_plan_info", "thcsox_profile", "thcsox_stage_times",
            "thcsox_backproject", "thcsox_dyson_plan", "thcsox_dyson_step",
            "thcsox_dyson_onebody", "thcsox_dyson_destroy", "thcsox_mlp_create",
-           "thcsox_mlp_forward", "thcsox_mlp_gradients", "thcsox_mlp_train_step",
+           "thcsox_mlp_forward", "thcsox_mlp_forward_bf16", "thcsox_mlp_gradients",
+           "thcsox_mlp_train_step",
            "thcsox_mlp_params", "thcsox_mlp_destroy", "thcsox_pair_scale",
            "thcsox_pair_gather", "thcsox_pair_scatter", "thcsox_set_symmetry",
            "thcsox_symmetric_flags", "thcsox_dyson_step_mu", "thcsox_mix",
@@ -141,6 +142,8 @@ def lib() -> ctypes.CDLL:
         L.thcsox_mlp_create.restype = i
         L.thcsox_mlp_forward.argtypes = [vp, vp, vp, i]
         L.thcsox_mlp_forward.restype = i
+        L.thcsox_mlp_forward_bf16.argtypes = [vp, vp, vp, ctypes.c_int64]
+        L.thcsox_mlp_forward_bf16.restype = i
         L.thcsox_mlp_gradients.argtypes = [vp, vp, vp, i, vp, ctypes.POINTER(d)]
         L.thcsox_mlp_gradients.restype = i
         L.thcsox_mlp_train_step.argtypes = [vp, vp, vp, i, fp, ctypes.POINTER(d)]
@@ -492,6 +495,20 @@ class MLP:
             out = torch.empty_like(x)
         _dev64(out, "out", (self.m,), x.shape[0], exact=True, f32=True)
         _check(_ordered(self.stream, lib().thcsox_mlp_forward, self.handle, x.data_ptr(),
+                        out.data_ptr(), x.shape[0]))
+        return out
+
+    def forward_bf16(self, x, out=None):
+        """Inference with the weights and layer inputs rounded to bf16 (FP32
+        accumulation), one fused kernel per 64 rows; any batch size."""
+        import torch
+        _dev64(x, "x", (self.m,), x.shape[0], exact=True, f32=True)
+        if out is None:
+            out = torch.empty_like(x)
+        _dev64(out, "out", (self.m,), x.shape[0], exact=True, f32=True)
+        if out.data_ptr() == x.data_ptr() and x.numel() > 0:
+            raise ValueError("out may not alias x")
+        _check(_ordered(self.stream, lib().thcsox_mlp_forward_bf16, self.handle, x.data_ptr(),
                         out.data_ptr(), x.shape[0]))
         return out
 

@@ -10,8 +10,10 @@ plain loop runs as usual and judges it (the converged answer does not depend
 on the start; only the number of iterations does).
 
 All arithmetic runs in libthcsox: SOX, energy, back-projection, Dyson step,
-pair gather/scatter and the network's forward, backward and Adam kernels.
-Torch provides device buffers and index tensors only.
+pair gather/scatter, the network's FP32 forward, backward and Adam kernels
+(training) and its fused bf16 inference kernel (the learned starts: weights and
+layer inputs rounded to bf16, FP32 accumulation).  Torch provides device
+buffers and index tensors only.
 
     python -m paper_2404_17744_amd.warmstart --train 200 --eval 56
 """
@@ -178,16 +180,17 @@ def train(x, t, hidden=512, epochs=30, batch=4096, lr=1e-3, seed=0, log=print):
     return net, losses
 
 
-def warm_sigma(scf, net):
+def warm_sigma(scf, net, bf16=True):
     """Predicted converged Sigma(tau) in the orbital basis for scf's system."""
-    return warm_sigmas([scf], net)[0]
+    return warm_sigmas([scf], net, bf16)[0]
 
 
-def warm_sigmas(scfs, net):
+def warm_sigmas(scfs, net, bf16=True):
     """Predicted converged Sigma(tau) for several systems at once: the first
     SOX evaluation of each, then ONE network forward over the THC pairs of all
-    of them (a ragged batch: system i contributes its naux_i^2 pair profiles),
-    then the scatter back to each system's THC basis and the back-projection."""
+    of them (a ragged batch: system i contributes its naux_i^2 pair profiles;
+    with bf16 the fused bf16 inference kernel, else the FP32 layers), then the
+    scatter back to each system's THC basis and the back-projection."""
     torch = __import__("torch")
     xs, scales = [], []
     for scf in scfs:
@@ -196,7 +199,7 @@ def warm_sigmas(scfs, net):
         xs.append(pair_profiles(scf.Sthc, scale))
         scales.append(scale)
     x = xs[0] if len(xs) == 1 else torch.cat(xs)
-    y = net.forward(x)
+    y = net.forward_bf16(x) if bf16 else net.forward(x)
     out, o = [], 0
     for scf, scale in zip(scfs, scales):
         m, A = scf.Sthc.shape[0], scf.Sthc.shape[1]
@@ -214,7 +217,8 @@ def inference_net(net, max_batch=65536):
     return thcsox.MLP(net.m, net.H, p, max_batch=max_batch)
 
 
-def evaluate(seeds, lam, net, precision="fp16x2", damping=1.0, log=print, n_range=(40, 160)):
+def evaluate(seeds, lam, net, precision="fp16x2", damping=1.0, log=print, n_range=(40, 160),
+             bf16=True):
     """SOX evaluations to |dE| < 1e-7 from the Hartree-Fock start and from the
     learned start, for every system, and the wall time of each.  The learned
     starts of all systems are predicted as one ragged batch (warm_sigmas); the
@@ -231,7 +235,7 @@ def evaluate(seeds, lam, net, precision="fp16x2", damping=1.0, log=print, n_rang
         rows.append({"seed": sd, "n": s.n, "hf_evals": ev_hf, "hf_converged": ok_hf,
                      "E_hf": E_hf[-1], "hf_s": t1 - t0})
     torch.cuda.synchronize(); t0 = time.time()
-    preds = warm_sigmas(scfs, net)
+    preds = warm_sigmas(scfs, net, bf16)
     torch.cuda.synchronize(); t_pred = time.time() - t0
     pairs = np.array([s.naux ** 2 for s in systems], dtype=float)
     for r, s, scf, Sw in zip(rows, systems, scfs, preds):
@@ -248,6 +252,26 @@ def evaluate(seeds, lam, net, precision="fp16x2", damping=1.0, log=print, n_rang
     return rows
 
 
+def fp32_inference_check(net, x, t, ev, a, nr, hf):
+    """The same held-out systems with the FP32 forward instead of the bf16
+    inference kernel, and the loss of both forwards on the first training
+    samples (the loss of the bf16 forward from the oracle-parity kernel)."""
+    nb = min(65536, x.shape[0])
+    xs, ts = x[:nb].contiguous(), t[:nb].contiguous()
+    tn = ts.cpu().numpy().astype(np.float64)
+    loss32 = float(((net.forward(xs).cpu().numpy() - tn) ** 2).mean())
+    loss16 = float(((net.forward_bf16(xs).cpu().numpy() - tn) ** 2).mean())
+    inet = inference_net(net)
+    rows = evaluate(ev, a.lam, inet, a.precision, a.damping, n_range=nr, bf16=False)
+    inet.close()
+    wm = np.array([r["warm_evals"] for r in rows])
+    return {"fp32_inference": {"loss_fp32_forward": loss32, "loss_bf16_forward": loss16,
+                               "warm_evals_mean": float(wm.mean()),
+                               "warm_time_mean_s": float(np.mean([r["warm_s"] for r in rows])),
+                               "systems_saved": int((wm < hf).sum()),
+                               "systems_worse": int((wm > hf).sum())}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--train", type=int, default=200)
@@ -262,6 +286,9 @@ def main():
     ap.add_argument("--out", default=None)
     ap.add_argument("--nmin", type=int, default=40)
     ap.add_argument("--nmax", type=int, default=160)
+    ap.add_argument("--fp32-inference-check", action="store_true",
+                    help="also evaluate the held-out systems with the FP32 forward (the "
+                         "default inference rounds weights and layer inputs to bf16)")
     a = ap.parse_args()
     nr = (a.nmin, a.nmax)
     rng = np.random.default_rng(7)
@@ -291,6 +318,8 @@ def main():
            "fell_back": int(sum(r["warm_fell_back"] for r in rows)),
            "all_converged": bool(all(r["hf_converged"] and r["warm_converged"] for r in rows)),
            "rows": rows}
+    if a.fp32_inference_check:
+        res.update(fp32_inference_check(net, x, t, ev, a, nr, hf))
     print(json.dumps({k: v for k, v in res.items() if k != "rows"}), flush=True)
     if a.out:
         with open(a.out, "w") as f:

@@ -120,3 +120,64 @@ def test_pair_gather_scatter_roundtrip(dev):
     pairs = torch.tensor([0, 5, A * A - 1], dtype=torch.int64, device=dev)
     xs = warmstart.pair_profiles(S, scale, pairs).cpu().numpy()
     assert np.abs(xs - ref[[0, 5, A * A - 1]]).max() < 1e-7
+
+
+@pytest.mark.parametrize("m,H,B", [(64, 512, 300), (32, 128, 77), (64, 256, 64)])
+def test_mlp_forward_bf16_matches_oracle(dev, m, H, B):
+    """The fused bf16 inference kernel against the oracle's forward_bf16 (the
+    same roundings, exact sums): FP32 accumulation, the device exp in silu and
+    the rare bf16 rounding flip of a hidden value that these cause keep the
+    difference under half a bf16 unit of the residual branch; the full-precision
+    forward is farther away (the bf16 roundings themselves)."""
+    p32, x, _ = _case(m=m, H=H, B=B)
+    rng = np.random.default_rng(m + H)
+    for k in ("b1", "b2", "b3"):   # non-zero biases
+        p32[k] = (0.3 * rng.standard_normal(p32[k].shape)).astype(np.float32)
+    print(f"case mlp forward bf16 m{m} H{H} B{B}", flush=True)
+    net = thcsox.MLP(m, H, p32, max_batch=64)
+    xd = torch.from_numpy(x).to(dev)
+    y = net.forward_bf16(xd).cpu().numpy()
+    net.close()
+    p64 = {k: v.astype(np.float64) for k, v in p32.items()}
+    ref = omlp.forward_bf16(p64, x.astype(np.float64))
+    full, _ = omlp.forward(p64, x.astype(np.float64))
+    branch = np.abs(full - x).max()
+    err, dist = np.abs(y - ref).max(), np.abs(full - ref).max()
+    print(f"  max |gpu - oracle bf16| {err / branch:.2e}, |oracle bf16 - FP64 forward| "
+          f"{dist / branch:.2e} (relative to the branch)")
+    assert err <= 2.0 ** -9 * branch
+    assert dist > 4 * err
+
+
+def test_mlp_forward_bf16_edges_and_refresh(dev):
+    """Batch 0 is a no-op, unsupported widths are refused, a large ragged batch
+    matches the FP32 forward to bf16 accuracy, and after a training step the
+    bf16 copy follows the new parameters."""
+    from paper_2404_17744_amd.thcsox import ThcsoxError
+    p32, x, t = _case(m=64, H=512, B=256)
+    net = thcsox.MLP(64, 512, p32, max_batch=256)
+    print("case mlp forward bf16 edges", flush=True)
+    empty = torch.empty((0, 64), dtype=torch.float32, device=dev)
+    assert net.forward_bf16(empty).shape == (0, 64)
+    rng = np.random.default_rng(9)
+    big = torch.from_numpy(rng.standard_normal((100003, 64)).astype(np.float32)).to(dev)
+    yb, yf = net.forward_bf16(big), net.forward(big)
+    branch = (yf - big).abs().max().item()
+    assert (yb - yf).abs().max().item() <= 8 * 2.0 ** -8 * branch
+    sel = [0, 63, 64, 50000, 100002]
+    ref = omlp.forward_bf16({k: v.astype(np.float64) for k, v in p32.items()},
+                            big[sel].cpu().numpy().astype(np.float64))
+    assert np.abs(yb[sel].cpu().numpy() - ref).max() <= 2.0 ** -9 * branch
+    xd, td = torch.from_numpy(x).to(dev), torch.from_numpy(t).to(dev)
+    net.train_step(xd, td, 1e-2)
+    p_new = {k: v.astype(np.float64) for k, v in net.params().items()}
+    y2 = net.forward_bf16(xd).cpu().numpy()
+    ref2 = omlp.forward_bf16(p_new, x.astype(np.float64))
+    assert np.abs(y2 - ref2).max() <= 2.0 ** -9 * branch
+    net.close()
+    with pytest.raises(ThcsoxError):
+        odd = thcsox.MLP(48, 128, {k: v for k, v in _case(m=48, H=128, B=4)[0].items()})
+        try:
+            odd.forward_bf16(torch.zeros((4, 48), dtype=torch.float32, device=dev))
+        finally:
+            odd.close()

@@ -108,3 +108,47 @@ def test_adam_three_steps_hand_derived():
     want2 = -lr * (0.39 / 0.19) / np.sqrt(0.009999 / 0.001999)
     assert abs(steps[1, 2] - want2) < 1e-14
     assert st["t"] == 3
+
+
+def test_bf16_round_values():
+    """Nearest with ties to even on the 8-bit significand: 1 + 2^-8 lies halfway
+    between 1 and 1 + 2^-7 and goes to 1 (even); 1 + 3 2^-8 lies halfway between
+    1 + 2^-7 (odd) and 1 + 2^-6 and goes up; just above a tie rounds up; signs
+    and powers of two pass; and it agrees with torch's bfloat16 conversion."""
+    import torch
+    cases = {1.0: 1.0, 1 + 2 ** -8: 1.0, 1 + 3 * 2 ** -8: 1 + 2 ** -6,
+             1 + 2 ** -8 + 2 ** -20: 1 + 2 ** -7, -(1 + 3 * 2 ** -8): -(1 + 2 ** -6),
+             2.0 ** -30: 2.0 ** -30, 3.0: 3.0, 0.0: 0.0}
+    for a, want in cases.items():
+        assert omlp.bf16_round(a) == want, (a, omlp.bf16_round(a), want)
+    rng = np.random.default_rng(0)
+    v = (rng.standard_normal(20000) * 10.0 ** rng.uniform(-6, 6, 20000)).astype(np.float32)
+    ref = torch.from_numpy(v).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(omlp.bf16_round(v), ref)
+
+
+def test_forward_bf16_within_the_rounding_bound():
+    """bf16 weights and layer inputs move the output of the residual branch by
+    a few bf16 units of it (relative 2^-8 per rounding, four roundings per
+    path) on random data; and on a network whose weights and inputs are already
+    bf16 values (one-hot inputs, identity W2) the only roundings left are those
+    of h1 and h2, written out here by hand."""
+    m, H = 16, 32
+    p = omlp.init_params(m, H, seed=2)
+    p["W3"] *= 30.0
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal((200, m))
+    ref, _ = omlp.forward(p, x)
+    got = omlp.forward_bf16(p, x)
+    branch = np.abs(ref - x).max()
+    assert 0.0 < np.abs(got - ref).max() <= 8 * 2.0 ** -8 * branch
+    # exact case: W, x bf16 values; one-hot rows make every product a single term
+    q = {k: omlp.bf16_round(v) for k, v in p.items()}
+    q["W2"] = np.eye(H)
+    xe = np.zeros((m, m)); xe[np.arange(m), np.arange(m)] = 1.0
+    # then z1 = W1 column + b1 (bf16 values), h1 = silu(z1) is rounded once in
+    # both; the difference from forward is exactly the rounding of h1 and h2
+    h1 = omlp.silu(q["W1"].T + q["b1"])
+    h2 = omlp.silu(omlp.bf16_round(h1) + q["b2"])
+    want = xe + omlp.bf16_round(h2) @ q["W3"].T + q["b3"]
+    assert np.allclose(omlp.forward_bf16(q, xe), want, rtol=0, atol=1e-15)
