@@ -4,14 +4,17 @@
 //
 // for one or more tau points ("sets") per launch, as C(i, j) = sum_k Uop[i][k]
 // Gop[j][k] with Uop the rows (P, q) of U and Gop the rows v of G(beta - tau)^T,
-// both K-major fp16 planes (x = x0 + x1, products x1 y0 + x0 y1 + x0 y0 on the
-// f16 matrix cores, FP32 accumulation).  The result is written in FP32 and max
-// |A| is max-reduced per set for the scaling that the fused stage applies when
-// it splits A.
+// both K-major fp16 operands in the c32 layout (the two planes x = x0 + x1
+// interleaved per 32-wide k chunk: row r, plane p, k at r * 2 ldk + (k / 32) *
+// 64 + 32 p + k % 32); products x1 y0 + x0 y1 + x0 y0 on the f16 matrix cores,
+// FP32 accumulation.  The result is scaled by the power of two taken from
+// amax[set] (a bound on |A| placed near 2^14, computed before the launch) and
+// written as fp16 planes in the same c32 layout, rows (v, P) with k = q, which
+// is what the fused stage loads.
 //
 // Rows are walked in the padded row space of A, i = P ldk + q: a 128-row tile is
-// 512 contiguous bytes of one v panel, so every 128-byte line of A is written
-// whole by one workgroup (rows n <= q < ldk read U as zero and write zeros).
+// four whole 32-wide chunks of one v row set, so no output line is shared by two
+// workgroups (rows n <= q < ldk read U as zero and write zeros).
 // A workgroup of eight waves (two per SIMD) works on 128 rows at a time and TN =
 // 64 WBN columns (v), WBN <= 5; wave (wm, wn) holds 64 x 16 WBN of it.  The grid
 // is persistent (about one workgroup per compute unit): a workgroup walks its
@@ -22,15 +25,14 @@
 // that XCD's L2 to the others.  Each 32-wide k stage of both operands (U: 16 KiB,
 // G: TN x 128 B) is loaded from memory straight into one of two LDS buffers, one
 // stage ahead of the matrix cores; the fragments of the next stage are read while
-// the second half of the current stage's MFMAs run.  The MFMA takes the G
-// fragment as its row operand, so a lane's output elements run along i: stores
-// of 16 lanes cover 64 contiguous bytes.
+// the second half of the current stage's MFMAs run.  The MFMA takes the U
+// fragment as its row operand, so a lane's four outputs are four consecutive
+// rows i of one v: one 8-byte store per plane.
 #include <algorithm>
 
 #include "kernels.hpp"
 #include "mfma.hpp"
 #include "panel.hpp"
-#include "reduce.hpp"
 
 namespace thcsox {
 namespace {
@@ -80,10 +82,9 @@ __device__ __forceinline__ void astage_body(const AStageArgs& g, ABuf& b0, ABuf&
   const int kst = g.ldk / AKC;
   const int64_t ldk = g.ldk;
 
-  const _Float16* B = static_cast<const _Float16*>(g.Gb) + set * g.gb_set + j0 * ldk;
-  __amdgpu_buffer_rsrc_t rB[2];
-#pragma unroll
-  for (int p = 0; p < 2; ++p) rB[p] = make_rsrc(B + p * g.gb_plane, TN * ldk * 2);
+  const int64_t ld2 = 2 * ldk;   // halves per c32 row
+  const _Float16* B = static_cast<const _Float16*>(g.Gb) + set * g.gb_set + j0 * ld2;
+  const __amdgpu_buffer_rsrc_t rB = make_rsrc(B, rows_j * ld2 * 2);
   // memory-to-LDS slabs of 16 rows: U has 8 per plane (wave w moves slab w of
   // both planes), G has TN / 16 per plane, 8 WBN in all (wave w moves the
   // slabs w + 8 j, j < WBN, counted across the two planes)
@@ -95,36 +96,36 @@ __device__ __forceinline__ void astage_body(const AStageArgs& g, ABuf& b0, ABuf&
     const int slab = (wave + ANW * j) % GSP;
     const int row = slab * 16 + (lane >> 2);
     const int c = lds_chunk(row, lane & 3);
-    dg[j] = row < rows_j ? (uint32_t)((row * ldk + 8 * c) * 2) : OOB;
+    dg[j] = row < rows_j ? (uint32_t)((row * ld2 + 8 * c) * 2) : OOB;
   }
   // the U rows of the tile being fetched: this lane's row i = i0 + urow is U row
   // P n + q (none for q >= n), addressed from the tile's first P
   const _Float16* Ub = static_cast<const _Float16*>(g.U);
   const int64_t urows = (int64_t)g.naux * g.n;
-  __amdgpu_buffer_rsrc_t rU[2];
+  __amdgpu_buffer_rsrc_t rU;
   uint32_t du = OOB;
   auto set_tile = [&](int t) {
     const int i0 = (first + t * stride) * AM;
     const int P0 = __builtin_amdgcn_readfirstlane(i0 / g.ldk);
     const int i = i0 + urow, P = i / g.ldk, q = i - P * g.ldk;
     du = (P < g.naux && q < g.n)
-             ? (uint32_t)((((P - P0) * g.n + q) * ldk + 8 * lds_chunk(urow, lane & 3)) * 2)
+             ? (uint32_t)((((P - P0) * g.n + q) * ld2 + 8 * lds_chunk(urow, lane & 3)) * 2)
              : OOB;
     const int64_t r0 = (int64_t)P0 * g.n;
-#pragma unroll
-    for (int p = 0; p < 2; ++p) rU[p] = make_rsrc(Ub + p * g.u_plane + r0 * ldk, (urows - r0) * ldk * 2);
+    rU = make_rsrc(Ub + r0 * ld2, (urows - r0) * ld2 * 2);
   };
-  // stage k of the current fetch tile -> LDS buffer
+  // stage k of the current fetch tile -> LDS buffer; plane p of chunk k is
+  // (64 k + 32 p) halves into a c32 row
   auto dma = [&](ABuf& bf, int k) {
 #pragma unroll
     for (int p = 0; p < 2; ++p)
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(rU[p], &bf.u[p][wave * 16 * AKC], 16, du,
-                                               k * AKC * 2, 0, 0);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rU, &bf.u[p][wave * 16 * AKC], 16, du,
+                                               (2 * k + p) * AKC * 2, 0, 0);
 #pragma unroll
     for (int j = 0; j < WBN; ++j) {
       const int s = wave + ANW * j, p = s / GSP, slab = s % GSP;
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(p ? rB[1] : rB[0], &bf.g[p][slab * 16 * AKC], 16,
-                                               dg[j], k * AKC * 2, 0, 0);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rB, &bf.g[p][slab * 16 * AKC], 16, dg[j],
+                                               (2 * k + p) * AKC * 2, 0, 0);
     }
   };
 
@@ -149,7 +150,7 @@ __device__ __forceinline__ void astage_body(const AStageArgs& g, ABuf& b0, ABuf&
       for (int t = 0; t < WBN; ++t) fr.g[p][t] = *reinterpret_cast<const f16x8*>(&bf.g[p][gj[t]]);
     }
   };
-  // acc[tj][ti]: rows v (tile tj), columns i (tile ti)
+  // acc[tj][ti]: rows i (tile ti), columns v (tile tj)
   f4 acc[WBN][4];
 #pragma unroll
   for (int a = 0; a < WBN; ++a)
@@ -162,34 +163,45 @@ __device__ __forceinline__ void astage_body(const AStageArgs& g, ABuf& b0, ABuf&
       const int tile = q / 3, pp = q % 3;
       const int tj = tile / 4, ti = tile % 4;
       const int pg = pp == 0 ? 1 : 0, pu = pp == 1 ? 1 : 0;
-      acc[tj][ti] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fr.g[pg][tj], fr.u[pu][ti],
+      acc[tj][ti] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fr.u[pu][ti], fr.g[pg][tj],
                                                            acc[tj][ti], 0, 0, 0);
     }
   };
 
-  float lmax = 0.f;
-  float* C = g.A + set * g.a_set;
-  const int64_t c_j = (int64_t)g.naux * ldk;
-  const int jb = j0 + wn * 16 * WBN + 4 * (lane >> 4);
-  // write the finished tile t and clear the accumulators
+  // the scale of A: 2^-ilogb(amax[set]); amax is a bound on |A| times 2^-14, so
+  // every scaled value stays below 2^15 and fp16 keeps 11 + 11 bits of it
+  const float a_scale = (float)pow2_scale_f(g.amax + set);
+  _Float16* C = g.A + set * g.a_set;
+  const int64_t c_j = (int64_t)g.naux * ld2;   // halves between v rows of A
+  const int jb = j0 + wn * 16 * WBN + (lane & 15);
+  typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+  // write the finished tile t: lane holds rows i0 .. i0 + 3 (one 32-wide chunk)
+  // of column v; element (v, i, plane p) is at v c_j + 64 (i / 32) + i % 32 + 32 p
   auto store_tile = [&](int t) {
-    const int ib = (first + t * stride) * AM + wm * 64 + (lane & 15);
+    const int ib = (first + t * stride) * AM + wm * 64 + 4 * (lane >> 4);
 #pragma unroll
     for (int ti = 0; ti < 4; ++ti) {
-      const int i = ib + 16 * ti;
-      const bool ok = i < M;
+      const int i0 = ib + 16 * ti;
+      const bool ok = i0 < M;   // M is a multiple of 32: all four rows or none
+      const int64_t io = 64 * (i0 >> 5) + (i0 & 31);
 #pragma unroll
-      for (int tj = 0; tj < WBN; ++tj)
+      for (int tj = 0; tj < WBN; ++tj) {
+        const int j = jb + 16 * tj;
+        if (ok && j < g.n) {
+          h4 hi, lo;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int j = jb + 16 * tj + r;
-          if (ok && j < g.n) {
-            const float v = acc[tj][ti][r];
-            C[i + (int64_t)j * c_j] = v;
-            lmax = fmaxf(lmax, fabsf(v));
+          for (int r = 0; r < 4; ++r) {
+            const float x = acc[tj][ti][r] * a_scale;
+            const _Float16 h = (_Float16)x;
+            hi[r] = h;
+            lo[r] = (_Float16)(x - (float)h);
           }
-          acc[tj][ti][r] = 0.f;
+          _Float16* o = C + (int64_t)j * c_j + io;
+          *reinterpret_cast<h4*>(o) = hi;
+          *reinterpret_cast<h4*>(o + 32) = lo;
         }
+        acc[tj][ti] = f4{0.f, 0.f, 0.f, 0.f};
+      }
     }
   };
 
@@ -227,7 +239,6 @@ __device__ __forceinline__ void astage_body(const AStageArgs& g, ABuf& b0, ABuf&
   }
   // the last (repeated) memory-to-LDS loads land before the workgroup may end
   __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  if (g.amax != nullptr) block_atomic_max<ANW>((double)lmax, g.amax + set);
 }
 
 // one kernel per column count (the body is a device template)
@@ -267,9 +278,9 @@ hipError_t a_launch(void (*kernel)(AStageArgs), const AStageArgs& g, hipStream_t
 hipError_t astage_f16(const AStageArgs& g, hipStream_t s) {
   if (g.naux <= 0 || g.n <= 0 || g.nsets <= 0) return hipSuccess;
   if (g.ldk % (2 * AKC) != 0 || g.ldk < g.n) return hipErrorInvalidValue;
-  // 32-bit row indices and buffer offsets inside one tile
+  // 32-bit row indices and buffer offsets inside one tile (c32 rows of 4 ldk bytes)
   if ((int64_t)g.naux * g.ldk + AM > 0x7fffffffLL ||
-      (int64_t)(AM + 2 * g.n) * g.ldk * 2 > 0x7fffffffLL || (int64_t)320 * g.ldk * 2 > 0x7fffffffLL)
+      (int64_t)(AM + 2 * g.n) * g.ldk * 4 > 0x7fffffffLL || (int64_t)320 * g.ldk * 4 > 0x7fffffffLL)
     return hipErrorInvalidValue;
   if (g.n <= 128) return a_launch<2>(astage_f16_kernel_2, g, s);
   if (g.n <= 192) return a_launch<3>(astage_f16_kernel_3, g, s);

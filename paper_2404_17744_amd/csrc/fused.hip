@@ -277,6 +277,7 @@ void fused_tile(int mode, int* rows, int* cols) {
 int fused_xcds() { return NXCD; }
 
 hipError_t sox_fused(int mode, const FusedArgs& f, hipStream_t s) {
+  if (mode == MODE_F16X2) return sox_fused_f16(f, s);   // own kernel and checks
   int TR, TP;
   fused_tile(mode, &TR, &TP);
   if (f.vsplit % NXCD != 0 || (int64_t)f.vsplit * f.vchunk < f.n) return hipErrorInvalidValue;
@@ -292,7 +293,6 @@ hipError_t sox_fused(int mode, const FusedArgs& f, hipStream_t s) {
       if (f.a_f32) fused_kernel<MODE_BF16X3, true><<<grid, NT, 0, s>>>(f);
       else fused_kernel<MODE_BF16X3, false><<<grid, NT, 0, s>>>(f);
       break;
-    case MODE_F16X2: return sox_fused_f16(f, s);   // FP32 A split on the fly
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

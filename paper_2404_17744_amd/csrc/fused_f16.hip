@@ -4,31 +4,35 @@
 //
 // Every operand is a power-of-two scaled value split into two fp16 planes
 // x = x0 + x1; a product is formed from the plane products x1 y0 + x0 y1 + x0 y0
-// on the f16 matrix cores (16x16x32, FP32 accumulation).
+// on the f16 matrix cores (16x16x32, FP32 accumulation).  The operands are
+// K-major rows with the two planes interleaved per 32-wide k chunk (layout c32:
+// row r, plane p, k at r * 2 ldk + (k / 32) * 64 + 32 p + k % 32), so one
+// 128-byte request fetches both planes of a row's chunk.
 //
-// Eight waves (two per SIMD) in a 2 x 4 arrangement each own a 64 x 32 sub-tile
-// (4 x 2 MFMA tiles) of accB, accC and the FP32 partial sum of D; everything a
-// wave holds fits its 256 registers, so the two waves of a SIMD hide each
-// other's LDS and memory latency.  A stage is one v and one
-// 32-wide k chunk: four panels (G rows R, U_v rows R, A_v rows P, GX rows P) of
-// 128 rows x 32 k in two fp16 planes, 64 KiB, double buffered in LDS (128 KiB).
-// The fp16 panels are loaded from memory directly into LDS; the A panel arrives
-// as FP32 in registers and is split while it is written to LDS.
+// Work split.  A workgroup owns a 128 x 128 tile of D and a range of v, taken
+// two v at a time: the k loop of a pair forms B and C for both v at once, so
+// the v-independent panels (G rows R, GX rows P) are loaded once per pair and
+// feed four products.  Four waves (one per SIMD) in a 2 x 2 arrangement each
+// own 64 x 64 of the tile: the four accumulator sets B1, B2, C1, C2 (256
+// registers) live in the matrix-core registers (AGPRs), fragments in the
+// ordinary ones.  The partial sum of D (FP32, at most 8 v) lives in LDS, one
+// private 16-byte slot per lane and MFMA tile, and is updated once per pair:
+// D += B1 o C1 + B2 o C2.
 //
-// The loop is software pipelined so that the matrix cores, the LDS and the
-// memory system work at the same time.  With cur = t mod 2, stage t runs as
-//   phase 1: fragments of the C product (stage t)   <- LDS buffer cur,
-//            matrix cores: B product, first 32 of 48 MFMAs;
-//   phase 2: A of stage t+1 (registers) -> LDS buffer cur^1,
-//            matrix cores: last 16 MFMAs of B, first 16 of C;
-//   wait for this wave's loads, barrier;
-//   phase 3: fragments of the B product (stage t+1) <- LDS buffer cur^1,
-//            loads of stage t+2 -> LDS buffer cur and registers,
-//            matrix cores: last 32 MFMAs of C.
-// The loop body has no branches: past the last stage the loads repeat the last
-// stage and the extra panels written to LDS are never used.  The operand row
-// length (ldk) is a multiple of 64, so each v takes an even number of stages
-// and the loop runs two stages per trip with the buffers fixed at compile time.
+// Pipeline.  A k chunk is two half stages, each three panels of 128 rows x 32 k
+// x 2 planes (48 KiB): the B half (G, A_v1, A_v2) in LDS buffer sB and the C
+// half (GX, U_v1, U_v2) in sC.  With 64 KiB for D the workgroup uses the full
+// 160 KiB of LDS.  Chunk t runs as
+//   phase B(t): barrier (C(t) is in sC, every wave has read B(t) from sB);
+//               loads of B(t+1) -> sB; fragments of C(t) <- sC;
+//               matrix cores: B1, B2 += products of B(t) (fragments read before)
+//   phase C(t): barrier (B(t+1) is in sB, every wave has read C(t) from sC);
+//               loads of C(t+1) -> sC; fragments of B(t+1) <- sB;
+//               matrix cores: C1, C2 += products of C(t)
+// so each half stage is loaded one phase ahead of its fragment reads, and each
+// fragment is read one phase ahead of its products.  The first chunk of a pair
+// starts the accumulators from zero inside the MFMA (no register clearing).
+// Past the last chunk the loads repeat it (never used).
 #include "kernels.hpp"
 #include "mfma.hpp"
 #include "panel.hpp"
@@ -36,281 +40,287 @@
 namespace thcsox {
 namespace {
 
-constexpr int TT = 128;        // tile edge of D (R and P)
-constexpr int WR_ = 2, WP_ = 4;                 // waves along R and along P
-constexpr int NW = WR_ * WP_, NTH = 64 * NW;
-constexpr int WBR = TT / 16 / WR_, WBP = TT / 16 / WP_;   // MFMA tiles per wave
-constexpr int KC = 32;         // k per stage (one f16 MFMA)
-constexpr int PANEL = TT * KC; // halves per panel plane
-constexpr int FLUSH16 = 8;     // v per FP32 partial sum of D
+constexpr int TT = 128;          // tile edge of D (R and P)
+constexpr int NW = 4, NTH = 64 * NW;
+constexpr int KC = 32;           // k per chunk (one f16 MFMA)
+constexpr int PANEL = TT * KC * 2;   // halves per panel (both planes)
+constexpr int FLUSH_PAIRS = 4;   // pairs per FP32 partial sum of D (8 v)
 constexpr int NXCD16 = 8;
-constexpr int BAND16 = 2;   // R blocks per band (measured: 2 beats 1, 3, 4, 5, 6, 8, 15)
+constexpr int BAND16 = 2;        // R blocks per band of the tile walk (measured: 2 beats 1, 3, 4, 15)
 
-typedef _Float16 h4 __attribute__((ext_vector_type(4)));
-
-// One LDS stage buffer: [panel G, U, A, X][plane][row * 32 + physical chunk * 8 + e].
-// The two buffers are separate objects and every access names one of them at
-// compile time, so the compiler can tell that reads of one buffer do not wait
-// for memory-to-LDS loads still landing in the other.
-struct Buf {
-  _Float16 s[4][2][PANEL];
+// One half stage: three panels, each [row][plane][32] (128-byte rows) with the
+// eight 16-byte chunks of a row permuted by sw8.
+struct Half {
+  _Float16 s[3][PANEL];
 };
 
+// Physical 16-byte chunk of logical chunk c (= 4 plane + k / 8) in LDS row r.
+// Fragment reads take 16 consecutive rows at one logical chunk; XOR-ing the
+// chunk with (r / 2) mod 8 places the 16 rows' chunks at all eight positions of
+// two consecutive 128-byte rows (rocprofv3 counts no LDS bank conflicts).
+__device__ __forceinline__ int sw8(int r, int c) { return c ^ ((r >> 1) & 7); }
+
 __device__ __forceinline__ void vm_lds_barrier() {
-  // This wave's memory loads (including those that write LDS) and LDS accesses
-  // complete, then the workgroup barrier.
+  // this wave's memory loads (including those that write LDS) and LDS accesses
+  // complete, then the workgroup barrier
   __asm__ volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
-__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(NW / 4, NW / 4)))
+__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void fused_f16_kernel(FusedArgs f) {
-  __shared__ __attribute__((aligned(16))) Buf sb0;
-  __shared__ __attribute__((aligned(16))) Buf sb1;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wr = wave / WP_, wc = wave % WP_;
+  __shared__ __attribute__((aligned(16))) Half sB;   // G, A_v1, A_v2
+  __shared__ __attribute__((aligned(16))) Half sC;   // GX, U_v1, U_v2
+  __shared__ __attribute__((aligned(16))) f4 sD[NW * 16 * 64];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wr = wave >> 1, wc = wave & 1;
+  const int naux = f.naux, n = f.n, ldk = f.ldk;
 
-  // tile and v range: XCD-aware order (workgroup b runs on XCD b mod 8; each XCD
-  // owns the partial slots z = xcd, xcd + 8, ..., a block of consecutive v ranges
-  // (below), and walks the tiles in bands of BAND16
-  // R blocks so its resident workgroups share U_v and A_v panels in its L2)
-  const int nb = (f.naux + TT - 1) / TT;
+  // tile and pair range: XCD-aware order (workgroup b runs on XCD b mod 8; each
+  // XCD owns the partial slots z = xcd, xcd + 8, ..., a block of consecutive
+  // pair ranges, and walks the tiles in bands of BAND16 R blocks so its resident
+  // workgroups share panels in its L2).  The integer divisions run on the vector
+  // unit; readfirstlane marks their results uniform so that buffer resources and
+  // offsets stay scalar.
+  const int nb = (naux + TT - 1) / TT;
   const int tiles = nb * nb;
   const int b = blockIdx.x;
   const int xcd = b % NXCD16, local = b / NXCD16;
-  const int z = xcd + NXCD16 * (local / tiles);
+  const int z = __builtin_amdgcn_readfirstlane(xcd + NXCD16 * (local / tiles));
   const int to = local % tiles;
   const int band = to / (BAND16 * nb);
   const int rb0 = band * BAND16, bh = min(BAND16, nb - rb0);
   const int within = to - rb0 * nb;
-  const int P0 = (within / bh) * TT, R0 = (rb0 + within % bh) * TT;
+  const int P0 = __builtin_amdgcn_readfirstlane((within / bh) * TT);
+  const int R0 = __builtin_amdgcn_readfirstlane((rb0 + within % bh) * TT);
   if (f.sym != nullptr && *f.sym != 0 && R0 >= P0 + TT) return;
 
-  // v range: XCD x owns the consecutive ranges x q .. x q + q - 1 (q = vsplit / NXCD16),
-  // and the ranges split n as evenly as floor division allows, so every XCD gets
-  // the same number of v to within one; range r is [r n / vsplit, (r + 1) n / vsplit)
+  // pair range: XCD x owns the consecutive ranges x q .. x q + q - 1
+  // (q = vsplit / 8); range r is pairs [r np / vsplit, (r + 1) np / vsplit)
+  const int npair = (n + 1) / 2;
   const int vr = (z % NXCD16) * (f.vsplit / NXCD16) + z / NXCD16;
-  const int v_lo = (int)((int64_t)vr * f.n / f.vsplit);
-  const int v_hi = (int)((int64_t)(vr + 1) * f.n / f.vsplit);
-  const int kst = f.ldk / KC;
-  const int nstage = (v_hi > v_lo) ? (v_hi - v_lo) * kst : 0;
-  const int64_t ldk = f.ldk;
-  const int64_t u_row = (int64_t)f.n * ldk;     // elements between R rows of U
-  const int64_t a_v = (int64_t)f.naux * ldk;    // elements between v slabs of A
-  const float a_scale = (float)pow2_scale_f(f.amax_a);
-  const int rows_r = min(TT, f.naux - R0), rows_p = min(TT, f.naux - P0);
+  const int p_lo = __builtin_amdgcn_readfirstlane((int)((int64_t)vr * npair / f.vsplit));
+  const int p_hi = __builtin_amdgcn_readfirstlane((int)((int64_t)(vr + 1) * npair / f.vsplit));
+  const int npr = p_hi - p_lo;
+  const int kst = ldk / KC;
+  const int ld2 = 2 * ldk;   // halves per c32 row
+  const int rows_r = min(TT, naux - R0), rows_p = min(TT, naux - P0);
 
-  const _Float16* Gt = static_cast<const _Float16*>(f.Gt) + R0 * ldk;
-  const _Float16* GX = static_cast<const _Float16*>(f.GXt) + P0 * ldk;
-  const _Float16* U = static_cast<const _Float16*>(f.U) + R0 * u_row;
-  const float* A = static_cast<const float*>(f.A) + P0 * ldk;
-  __amdgpu_buffer_rsrc_t rG[2], rX[2];
-#pragma unroll
-  for (int p = 0; p < 2; ++p) {
-    rG[p] = make_rsrc(Gt + p * f.g_plane, TT * ldk * 2);
-    rX[p] = make_rsrc(GX + p * f.g_plane, TT * ldk * 2);
-  }
+  const _Float16* Gt = static_cast<const _Float16*>(f.Gt);
+  const _Float16* GX = static_cast<const _Float16*>(f.GXt);
+  const __amdgpu_buffer_rsrc_t rG = make_rsrc(Gt + (int64_t)R0 * ld2, (int64_t)rows_r * ld2 * 2);
+  const __amdgpu_buffer_rsrc_t rX = make_rsrc(GX + (int64_t)P0 * ld2, (int64_t)rows_p * ld2 * 2);
+  const _Float16* Ubase = static_cast<const _Float16*>(f.U) + (int64_t)R0 * n * ld2;
+  const _Float16* Abase = static_cast<const _Float16*>(f.A) + (int64_t)P0 * ld2;
+  const int64_t a_v = (int64_t)naux * ld2;   // halves between v slabs of A
 
-  // The fp16 panels (G, U_v, GX) go from memory straight into LDS (buffer loads
-  // with the LDS destination): wave w moves the 16-row slabs w, w + NW, ... of
-  // each panel plane (one slab with eight waves); lane l lands at slab row l / 4, physical chunk l % 4, so it
-  // loads the logical chunk that the swizzle maps there.  Rows past the end of
-  // naux read as zero (their offsets point out of the buffer).
-  constexpr int SL = 8 / NW;   // 16-row slabs per wave and panel plane
-  uint32_t dg[SL], du[SL], dx[SL];
+  // memory -> LDS: one instruction moves 8 rows x 128 bytes; wave w moves the
+  // 8-row slabs w, w + 4, w + 8, w + 12 of each panel.  Lane l lands at slab row
+  // l / 8, physical chunk l % 8, and loads the logical chunk sw8 maps there.
+  // Rows past the valid range lie beyond the buffer resource and read as zero.
+  uint32_t dR[4], dU[4];
 #pragma unroll
-  for (int j = 0; j < SL; ++j) {
-    const int row = (wave + NW * j) * 16 + (lane >> 2);
-    const int c = lds_chunk(row, lane & 3);   // the map is its own inverse
-    dg[j] = row < rows_r ? (uint32_t)((row * ldk + 8 * c) * 2) : OOB;
-    du[j] = row < rows_r ? (uint32_t)((row * u_row + 8 * c) * 2) : OOB;
-    dx[j] = row < rows_p ? (uint32_t)((row * ldk + 8 * c) * 2) : OOB;
+  for (int j = 0; j < 4; ++j) {
+    const int row = (wave + NW * j) * 8 + (lane >> 3);
+    const int c = sw8(row, lane & 7);
+    dR[j] = (uint32_t)((row * ld2 + 8 * c) * 2);
+    dU[j] = (uint32_t)((row * (n * ld2) + 8 * c) * 2);
   }
-  auto dma = [&](Buf& b, int v, int k0) {
+  // per pair: A slabs v1, v2 (rows P) and U rows (R, v1), (R, v2); a missing
+  // second v (odd n) gets empty resources, so its panels read as zero and B2 = 0
+  __amdgpu_buffer_rsrc_t rA1, rA2, rU1, rU2;
+  const int64_t a_bytes = (int64_t)rows_p * ld2 * 2;
+  const int64_t u_bytes = ((int64_t)(rows_r - 1) * n * ld2 + ld2) * 2;
+  auto set_pair = [&](int pr) {
+    const int v1 = 2 * (p_lo + pr);
+    const bool two = v1 + 1 < n;
+    rA1 = make_rsrc(Abase + (int64_t)v1 * a_v, a_bytes);
+    rA2 = make_rsrc(Abase + (int64_t)(v1 + 1) * a_v, two ? a_bytes : 0);
+    rU1 = make_rsrc(Ubase + (int64_t)v1 * ld2, u_bytes);
+    rU2 = make_rsrc(Ubase + (int64_t)(v1 + 1) * ld2, two ? u_bytes : 0);
+  };
+  auto dmaB = [&](int k0) {
+    const int so = k0 * 4;   // bytes to the k chunk (both planes)
 #pragma unroll
-    for (int p = 0; p < 2; ++p) {
-      const __amdgpu_buffer_rsrc_t rU =
-          make_rsrc(U + p * f.u_plane + (int64_t)v * ldk, (int64_t)TT * u_row * 2);
+    for (int j = 0; j < 4; ++j) {
+      const int slab = (wave + NW * j) * 8 * 64;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rG, &sB.s[0][slab], 16, dR[j], so, 0, 0);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rA1, &sB.s[1][slab], 16, dR[j], so, 0, 0);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rA2, &sB.s[2][slab], 16, dR[j], so, 0, 0);
+    }
+  };
+  auto dmaC = [&](int k0) {
+    const int so = k0 * 4;
 #pragma unroll
-      for (int j = 0; j < SL; ++j) {
-        const int slab = (wave + NW * j) * 16 * KC;
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(rG[p], &b.s[0][p][slab], 16, dg[j], k0 * 2, 0, 0);
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(rU, &b.s[1][p][slab], 16, du[j], k0 * 2, 0, 0);
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(rX[p], &b.s[3][p][slab], 16, dx[j], k0 * 2, 0, 0);
+    for (int j = 0; j < 4; ++j) {
+      const int slab = (wave + NW * j) * 8 * 64;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rX, &sC.s[0][slab], 16, dR[j], so, 0, 0);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rU1, &sC.s[1][slab], 16, dU[j], so, 0, 0);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rU2, &sC.s[2][slab], 16, dU[j], so, 0, 0);
+    }
+  };
+
+  // fragment (row r, plane p, k chunk lane / 16) at halves r * 64 + sw8(r, 4 p + lane / 16) * 8;
+  // sw8 depends on r mod 16 only, so the rows of tile t are 16 t * 64 halves further
+  const int lr = lane & 15, kc = lane >> 4;
+  const int rr = wr * 64 + lr, rc = wc * 64 + lr;
+  const int fr0 = rr * 64 + sw8(rr, kc) * 8, fr1 = rr * 64 + sw8(rr, 4 + kc) * 8;
+  const int fc0 = rc * 64 + sw8(rc, kc) * 8, fc1 = rc * 64 + sw8(rc, 4 + kc) * 8;
+  // fragments of one half stage: the shared operand s (G or GX) and the per-v
+  // operands m1, m2 (A_v or U_v), [plane][tile]
+  struct Frags { f16x8 s[2][4], m1[2][4], m2[2][4]; };
+  Frags fb, fc;
+  auto rd = [&](const _Float16* base, int off, int t) {
+    return *reinterpret_cast<const f16x8*>(base + off + t * 16 * 64);
+  };
+  auto readB = [&](Frags& fr) {   // G (R side), A_v1, A_v2 (P side)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      fr.s[0][t] = rd(sB.s[0], fr0, t);  fr.s[1][t] = rd(sB.s[0], fr1, t);
+      fr.m1[0][t] = rd(sB.s[1], fc0, t); fr.m1[1][t] = rd(sB.s[1], fc1, t);
+      fr.m2[0][t] = rd(sB.s[2], fc0, t); fr.m2[1][t] = rd(sB.s[2], fc1, t);
+    }
+  };
+  auto readC = [&](Frags& fr) {   // GX (P side), U_v1, U_v2 (R side)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      fr.s[0][t] = rd(sC.s[0], fc0, t);  fr.s[1][t] = rd(sC.s[0], fc1, t);
+      fr.m1[0][t] = rd(sC.s[1], fr0, t); fr.m1[1][t] = rd(sC.s[1], fr1, t);
+      fr.m2[0][t] = rd(sC.s[2], fr0, t); fr.m2[1][t] = rd(sC.s[2], fr1, t);
+    }
+  };
+
+  // accumulators [ti][tj]: rows R of tile ti, columns P of tile tj (cleared once
+  // here; each pair then starts them from zero inside its first MFMAs)
+  f4 B1[4][4], B2[4][4], C1[4][4], C2[4][4];
+  const f4 zero = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj) B1[ti][tj] = B2[ti][tj] = C1[ti][tj] = C2[ti][tj] = zero;
+  // B products: acc[ti][tj] += G[ti] . A_m[tj] (planes x1 y0 + x0 y1 + x0 y0)
+  auto mfmaB = [&](const Frags& fr, bool first) {
+#pragma unroll
+    for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 4; ++tj) {
+        f4 a1 = first ? zero : B1[ti][tj];
+        a1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(fr.s[1][ti], fr.m1[0][tj], a1, 0, 0, 0);
+        a1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(fr.s[0][ti], fr.m1[1][tj], a1, 0, 0, 0);
+        B1[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fr.s[0][ti], fr.m1[0][tj], a1, 0, 0, 0);
+        f4 a2 = first ? zero : B2[ti][tj];
+        a2 = __builtin_amdgcn_mfma_f32_16x16x32_f16(fr.s[1][ti], fr.m2[0][tj], a2, 0, 0, 0);
+        a2 = __builtin_amdgcn_mfma_f32_16x16x32_f16(fr.s[0][ti], fr.m2[1][tj], a2, 0, 0, 0);
+        B2[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fr.s[0][ti], fr.m2[0][tj], a2, 0, 0, 0);
       }
-    }
   };
-  // the FP32 A panel is staged through registers (1024 / NTH units of 4 floats
-  // per thread: row u/8, piece u%8, u = tid + NTH i) and split when written to LDS
-  constexpr int AU = 1024 / NTH;
-  uint32_t offa[AU];
-  int lda_[AU];
+  // C products: acc[ti][tj] += U_m[ti] . GX[tj]
+  auto mfmaC = [&](const Frags& fr, bool first) {
 #pragma unroll
-  for (int i = 0; i < AU; ++i) {
-    const int u = tid + i * NTH, row = u >> 3, c4 = u & 7;
-    offa[i] = row < rows_p ? (uint32_t)((row * ldk + 4 * c4) * 4) : OOB;
-    lda_[i] = row * KC + lds_chunk(row, c4 >> 1) * 8 + (c4 & 1) * 4;
-  }
-  f4 ra[AU];
-  auto fetch_a = [&](int v, int k0) {
-    const __amdgpu_buffer_rsrc_t rA = make_rsrc(A + (int64_t)v * a_v, (int64_t)TT * ldk * 4);
+    for (int ti = 0; ti < 4; ++ti)
 #pragma unroll
-    for (int i = 0; i < AU; ++i)
-      ra[i] = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(rA, offa[i], k0 * 4, 0));
-  };
-  auto put_a = [&](Buf& b) {
-#pragma unroll
-    for (int i = 0; i < AU; ++i) {
-      h4 hi, lo;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const float x = ra[i][e] * a_scale;
-        const _Float16 h = (_Float16)x;
-        hi[e] = h;
-        lo[e] = (_Float16)(x - (float)h);
+      for (int tj = 0; tj < 4; ++tj) {
+        f4 a1 = first ? zero : C1[ti][tj];
+        a1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(fr.m1[1][ti], fr.s[0][tj], a1, 0, 0, 0);
+        a1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(fr.m1[0][ti], fr.s[1][tj], a1, 0, 0, 0);
+        C1[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fr.m1[0][ti], fr.s[0][tj], a1, 0, 0, 0);
+        f4 a2 = first ? zero : C2[ti][tj];
+        a2 = __builtin_amdgcn_mfma_f32_16x16x32_f16(fr.m2[1][ti], fr.s[0][tj], a2, 0, 0, 0);
+        a2 = __builtin_amdgcn_mfma_f32_16x16x32_f16(fr.m2[0][ti], fr.s[1][tj], a2, 0, 0, 0);
+        C2[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fr.m2[0][ti], fr.s[0][tj], a2, 0, 0, 0);
       }
-      *reinterpret_cast<h4*>(&b.s[2][0][lda_[i]]) = hi;
-      *reinterpret_cast<h4*>(&b.s[2][1][lda_[i]]) = lo;
-    }
   };
 
-  // fragment reads: R side rows wr*64 + 16 ti, P side rows wc*64 + 16 tj
-  int fr_off[WBR], fc_off[WBP];
+  // the partial sum of D: slot (wave, tile) of each lane, 64 lanes x 16 bytes
+  f4* const Dw = sD + wave * 16 * 64 + lane;
+  auto dzero = [&]() {
 #pragma unroll
-  for (int t = 0; t < WBR; ++t) {
-    const int r = wr * 16 * WBR + 16 * t + (lane & 15);
-    fr_off[t] = r * KC + lds_chunk(r, lane >> 4) * 8;
-  }
-#pragma unroll
-  for (int t = 0; t < WBP; ++t) {
-    const int c = wc * 16 * WBP + 16 * t + (lane & 15);
-    fc_off[t] = c * KC + lds_chunk(c, lane >> 4) * 8;
-  }
-  struct Frags { f16x8 r[2][WBR], c[2][WBP]; };   // [plane][tile]
-  Frags fB, fC;
-  auto read_frags = [&](Frags& fr, const Buf& b, int pr, int pc) {
-#pragma unroll
-    for (int p = 0; p < 2; ++p) {
-#pragma unroll
-      for (int t = 0; t < WBR; ++t)
-        fr.r[p][t] = *reinterpret_cast<const f16x8*>(&b.s[pr][p][fr_off[t]]);
-#pragma unroll
-      for (int t = 0; t < WBP; ++t)
-        fr.c[p][t] = *reinterpret_cast<const f16x8*>(&b.s[pc][p][fc_off[t]]);
-    }
+    for (int t = 0; t < 16; ++t) Dw[t * 64] = zero;
   };
-
-  f4 accB[WBR][WBP], accC[WBR][WBP];
-  float accD[WBR][WBP][4];
+  auto dupdate = [&]() {
 #pragma unroll
-  for (int i = 0; i < WBR; ++i)
+    for (int ti = 0; ti < 4; ++ti)
 #pragma unroll
-    for (int j = 0; j < WBP; ++j)
+      for (int tj = 0; tj < 4; ++tj) {
+        f4 d = Dw[(ti * 4 + tj) * 64];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) accD[i][j][r] = 0.f;
-
-  // MFMA number q (0..47) of one product: tile (q / 3) of the 4 x 4, plane pair q % 3
-  constexpr int NQ = WBR * WBP * 3;   // MFMAs per product and stage
-  auto mfma_range = [&](f4 (&acc)[WBR][WBP], const Frags& fr, int q0, int q1) {
-#pragma unroll
-    for (int q = q0; q < q1; ++q) {
-      const int tile = q / 3, pp = q % 3;
-      const int ti = tile / WBP, tj = tile % WBP;
-      const int pa = pp == 0 ? 1 : 0, pb = pp == 1 ? 1 : 0;
-      acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fr.r[pa][ti], fr.c[pb][tj],
-                                                           acc[ti][tj], 0, 0, 0);
-    }
+        for (int r = 0; r < 4; ++r) {
+          d[r] = fmaf(B1[ti][tj][r], C1[ti][tj][r], d[r]);
+          d[r] = fmaf(B2[ti][tj][r], C2[ti][tj][r], d[r]);
+        }
+        Dw[(ti * 4 + tj) * 64] = d;
+      }
   };
-
-  // this lane's first element of D: row R0 + wr*64 + 4*(lane/16), column P0 + wc*64 + lane%16
-  const int Rl = R0 + wr * 16 * WBR + 4 * (lane >> 4), Pl = P0 + wc * 16 * WBP + (lane & 15);
-  const int64_t dl_off = (int64_t)z * f.naux * f.naux + (int64_t)Rl * f.naux + Pl;
-  double* const Dl = f.Dpart + dl_off;
-  float* const Dl32 = reinterpret_cast<float*>(f.Dpart) + dl_off;
+  // D tile -> partial tile z (FP32 store, or FP64 add unless first): thread t
+  // takes column P0 + t % 128 and rows R0 + t / 128 + 2 i, reading each element
+  // from the LDS slot of the lane that formed it (lane 16 (R % 16 / 4) + P % 16
+  // of wave 2 (R / 64) + P / 64, tile (R % 64 / 16, P % 64 / 16), element R % 4),
+  // so the global writes are coalesced rows.  Barriers before (other waves'
+  // slots) and after (the slots may be cleared next).
   auto flush = [&](bool first) {
-#pragma unroll
-    for (int ti = 0; ti < WBR; ++ti)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const bool row_ok = Rl + 16 * ti + r < f.naux;
-#pragma unroll
-        for (int tj = 0; tj < WBP; ++tj) {
-          if (row_ok && Pl + 16 * tj < f.naux) {
-            if (f.dpart_f32) {   // one range = one FP32 partial sum (first is true)
-              Dl32[(16 * ti + r) * f.naux + 16 * tj] = accD[ti][tj][r];
-            } else {
-              double* d = Dl + (16 * ti + r) * f.naux + 16 * tj;
-              *d = (first ? 0.0 : *d) + (double)accD[ti][tj][r];
-            }
-          }
-          accD[ti][tj][r] = 0.f;
+    __syncthreads();
+    const float* sDf = reinterpret_cast<const float*>(sD);
+    const int Pt = tid & (TT - 1), P = P0 + Pt;
+    const int pslot = (Pt >> 6) * 16 * 64 + ((Pt >> 4) & 3) * 64 + (Pt & 15);
+    const int64_t zo = (int64_t)z * naux * naux + P;
+    for (int Rt = tid >> 7; Rt < TT; Rt += NTH / TT) {
+      const int R = R0 + Rt;
+      if (R < naux && P < naux) {
+        const int slot = pslot + (Rt >> 6) * 2 * 16 * 64 + ((Rt >> 4) & 3) * 4 * 64 + ((Rt >> 2) & 3) * 16;
+        const float v = sDf[slot * 4 + (Rt & 3)];
+        const int64_t o = zo + (int64_t)R * naux;
+        if (f.dpart_f32) {   // one range = one FP32 partial sum (first is true)
+          reinterpret_cast<float*>(f.Dpart)[o] = v;
+        } else {
+          f.Dpart[o] = (first ? 0.0 : f.Dpart[o]) + (double)v;
         }
       }
-  };
-
-  // next stage to fetch, clamped to the last one
-  int lv = v_lo, lk = 0;
-  auto advance = [&]() {
-    const bool last = (lv == v_hi - 1) && (lk == kst - 1);
-    const bool wrap = (lk == kst - 1);
-    lk = last ? lk : (wrap ? 0 : lk + 1);
-    lv = last ? lv : (wrap ? lv + 1 : lv);
-  };
-
-  if (nstage > 0) {
-    dma(sb0, lv, lk * KC);
-    fetch_a(lv, lk * KC);
-    advance();
-    put_a(sb0);
-    dma(sb1, lv, lk * KC);
-    fetch_a(lv, lk * KC);
-    advance();
-    vm_lds_barrier();
-    read_frags(fB, sb0, 0, 2);
-  }
-  // one stage; `cur` holds stage t, `nxt` receives stage t+1 (already loading)
-  auto stage = [&](Buf& cur, Buf& nxt) {
-    // phase 1: C fragments of stage t; B product
-    read_frags(fC, cur, 1, 3);
-    mfma_range(accB, fB, 0, 2 * NQ / 3);
-    // phase 2: A of stage t+1 into the other buffer; C product starts
-    mfma_range(accB, fB, 2 * NQ / 3, NQ);
-    put_a(nxt);
-    mfma_range(accC, fC, 0, NQ / 3);
-    // stage t+1 complete in LDS (its memory-to-LDS loads were issued one phase 3 ago)
-    vm_lds_barrier();
-    // phase 3: B fragments of stage t+1; stage t+2 loads into this buffer
-    read_frags(fB, nxt, 0, 2);
-    dma(cur, lv, lk * KC);
-    fetch_a(lv, lk * KC);
-    advance();
-    mfma_range(accC, fC, NQ / 3, NQ);
-  };
-  int nv = 0;
-  for (int v = v_lo; v < v_hi; ++v) {
-#pragma unroll
-    for (int i = 0; i < WBR; ++i)
-#pragma unroll
-      for (int j = 0; j < WBP; ++j) {
-        accB[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-        accC[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-      }
-    // kst is even, so every v starts on buffer 0
-    for (int ks = 0; ks < kst; ks += 2) {
-      stage(sb0, sb1);
-      stage(sb1, sb0);
     }
-#pragma unroll
-    for (int i = 0; i < WBR; ++i)
-#pragma unroll
-      for (int j = 0; j < WBP; ++j)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) accD[i][j][r] = fmaf(accB[i][j][r], accC[i][j][r], accD[i][j][r]);
-    ++nv;
-    if ((nv % FLUSH16 == 0) && v + 1 < v_hi) flush(nv == FLUSH16);
+    __syncthreads();
+  };
+
+  dzero();
+  // fetch cursor over (pair, chunk), clamped to the last chunk
+  int cp = 0, ck = 0;
+  auto advance = [&]() {
+    const bool last = (cp == npr - 1) && (ck == kst - 1);
+    const bool wrap = (ck == kst - 1);
+    ck = last ? ck : (wrap ? 0 : ck + 1);
+    if (wrap && !last) set_pair(++cp);
+  };
+  if (npr > 0) {
+    set_pair(0);
+    dmaB(0);
+    dmaC(0);
+    advance();
+    vm_lds_barrier();
+    readB(fb);
+  }
+  auto chunk = [&](bool first) {
+    vm_lds_barrier();
+    dmaB(ck * KC);
+    readC(fc);
+    mfmaB(fb, first);
+    vm_lds_barrier();
+    dmaC(ck * KC);
+    advance();
+    readB(fb);
+    mfmaC(fc, first);
+  };
+  int done = 0;
+  for (int pr = 0; pr < npr; ++pr) {
+    chunk(true);
+    for (int k = 1; k < kst; ++k) chunk(false);
+    dupdate();
+    ++done;
+    if (done % FLUSH_PAIRS == 0 && pr + 1 < npr) {
+      flush(done == FLUSH_PAIRS);
+      dzero();
+    }
   }
   // the last (repeated) memory-to-LDS loads land before the workgroup may end
   __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  flush(nv <= FLUSH16);   // also writes zeros for an empty v range
+  flush(done <= FLUSH_PAIRS);   // also writes zeros for an empty range
 }
 
 inline unsigned cdiv16(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
@@ -323,13 +333,13 @@ void fused_f16_tile(int* rows, int* cols) {
 }
 
 hipError_t sox_fused_f16(const FusedArgs& f, hipStream_t s) {
-  if (!f.a_f32 || f.vsplit % NXCD16 != 0 || (int64_t)f.vsplit * f.vchunk < f.n ||
-      (f.dpart_f32 && f.vchunk > FLUSH16) ||
-      f.ldk % (2 * KC) != 0)
+  const int npair = (f.n + 1) / 2;
+  const int pairs_max = (npair + f.vsplit - 1) / f.vsplit;   // longest pair range
+  if (f.a_f32 || f.vsplit % NXCD16 != 0 || f.ldk % KC != 0 || f.ldk < f.n ||
+      (f.dpart_f32 && pairs_max > FLUSH_PAIRS))
     return hipErrorInvalidValue;
-  // buffer offsets inside one tile's rows of U (fp16) and A (FP32) are 32-bit
-  if ((int64_t)TT * f.n * f.ldk * 2 > 0x7fffffffLL || (int64_t)TT * f.ldk * 4 > 0x7fffffffLL)
-    return hipErrorInvalidValue;
+  // buffer offsets inside one tile's rows of U (c32 rows of 4 ldk bytes) are 32-bit
+  if ((int64_t)TT * f.n * f.ldk * 4 > 0x7fffffffLL) return hipErrorInvalidValue;
   const unsigned nb = cdiv16(f.naux, TT);
   fused_f16_kernel<<<dim3(nb * nb * f.vsplit), NTH, 0, s>>>(f);
   return hipGetLastError();

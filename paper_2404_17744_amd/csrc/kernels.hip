@@ -165,9 +165,54 @@ __global__ __launch_bounds__(NT) void split_kernel(SplitArgs a) {
     }
     T o[NP];
     Split<M>::run(x, o);
+    if (a.c32) {   // planes interleaved per 32-wide chunk
 #pragma unroll
-    for (int p = 0; p < NP; ++p) dst[p * a.d_plane + dof + c] = o[p];
+      for (int p = 0; p < NP; ++p) dst[dof + (c >> 5) * 64 + 32 * p + (c & 31)] = o[p];
+    } else {
+#pragma unroll
+      for (int p = 0; p < NP; ++p) dst[p * a.d_plane + dof + c] = o[p];
+    }
   }
+}
+
+// out = max over rows r < rows of sum_{c < len} x[r ld + c]^2 (max-reduced, bits)
+__global__ __launch_bounds__(NT) void rownorm2_kernel(const double* x, int64_t rows, int len,
+                                                      int64_t ld, unsigned long long* out) {
+  double m = 0.0;
+  for (int64_t r = (int64_t)blockIdx.x * NT + threadIdx.x; r < rows; r += (int64_t)gridDim.x * NT) {
+    const double* xr = x + r * ld;
+    double s = 0.0;
+    for (int c = 0; c < len; ++c) s = fma(xr[c], xr[c], s);
+    m = fmax(m, s);
+  }
+  block_atomic_max<NT / 64>(m, out);
+}
+
+// out[b] = max over columns v < n of sum_{s < n} G_b[s n + v]^2, G_b = G + b stride
+__global__ __launch_bounds__(NT) void colnorm2_kernel(const double* G, int n, int64_t stride,
+                                                      unsigned long long* out) {
+  const double* g = G + (int64_t)blockIdx.x * stride;
+  double m = 0.0;
+  for (int v = threadIdx.x; v < n; v += NT) {
+    double s = 0.0;
+    for (int r = 0; r < n; ++r) s = fma(g[(int64_t)r * n + v], g[(int64_t)r * n + v], s);
+    m = fmax(m, s);
+  }
+  block_atomic_max<NT / 64>(m, out + blockIdx.x);
+}
+
+// amax_a[b] = bound_b * 2^-14, bound_b = (1 + 2^-10) |U row|max su |Gb row|max(b) sg(b):
+// by Cauchy-Schwarz |A| <= bound_b for A formed from the scaled planes.
+__global__ void ascale_kernel(const unsigned long long* unorm2, const unsigned long long* amax_u,
+                              const unsigned long long* gnorm2, const unsigned long long* amax_gb,
+                              int64_t gb_stride, int nb, unsigned long long* amax_a) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  const double un = sqrt(__longlong_as_double((long long)*unorm2));
+  const double gn = sqrt(__longlong_as_double((long long)gnorm2[b]));
+  const double bound = (1.0 + 0x1p-10) * un * pow2_scale(amax_u) * gn *
+                       pow2_scale(amax_gb + (int64_t)b * gb_stride);
+  amax_a[b] = (unsigned long long)__double_as_longlong(bound * 0x1p-14);
 }
 
 __global__ __launch_bounds__(NT) void absmax_kernel(const double* x, int64_t len, int64_t stride,
@@ -408,6 +453,30 @@ hipError_t absmax64(const double* x, int64_t len, int64_t stride, int batch,
   unsigned bx = cdiv(len, NT);
   if (bx > 64) bx = 64;
   absmax_kernel<<<dim3(bx, batch), NT, 0, s>>>(x, len, stride, amax);
+  return hipGetLastError();
+}
+
+hipError_t rownorm2_max(const double* x, int64_t rows, int len, int64_t ld,
+                        unsigned long long* out, hipStream_t s) {
+  if (rows <= 0 || len <= 0) return hipSuccess;
+  unsigned b = cdiv(rows, NT);
+  if (b > 1024) b = 1024;
+  rownorm2_kernel<<<b, NT, 0, s>>>(x, rows, len, ld, out);
+  return hipGetLastError();
+}
+
+hipError_t colnorm2_max(const double* G, int n, int64_t stride, int nb, unsigned long long* out,
+                        hipStream_t s) {
+  if (nb <= 0 || n <= 0) return hipSuccess;
+  colnorm2_kernel<<<nb, NT, 0, s>>>(G, n, stride, out);
+  return hipGetLastError();
+}
+
+hipError_t ascale_bound(const unsigned long long* unorm2, const unsigned long long* amax_u,
+                        const unsigned long long* gnorm2, const unsigned long long* amax_gb,
+                        int64_t gb_stride, int nb, unsigned long long* amax_a, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  ascale_kernel<<<cdiv(nb, 64), 64, 0, s>>>(unorm2, amax_u, gnorm2, amax_gb, gb_stride, nb, amax_a);
   return hipGetLastError();
 }
 

@@ -36,23 +36,28 @@ struct GemmKArgs {
 };
 hipError_t gemm_kmajor(int mode, bool out_f64, const GemmKArgs& g, hipStream_t s);
 // The A stage of the fp16x2 mode for nsets tau points at once:
-//   A[set][v][P][q] = sum_s U[P][q][s] Gb[set][v][s]   (q < n; rows n <= q < ldk get 0)
-// U: fp16 planes [naux][n][ldk]; Gb: fp16 planes [set][n][ldk] (G(beta - tau)^T);
-// A: FP32 [set][n][naux][ldk]; amax[set] (may be NULL): max |A| of each set,
-// max-reduced as the bits of a non-negative double.  ldk must be a multiple of 64.
+//   A[set][v][P][q] = scale[set] * sum_s U[P][q][s] Gb[set][v][s]   (q < n; rows n <= q < ldk get 0)
+// All operands are fp16 planes in the c32 layout (row r, plane p, k at
+// r * 2 ldk + (k / 32) * 64 + 32 p + k % 32): U rows (P, q), Gb rows (set, v)
+// (G(beta - tau)^T, gb_set = n * 2 ldk halves apart), A rows (set, v, P) with
+// k = q (a_set halves apart).  scale[set] = 2^-ilogb(amax[set]); amax[set] must
+// bound max |A| / 2^14 (see ascale_bound).  ldk must be a multiple of 64.
 struct AStageArgs {
   int naux, n, ldk, nsets;
-  const void* U; int64_t u_plane;
-  const void* Gb; int64_t gb_plane, gb_set;
-  float* A; int64_t a_set;
-  unsigned long long* amax;
+  const void* U;
+  const void* Gb; int64_t gb_set;
+  _Float16* A; int64_t a_set;
+  const unsigned long long* amax;
 };
 hipError_t astage_f16(const AStageArgs& a, hipStream_t s);
 
 // The fused B/C/D stage for one tau point (v split over grid.z):
 //   Dpart[z][R][P] = sum_{v in split z} (sum_q Gt[R][q] A[v][P][q]) (sum_w U[R][v][w] GXt[P][w])
 // With a_f32, A is an FP32 array [n][naux][ldk] split into the mode's planes on
-// the fly after scaling by the power of two taken from *amax_a.
+// the fly after scaling by the power of two taken from *amax_a.  In the fp16x2
+// mode every operand (A included, already scaled) is in the c32 layout, the
+// plane strides are unused, and the v split counts pairs of v: split z covers
+// the pairs [z' np / vsplit, (z' + 1) np / vsplit) (np = ceil(n / 2)).
 struct FusedArgs {
   int n, naux, ldk, vsplit, vchunk;
   const void* Gt; const void* GXt; int64_t g_plane;   // [naux][ldk] planes
@@ -81,11 +86,14 @@ int fused_xcds();   // vsplit must be a multiple of this (one v range per XCD in
 // two 2^-floor(log2(amax[r2 * amax_s2])) (scale 1 if amax is null or zero):
 //   src(r1,r2,c) = src[r1*s1 + r2*s2 + c*sc],  dst plane p:
 //   dst[p*d_plane + r1*d1 + r2*d2 + c] for c < cols, zero for cols <= c < ldk.
+// With c32 (fp16x2 only) the planes are interleaved per 32-wide chunk instead:
+//   element c of plane p at dst[r1*d1 + r2*d2 + (c / 32) * 64 + 32 p + c % 32].
 struct SplitArgs {
   int rows1, rows2, cols, ldk;
   const void* src; bool src_f32; int64_t s1, s2, sc;
   void* dst; int64_t d1, d2, d_plane;
   const unsigned long long* amax; int64_t amax_s2;
+  bool c32;
 };
 hipError_t split_planes(int mode, const SplitArgs& a, hipStream_t s);
 
@@ -93,6 +101,22 @@ hipError_t split_planes(int mode, const SplitArgs& a, hipStream_t s);
 hipError_t absmax64(const double* x, int64_t len, int64_t stride, int batch,
                     unsigned long long* amax, hipStream_t s);
 hipError_t fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);
+// *out = max over rows r < rows of sum_{c < len} x[r ld + c]^2 (max-reduced, bits;
+// *out must hold 0 or an earlier maximum).
+hipError_t rownorm2_max(const double* x, int64_t rows, int len, int64_t ld,
+                        unsigned long long* out, hipStream_t s);
+// out[b] = max over columns v of sum_s G_b[s][v]^2 for the n x n matrices
+// G_b = G + b stride, b < nb (stride may be negative; out zeroed by the caller).
+hipError_t colnorm2_max(const double* G, int n, int64_t stride, int nb, unsigned long long* out,
+                        hipStream_t s);
+// The A-stage scale of the fp16x2 mode, before A exists: for b < nb,
+//   amax_a[b] = 2^-14 (1 + 2^-10) sqrt(*unorm2) su sqrt(gnorm2[b]) sg_b
+// with su = 2^-ilogb(*amax_u), sg_b = 2^-ilogb(amax_gb[b gb_stride]): unorm2 and
+// gnorm2 are the largest squared row norms of U and of G(beta - tau)^T, so by
+// Cauchy-Schwarz the scale 2^-ilogb(amax_a[b]) keeps every |A| below 2^15.
+hipError_t ascale_bound(const unsigned long long* unorm2, const unsigned long long* amax_u,
+                        const unsigned long long* gnorm2, const unsigned long long* amax_gb,
+                        int64_t gb_stride, int nb, unsigned long long* amax_a, hipStream_t s);
 
 // Sthc[R][P] = -factor * sum_z Dpart[z][R][P], factor = product of the inverse
 // operand scales (see scale_factor in the kernel source).

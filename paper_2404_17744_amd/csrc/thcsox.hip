@@ -134,17 +134,21 @@ struct thcsox_plan_s {
   double2* Am = nullptr;
   int* gj = nullptr;        // [2 naux + 1]: pivots, permutation, flag
   double* w = nullptr;      // [m]
-  void* U = nullptr;        // planes of [naux][n][ldk]
+  void* U = nullptr;        // planes of [naux][n][ldk] (fp16x2: c32 rows [naux][n])
   int64_t u_plane = 0;
-  void* A = nullptr;        // planes of [n][naux][ldk]
+  void* A = nullptr;        // planes of [n][naux][ldk] (fp16x2: [a_sets] c32 rows [n][naux])
   int64_t a_plane = 0;
-  float* A32 = nullptr;     // [a_sets][n][naux][ldk], split modes only
+  float* A32 = nullptr;     // [n][naux][ldk], bf16x3 only
   int a_sets = 1;           // tau points per A-stage launch (fp16x2: 2 while A is small)
+  // fp16x2: the largest squared row norms of U ([0]) and of the screened core's
+  // U ([1]), and of G(beta - tau)^T for each tau of a batch ([2 ..]): the A
+  // stage's scale is taken from their product before A is formed
+  unsigned long long* norm2 = nullptr;
   int tb = 1;               // tau points per projection / back-projection batch
-  void* Gt = nullptr;       // planes of [tb][naux][ldk]
+  void* Gt = nullptr;       // planes of [tb][naux][ldk] (fp16x2: c32 rows [tb][naux])
   void* GX = nullptr;
   int64_t g_plane = 0;
-  void* Gb = nullptr;       // planes of [tb][n][ldk]: G(beta - tau)^T
+  void* Gb = nullptr;       // planes of [tb][n][ldk]: G(beta - tau)^T (fp16x2: c32 rows)
   int64_t gb_plane = 0;
   double* Gt64 = nullptr;   // [tb][naux][n]
   double* GX64 = nullptr;   // [tb][naux][n]
@@ -226,8 +230,10 @@ namespace {
 
 // U_Pqs = sum_Q V_PQ X_qQ X_sQ in FP64, chunked over q, stored in the operand
 // planes Uout (the plan's U, or the second U of a screened core).  Split modes
-// first take max|U| into *amax_slot (pass 0), then store (pass 1).
-int build_u(thcsox_plan_s* p, const double* V, void* Uout, unsigned long long* amax_slot) {
+// first take max|U| into *amax_slot (pass 0; fp16x2 also the largest squared row
+// norm into *norm_slot), then store (pass 1).
+int build_u(thcsox_plan_s* p, const double* V, void* Uout, unsigned long long* amax_slot,
+            unsigned long long* norm_slot) {
   const int n = p->n, naux = p->naux, ldk = p->ldk;
   const hipStream_t s = p->stream;
   size_t per_q = (size_t)n * naux * sizeof(double);
@@ -237,6 +243,9 @@ int build_u(thcsox_plan_s* p, const double* V, void* Uout, unsigned long long* a
   double* Uc = nullptr;
   if (p->mode != MODE_F64) TRY(p->alloc(&Uc, (size_t)qb * n * naux));
   HIP_TRY(fill_u64(amax_slot, 1, 0ull, s));
+  const bool c32 = p->mode == MODE_F16X2;
+  if (c32) HIP_TRY(fill_u64(norm_slot, 1, 0ull, s));
+  const int64_t lrow = c32 ? 2 * (int64_t)ldk : ldk;   // elements per operand row
   const int passes = p->mode == MODE_F64 ? 1 : 2;
   for (int pass = 0; pass < passes; ++pass) {
     for (int q0 = 0; q0 < n; q0 += qb) {
@@ -256,13 +265,15 @@ int build_u(thcsox_plan_s* p, const double* V, void* Uout, unsigned long long* a
       if (p->mode == MODE_F64) continue;
       if (pass == 0) {
         HIP_TRY(absmax64(Uc, (int64_t)naux * qc * n, 0, 1, amax_slot, s));
+        // rows (P, q) of the chunk are the consecutive n-element rows of Uc
+        if (c32) HIP_TRY(rownorm2_max(Uc, (int64_t)naux * qc, n, n, norm_slot, s));
       } else {
         SplitArgs a{};
         a.rows1 = naux; a.rows2 = qc; a.cols = n; a.ldk = ldk;
         a.src = Uc; a.src_f32 = false; a.s1 = (int64_t)qc * n; a.s2 = n; a.sc = 1;
-        a.dst = static_cast<char*>(Uout) + (size_t)q0 * ldk * p->esize;
-        a.d1 = (int64_t)n * ldk; a.d2 = ldk; a.d_plane = p->u_plane;
-        a.amax = amax_slot;
+        a.dst = static_cast<char*>(Uout) + (size_t)q0 * lrow * p->esize;
+        a.d1 = (int64_t)n * lrow; a.d2 = lrow; a.d_plane = p->u_plane;
+        a.amax = amax_slot; a.c32 = c32;
         HIP_TRY(split_planes(p->mode, a, s));
       }
     }
@@ -307,6 +318,7 @@ int backproject_batch(thcsox_plan_s* p, const double* St, int64_t st_stride, dou
 struct Cores {
   const void* UA; const unsigned long long* amaxA;
   const void* UC; const unsigned long long* amaxC;
+  const unsigned long long* normA;   // fp16x2: largest squared row norm of UA
 };
 
 // Tau points k0 <= k < k1 (k1 - k0 <= tb): Sigma[k] (and Sig_thc[k]) from G,
@@ -339,19 +351,31 @@ int sigma_batch(thcsox_plan_s* p, const double* G, double* Sigma, double* Sthc_o
   HIP_TRY(absmax64(p->Gt64, an, an, nb, p->am_gt() + k0, s));
   HIP_TRY(absmax64(p->GX64, an, an, nb, p->am_gx() + k0, s));
 
+  // fp16x2 keeps the two planes of each 32-wide chunk together (c32 rows of 2 ldk)
+  const bool c32 = mode == MODE_F16X2;
+  const int64_t lrow = c32 ? 2 * (int64_t)ldk : ldk;
   SplitArgs sa{};
   sa.rows1 = naux; sa.rows2 = nb; sa.cols = n; sa.ldk = ldk;
   sa.src_f32 = false; sa.s1 = n; sa.s2 = an; sa.sc = 1;
-  sa.d1 = ldk; sa.d2 = (int64_t)naux * ldk; sa.d_plane = p->g_plane;
+  sa.d1 = lrow; sa.d2 = (int64_t)naux * lrow; sa.d_plane = p->g_plane; sa.c32 = c32;
   sa.src = p->Gt64; sa.dst = p->Gt; sa.amax = p->am_gt() + k0; sa.amax_s2 = 1;
   HIP_TRY(split_planes(mode, sa, s));
   sa.src = p->GX64; sa.dst = p->GX; sa.amax = p->am_gx() + k0;
   HIP_TRY(split_planes(mode, sa, s));
   // G(beta - tau)^T of each tau of the batch: row v holds G[m-1-k][s][v] over s
   sa.rows1 = n; sa.src = G + (int64_t)(m - 1 - k0) * nn; sa.s1 = 1; sa.s2 = -nn; sa.sc = n;
-  sa.d2 = (int64_t)n * ldk; sa.dst = p->Gb; sa.d_plane = p->gb_plane;
+  sa.d2 = (int64_t)n * lrow; sa.dst = p->Gb; sa.d_plane = p->gb_plane;
   sa.amax = p->am_g() + (m - 1 - k0); sa.amax_s2 = -1;
   HIP_TRY(split_planes(mode, sa, s));
+  if (c32) {
+    // the A stage's scale for each tau of the batch, from the row norms of U and
+    // of G(beta - tau)^T (the columns of G(beta - tau))
+    unsigned long long* gn = p->norm2 + 2;
+    HIP_TRY(fill_u64(gn, nb, 0ull, s));
+    HIP_TRY(colnorm2_max(G + (int64_t)(m - 1 - k0) * nn, n, -nn, nb, gn, s));
+    HIP_TRY(ascale_bound(cores.normA, cores.amaxA, gn, p->am_g() + (m - 1 - k0), -1, nb,
+                         p->am_a() + k0, s));
+  }
   HIP_TRY(p->mark(THCSOX_STAGE_PROJECT, false));
 
   const bool split_a = (mode == MODE_BF16X3 || mode == MODE_F16X2);
@@ -359,17 +383,18 @@ int sigma_batch(thcsox_plan_s* p, const double* G, double* Sigma, double* Sthc_o
     const int k = k0 + b, kb = m - 1 - k;
     const int* sym = same_core && p->sym_mode == THCSOX_SYM_AUTO ? p->symflag + k : nullptr;
     // A[v][P][q] = sum_s U[P][q][s] G(beta - tau)[s][v]: rows (P,q) of U against rows v of Gb
-    // (fp16x2: for up to a_sets tau points at once, into A32 set b % a_sets)
+    // (fp16x2: for up to a_sets tau points at once, into set b % a_sets of A)
     const int aset = mode == MODE_F16X2 ? b % p->a_sets : 0;
+    const int64_t a_set = (int64_t)n * naux * lrow;   // fp16x2: halves per set of A
     if (aset == 0) {
       HIP_TRY(p->mark(THCSOX_STAGE_A, true));
       if (mode == MODE_F16X2) {
         AStageArgs ast{};
         ast.naux = naux; ast.n = n; ast.ldk = ldk; ast.nsets = std::min(p->a_sets, nb - b);
-        ast.U = cores.UA; ast.u_plane = p->u_plane;
-        ast.Gb = static_cast<const char*>(p->Gb) + (size_t)b * n * ldk * es;
-        ast.gb_plane = p->gb_plane; ast.gb_set = (int64_t)n * ldk;
-        ast.A = p->A32; ast.a_set = p->a_plane;
+        ast.U = cores.UA;
+        ast.Gb = static_cast<const char*>(p->Gb) + (size_t)b * n * lrow * es;
+        ast.gb_set = (int64_t)n * lrow;
+        ast.A = static_cast<_Float16*>(p->A); ast.a_set = a_set;
         ast.amax = p->am_a() + k;
         HIP_TRY(astage_f16(ast, s));
       } else {
@@ -390,13 +415,19 @@ int sigma_batch(thcsox_plan_s* p, const double* G, double* Sigma, double* Sthc_o
 
     FusedArgs f{};
     f.n = n; f.naux = naux; f.ldk = ldk; f.vsplit = p->vsplit; f.vchunk = p->vchunk;
-    f.Gt = static_cast<const char*>(p->Gt) + (size_t)b * naux * ldk * es;
-    f.GXt = static_cast<const char*>(p->GX) + (size_t)b * naux * ldk * es;
+    f.Gt = static_cast<const char*>(p->Gt) + (size_t)b * naux * lrow * es;
+    f.GXt = static_cast<const char*>(p->GX) + (size_t)b * naux * lrow * es;
     f.g_plane = p->g_plane;
     f.U = cores.UC; f.u_plane = p->u_plane;
-    f.A = split_a ? static_cast<const void*>(p->A32 + aset * p->a_plane) : p->A;
+    if (c32) {   // A already split and scaled by the A stage
+      f.A = static_cast<const _Float16*>(p->A) + aset * a_set;
+      f.a_f32 = false;
+    } else {
+      f.A = split_a ? static_cast<const void*>(p->A32) : p->A;
+      f.a_f32 = split_a;
+    }
     f.a_plane = p->a_plane;
-    f.a_f32 = split_a; f.amax_a = split_a ? p->am_a() + k : nullptr;
+    f.amax_a = split_a ? p->am_a() + k : nullptr;
     f.Dpart = p->Dpart; f.dpart_f32 = p->dpart_f32;
     f.sym = sym;
     HIP_TRY(p->mark(THCSOX_STAGE_FUSED, true));
@@ -534,7 +565,8 @@ int thcsox_plan(thcsox_plan_t* out, int n, int naux, int ntau, double beta,
     fused_tile(precision, &TR, &TP);
     auto fits = [&](int64_t nn) {
       const int64_t l = precision == THCSOX_FP16X2 ? (nn + 63) / 64 * 64 : (nn + 31) / 32 * 32;
-      const int64_t es = precision == THCSOX_FP16X2 ? 2 : 8;
+      // bytes per k of an operand row: FP64 8; fp16x2 4 (both planes in one c32 row)
+      const int64_t es = precision == THCSOX_FP16X2 ? 4 : 8;
       // in double: exact near the bound, and no wrap-around for huge n
       return (double)std::max(TR, TP) * (double)nn * (double)l * (double)es <= 2147483647.0;
     };
@@ -598,7 +630,9 @@ int thcsox_plan(thcsox_plan_t* out, int n, int naux, int ntau, double beta,
     const long tiles = (long)((naux + TR - 1) / TR) * ((naux + TP - 1) / TP);
     int best = nx;
     double best_eff = -1.0;
-    for (int vs = nx; vs <= std::max(nx, std::min(8 * nx, n)); vs += nx) {
+    // the fp16x2 kernel takes v in pairs and splits the pairs
+    const int nv = precision == THCSOX_FP16X2 ? (n + 1) / 2 : n;
+    for (int vs = nx; vs <= std::max(nx, std::min(8 * nx, nv)); vs += nx) {
       const long wg = tiles * (vs / nx);                 // workgroups per XCD
       const long rounds = (wg + per_xcd - 1) / per_xcd;
       double eff = (double)wg / (double)(rounds * per_xcd);
@@ -612,14 +646,16 @@ int thcsox_plan(thcsox_plan_t* out, int n, int naux, int ntau, double beta,
     // n = 300, naux = 1800: 2-4 % faster than the balance choice above, full
     // and symmetric paths).
     if (precision != THCSOX_FP64) {
-      const int vs8 = ((n + 7) / 8 + nx - 1) / nx * nx;
+      const int per = precision == THCSOX_FP16X2 ? 4 : 8;   // pairs or v per range
+      const int vs8 = ((nv + per - 1) / per + nx - 1) / nx * nx;
       const double dbytes = 4.0 * vs8 * (double)naux * naux;   // FP32 partial tiles
       const bool fits = dbytes <= 2.0e9 &&
                         (workspace_limit == 0 || dbytes <= 0.25 * (double)workspace_limit);
       if (fits && vs8 > best) best = vs8;
     }
     p->vsplit = best;
-    p->vchunk = (n + best - 1) / best;   // longest v range (ranges are balanced over the XCDs)
+    // longest v range (ranges are balanced over the XCDs)
+    p->vchunk = precision == THCSOX_FP16X2 ? 2 * ((nv + best - 1) / best) : (n + best - 1) / best;
     // ranges of at most 8 v are one FP32 partial sum each: store them as FP32
     p->dpart_f32 = precision != THCSOX_FP64 && p->vchunk <= 8;
   }
@@ -664,12 +700,14 @@ int thcsox_plan(thcsox_plan_t* out, int n, int naux, int ntau, double beta,
   if ((rc = p->alloc(&p->E, 1))) return bail(rc);
   if ((rc = p->alloc(&tmp, np * es * (size_t)p->u_plane))) return bail(rc);
   p->U = tmp;
-  if (precision == THCSOX_BF16X3 || precision == THCSOX_FP16X2) {
-    if ((rc = p->alloc(&p->A32, (size_t)p->a_sets * p->a_plane))) return bail(rc);
+  if (precision == THCSOX_BF16X3) {
+    if ((rc = p->alloc(&p->A32, (size_t)p->a_plane))) return bail(rc);
   } else {
-    if ((rc = p->alloc(&tmp, np * es * (size_t)p->a_plane))) return bail(rc);
+    if ((rc = p->alloc(&tmp, np * es * (size_t)p->a_sets * p->a_plane))) return bail(rc);
     p->A = tmp;
   }
+  if (precision == THCSOX_FP16X2 && (rc = p->alloc(&p->norm2, (size_t)2 + p->tb)))
+    return bail(rc);
   if ((rc = p->alloc(&tmp, np * es * (size_t)p->g_plane))) return bail(rc);
   p->Gt = tmp;
   if ((rc = p->alloc(&tmp, np * es * (size_t)p->g_plane))) return bail(rc);
@@ -697,17 +735,17 @@ int thcsox_plan(thcsox_plan_t* out, int n, int naux, int ntau, double beta,
     return hip_bail(e, "copy weights");
   // zero the operand pads once (stages only ever write the first n of ldk columns)
   if ((e = hipMemsetAsync(p->U, 0, np * es * (size_t)p->u_plane, s))) return hip_bail(e, "zero U");
-  if (p->A && (e = hipMemsetAsync(p->A, 0, np * es * (size_t)p->a_plane, s)))
+  if (p->A && (e = hipMemsetAsync(p->A, 0, np * es * (size_t)p->a_sets * p->a_plane, s)))
     return hip_bail(e, "zero A");
   if ((e = hipMemsetAsync(p->symflag, 0, sizeof(int) * (size_t)ntau, s)))
     return hip_bail(e, "zero flags");
-  if (p->A32 && (e = hipMemsetAsync(p->A32, 0, sizeof(float) * p->a_sets * (size_t)p->a_plane, s)))
+  if (p->A32 && (e = hipMemsetAsync(p->A32, 0, sizeof(float) * (size_t)p->a_plane, s)))
     return hip_bail(e, "zero A32");
   if ((rc = p->alloc(&p->V, (size_t)naux * naux))) return bail(rc);
   if ((e = hipMemcpyAsync(p->V, V_dev, sizeof(double) * (size_t)naux * naux,
                           hipMemcpyDeviceToDevice, s)))
     return hip_bail(e, "copy V");
-  if ((rc = build_u(p, V_dev, p->U, p->amax))) return bail(rc);
+  if ((rc = build_u(p, V_dev, p->U, p->amax, p->norm2))) return bail(rc);
   if ((e = hipStreamSynchronize(s))) return hip_bail(e, "plan synchronise");
   *out = p;
   return 0;
@@ -729,7 +767,7 @@ int thcsox_sigma_sox(thcsox_plan_t p, const double* G_dev, double* Sigma_dev,
   TRY(prepare_g(p, G_dev));
   for (int k = k_begin; k < k_end; k += p->tb)
     TRY(sigma_batch(p, G_dev, Sigma_dev, Sigma_thc_dev, k, std::min(k_end, k + p->tb),
-                    Cores{p->U, p->amax, p->U, p->amax}));
+                    Cores{p->U, p->amax, p->U, p->amax, p->norm2}));
   return 0;
 }
 
@@ -835,11 +873,11 @@ int thcsox_sigma_screened(thcsox_plan_t p, const double* G_dev, const double* W_
     // the operand pads stay zero (every build writes only the first n of ldk columns)
     HIP_TRY(hipMemsetAsync(p->Uw, 0, (size_t)p->np * p->esize * (size_t)p->u_plane, s));
   }
-  TRY(build_u(p, W_dev, p->Uw, p->amax_w));
+  TRY(build_u(p, W_dev, p->Uw, p->amax_w, p->norm2 ? p->norm2 + 1 : nullptr));
   TRY(prepare_g(p, G_dev));
-  const Cores vw{p->U, p->amax, p->Uw, p->amax_w};
-  const Cores wv{p->Uw, p->amax_w, p->U, p->amax};
-  const Cores ww{p->Uw, p->amax_w, p->Uw, p->amax_w};
+  const Cores vw{p->U, p->amax, p->Uw, p->amax_w, p->norm2};
+  const Cores wv{p->Uw, p->amax_w, p->U, p->amax, p->norm2 ? p->norm2 + 1 : nullptr};
+  const Cores ww{p->Uw, p->amax_w, p->Uw, p->amax_w, p->norm2 ? p->norm2 + 1 : nullptr};
   for (int k = k_begin; k < k_end; k += p->tb) {
     const int k1 = std::min(k_end, k + p->tb);
     if (kind == THCSOX_SOSEX) {
