@@ -42,6 +42,9 @@ constexpr int AKC = 32;             // k per stage
 constexpr int ANW = 8, ANT = 64 * ANW;
 
 constexpr int AMAXN = 320;          // columns per workgroup at most (WBN <= 5)
+// staging row of one v in the epilogue: 64 rows i x 2 planes (c32 order) plus
+// 8 halves of padding (rows 272 bytes apart: 16 rows start on distinct banks)
+constexpr int STG_LD = 136;
 struct ABuf {
   _Float16 u[2][AM * AKC];              // [plane][row * 32 + physical chunk * 8 + e]
   _Float16 g[2][AMAXN * AKC];
@@ -56,7 +59,8 @@ __device__ __forceinline__ void a_vm_lds_barrier() {
 }
 
 template <int WBN>
-__device__ __forceinline__ void astage_body(const AStageArgs& g, ABuf& b0, ABuf& b1) {
+__device__ __forceinline__ void astage_body(const AStageArgs& g, ABuf& b0, ABuf& b1,
+                                            _Float16* sstage) {
   constexpr int TN = 64 * WBN;
   static_assert(TN <= AMAXN, "at most 320 columns per workgroup");
   const int tid = threadIdx.x, lane = tid & 63;
@@ -173,35 +177,46 @@ __device__ __forceinline__ void astage_body(const AStageArgs& g, ABuf& b0, ABuf&
   const float a_scale = (float)pow2_scale_f(g.amax + set);
   _Float16* C = g.A + set * g.a_set;
   const int64_t c_j = (int64_t)g.naux * ld2;   // halves between v rows of A
-  const int jb = j0 + wn * 16 * WBN + (lane & 15);
   typedef _Float16 h4 __attribute__((ext_vector_type(4)));
-  // write the finished tile t: lane holds rows i0 .. i0 + 3 (one 32-wide chunk)
-  // of column v; element (v, i, plane p) is at v c_j + 64 (i / 32) + i % 32 + 32 p
+  // write the finished tile t.  A wave's 64 rows i (a multiple of 64, so two
+  // whole 32-wide chunks) of one v row are 256 contiguous bytes of A.  Per 16
+  // columns: each lane puts its four consecutive rows of both planes into the
+  // wave's staging rows (v, c32 order), then reads back 16-byte pieces so that
+  // 16 lanes store one v row's 256 bytes.
+  _Float16* const stg = sstage + wave * 16 * STG_LD;
+  const int kq = lane >> 4, vl = lane & 15;
   auto store_tile = [&](int t) {
-    const int ib = (first + t * stride) * AM + wm * 64 + 4 * (lane >> 4);
+    const int ib = (first + t * stride) * AM + wm * 64;   // this wave's first row i
+    const bool ok = ib < M;   // M is a multiple of 64: all 64 rows or none
+    _Float16* const Crow = C + 64 * (int64_t)(ib >> 5);
 #pragma unroll
-    for (int ti = 0; ti < 4; ++ti) {
-      const int i0 = ib + 16 * ti;
-      const bool ok = i0 < M;   // M is a multiple of 32: all four rows or none
-      const int64_t io = 64 * (i0 >> 5) + (i0 & 31);
+    for (int tj = 0; tj < WBN; ++tj) {
 #pragma unroll
-      for (int tj = 0; tj < WBN; ++tj) {
-        const int j = jb + 16 * tj;
-        if (ok && j < g.n) {
-          h4 hi, lo;
+      for (int ti = 0; ti < 4; ++ti) {
+        const int il = 16 * ti + 4 * kq;   // local row of element r = 0
+        h4 hi, lo;
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const float x = acc[tj][ti][r] * a_scale;
-            const _Float16 h = (_Float16)x;
-            hi[r] = h;
-            lo[r] = (_Float16)(x - (float)h);
-          }
-          _Float16* o = C + (int64_t)j * c_j + io;
-          *reinterpret_cast<h4*>(o) = hi;
-          *reinterpret_cast<h4*>(o + 32) = lo;
+        for (int r = 0; r < 4; ++r) {
+          const float x = acc[tj][ti][r] * a_scale;
+          const _Float16 h = (_Float16)x;
+          hi[r] = h;
+          lo[r] = (_Float16)(x - (float)h);
         }
+        _Float16* o = stg + vl * STG_LD + (il >> 5) * 64 + (il & 31);
+        *reinterpret_cast<h4*>(o) = hi;
+        *reinterpret_cast<h4*>(o + 32) = lo;
         acc[tj][ti] = f4{0.f, 0.f, 0.f, 0.f};
       }
+      // this wave's staging writes complete before its lanes read other lanes' rows
+      __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int v = 4 * q + kq;
+        const u4 d = *reinterpret_cast<const u4*>(stg + v * STG_LD + vl * 8);
+        const int j = j0 + wn * 16 * WBN + 16 * tj + v;
+        if (ok && j < g.n) *reinterpret_cast<u4*>(Crow + (int64_t)j * c_j + vl * 8) = d;
+      }
+      __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     }
   };
 
@@ -247,7 +262,8 @@ __device__ __forceinline__ void astage_body(const AStageArgs& g, ABuf& b0, ABuf&
   void astage_f16_kernel_##W(AStageArgs g) {                                            \
     __shared__ __attribute__((aligned(16))) ABuf b0;                                    \
     __shared__ __attribute__((aligned(16))) ABuf b1;                                    \
-    astage_body<W>(g, b0, b1);                                                          \
+    __shared__ __attribute__((aligned(16))) _Float16 sstage[ANW * 16 * STG_LD];         \
+    astage_body<W>(g, b0, b1, sstage);                                                  \
   }
 THCSOX_ASTAGE_KERNEL(2)
 THCSOX_ASTAGE_KERNEL(3)
