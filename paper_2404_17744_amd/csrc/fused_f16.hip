@@ -46,7 +46,6 @@ constexpr int KC = 32;           // k per chunk (one f16 MFMA)
 constexpr int PANEL = TT * KC * 2;   // halves per panel (both planes)
 constexpr int FLUSH_PAIRS = 4;   // pairs per FP32 partial sum of D (8 v)
 constexpr int NXCD16 = 8;
-constexpr int BAND16 = 2;        // R blocks per band of the tile walk (measured: 2 beats 1, 3, 4, 15)
 
 // One half stage: three panels, each [row][plane][32] (128-byte rows) with the
 // eight 16-byte chunks of a row permuted by sw8.
@@ -78,22 +77,27 @@ void fused_f16_kernel(FusedArgs f) {
 
   // tile and pair range: XCD-aware order (workgroup b runs on XCD b mod 8; each
   // XCD owns the partial slots z = xcd, xcd + 8, ..., a block of consecutive
-  // pair ranges, and walks the tiles in bands of BAND16 R blocks so its resident
-  // workgroups share panels in its L2).  The integer divisions run on the vector
-  // unit; readfirstlane marks their results uniform so that buffer resources and
-  // offsets stay scalar.
+  // pair ranges, and walks the tiles of one slot row by row).  With symmetric D
+  // only the tiles on or above the diagonal are walked (nb (nb + 1) / 2 of them;
+  // the grid has nb^2 per slot, the rest exit at once).  The integer divisions
+  // run on the vector unit; readfirstlane marks their results uniform so that
+  // buffer resources and offsets stay scalar.
   const int nb = (naux + TT - 1) / TT;
-  const int tiles = nb * nb;
+  const bool symm = f.sym != nullptr && *f.sym != 0;
+  const int ntl = symm ? nb * (nb + 1) / 2 : nb * nb;
   const int b = blockIdx.x;
   const int xcd = b % NXCD16, local = b / NXCD16;
-  const int z = __builtin_amdgcn_readfirstlane(xcd + NXCD16 * (local / tiles));
-  const int to = local % tiles;
-  const int band = to / (BAND16 * nb);
-  const int rb0 = band * BAND16, bh = min(BAND16, nb - rb0);
-  const int within = to - rb0 * nb;
-  const int P0 = __builtin_amdgcn_readfirstlane((within / bh) * TT);
-  const int R0 = __builtin_amdgcn_readfirstlane((rb0 + within % bh) * TT);
-  if (f.sym != nullptr && *f.sym != 0 && R0 >= P0 + TT) return;
+  if (local >= ntl * (f.vsplit / NXCD16)) return;
+  const int z = __builtin_amdgcn_readfirstlane(xcd + NXCD16 * (local / ntl));
+  int rb = 0, pb = local % ntl;
+  if (symm) {   // row rb of the upper triangle holds the nb - rb tiles P >= R
+    while (pb >= nb - rb) { pb -= nb - rb; ++rb; }
+    pb += rb;
+  } else {
+    rb = pb / nb; pb -= rb * nb;
+  }
+  const int P0 = __builtin_amdgcn_readfirstlane(pb * TT);
+  const int R0 = __builtin_amdgcn_readfirstlane(rb * TT);
 
   // pair range: XCD x owns the consecutive ranges x q .. x q + q - 1
   // (q = vsplit / 8); range r is pairs [r np / vsplit, (r + 1) np / vsplit)
@@ -296,16 +300,28 @@ void fused_f16_kernel(FusedArgs f) {
     vm_lds_barrier();
     readB(fb);
   }
+  // spread a phase's 12 memory-to-LDS loads over its 96 MFMAs (one per 8):
+  // a load the texture unit cannot take yet stalls its wave, and with one wave
+  // per SIMD nothing else would keep the matrix core busy meanwhile
+  auto spread = [&]() {
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x010, 1, 0);   // one memory instruction
+      __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);   // eight MFMAs
+    }
+  };
   auto chunk = [&](bool first) {
     vm_lds_barrier();
     dmaB(ck * KC);
     readC(fc);
     mfmaB(fb, first);
+    spread();
     vm_lds_barrier();
     dmaC(ck * KC);
     advance();
     readB(fb);
     mfmaC(fc, first);
+    spread();
   };
   int done = 0;
   for (int pr = 0; pr < npr; ++pr) {
