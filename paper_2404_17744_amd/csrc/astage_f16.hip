@@ -45,10 +45,16 @@ constexpr int AMAXN = 320;          // columns per workgroup at most (WBN <= 5)
 // staging row of one v in the epilogue: 64 rows i x 2 planes (c32 order) plus
 // 8 halves of padding (rows 272 bytes apart: 16 rows start on distinct banks)
 constexpr int STG_LD = 136;
+// One stage: U rows and G rows, each [row][plane][32] (128 bytes: both planes of
+// the row's k chunk) with the eight 16-byte chunks of a row permuted by sw8a.
 struct ABuf {
-  _Float16 u[2][AM * AKC];              // [plane][row * 32 + physical chunk * 8 + e]
-  _Float16 g[2][AMAXN * AKC];
+  _Float16 u[AM * 2 * AKC];
+  _Float16 g[AMAXN * 2 * AKC];
 };
+// Physical 16-byte chunk of logical chunk c (= 4 plane + k / 8) in LDS row r;
+// 16 consecutive rows read at one logical chunk land on all eight positions of
+// two rows (depends on r mod 16 only).
+__device__ __forceinline__ int sw8a(int r, int c) { return c ^ ((r >> 1) & 7); }
 
 template <int WBN> struct AFrags {
   f16x8 u[2][4], g[2][WBN];   // [plane][tile]
@@ -89,69 +95,66 @@ __device__ __forceinline__ void astage_body(const AStageArgs& g, ABuf& b0, ABuf&
   const int64_t ld2 = 2 * ldk;   // halves per c32 row
   const _Float16* B = static_cast<const _Float16*>(g.Gb) + set * g.gb_set + j0 * ld2;
   const __amdgpu_buffer_rsrc_t rB = make_rsrc(B, rows_j * ld2 * 2);
-  // memory-to-LDS slabs of 16 rows: U has 8 per plane (wave w moves slab w of
-  // both planes), G has TN / 16 per plane, 8 WBN in all (wave w moves the
-  // slabs w + 8 j, j < WBN, counted across the two planes)
-  constexpr int GSP = TN / 16;               // G slabs per plane
-  const int urow = wave * 16 + (lane >> 2);
+  // memory to LDS: one instruction moves 8 rows x 128 bytes (both planes of a k
+  // chunk); lane l lands at row l / 8 of the slab, physical chunk l % 8, and
+  // loads the logical chunk sw8a maps there.  U: 16 slabs, wave w moves slabs
+  // 2 w and 2 w + 1; G: TN / 8 slabs, wave w moves slabs w + 8 j, j < WBN.
+  const int lrow = lane >> 3;
   uint32_t dg[WBN];
 #pragma unroll
   for (int j = 0; j < WBN; ++j) {
-    const int slab = (wave + ANW * j) % GSP;
-    const int row = slab * 16 + (lane >> 2);
-    const int c = lds_chunk(row, lane & 3);
-    dg[j] = row < rows_j ? (uint32_t)((row * ld2 + 8 * c) * 2) : OOB;
+    const int row = (wave + ANW * j) * 8 + lrow;
+    dg[j] = row < rows_j ? (uint32_t)((row * ld2 + 8 * sw8a(row, lane & 7)) * 2) : OOB;
   }
-  // the U rows of the tile being fetched: this lane's row i = i0 + urow is U row
-  // P n + q (none for q >= n), addressed from the tile's first P
+  // the U rows of the tile being fetched: this lane's rows i = i0 + urow[h] are U
+  // rows P n + q (none for q >= n), addressed from the tile's first P
   const _Float16* Ub = static_cast<const _Float16*>(g.U);
   const int64_t urows = (int64_t)g.naux * g.n;
   __amdgpu_buffer_rsrc_t rU;
-  uint32_t du = OOB;
+  uint32_t du[2] = {OOB, OOB};
   auto set_tile = [&](int t) {
     const int i0 = (first + t * stride) * AM;
     const int P0 = __builtin_amdgcn_readfirstlane(i0 / g.ldk);
-    const int i = i0 + urow, P = i / g.ldk, q = i - P * g.ldk;
-    du = (P < g.naux && q < g.n)
-             ? (uint32_t)((((P - P0) * g.n + q) * ld2 + 8 * lds_chunk(urow, lane & 3)) * 2)
-             : OOB;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int urow = (2 * wave + h) * 8 + lrow;
+      const int i = i0 + urow, P = i / g.ldk, q = i - P * g.ldk;
+      du[h] = (P < g.naux && q < g.n)
+                  ? (uint32_t)((((P - P0) * g.n + q) * ld2 + 8 * sw8a(urow, lane & 7)) * 2)
+                  : OOB;
+    }
     const int64_t r0 = (int64_t)P0 * g.n;
     rU = make_rsrc(Ub + r0 * ld2, (urows - r0) * ld2 * 2);
   };
-  // stage k of the current fetch tile -> LDS buffer; plane p of chunk k is
-  // (64 k + 32 p) halves into a c32 row
+  // stage k of the current fetch tile -> LDS buffer (chunk k is 64 k halves into a c32 row)
   auto dma = [&](ABuf& bf, int k) {
 #pragma unroll
-    for (int p = 0; p < 2; ++p)
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(rU, &bf.u[p][wave * 16 * AKC], 16, du,
-                                               (2 * k + p) * AKC * 2, 0, 0);
+    for (int h = 0; h < 2; ++h)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rU, &bf.u[(2 * wave + h) * 8 * 64], 16, du[h],
+                                               k * 64 * 2, 0, 0);
 #pragma unroll
-    for (int j = 0; j < WBN; ++j) {
-      const int s = wave + ANW * j, p = s / GSP, slab = s % GSP;
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(rB, &bf.g[p][slab * 16 * AKC], 16, dg[j],
-                                               (2 * k + p) * AKC * 2, 0, 0);
-    }
+    for (int j = 0; j < WBN; ++j)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rB, &bf.g[(wave + ANW * j) * 8 * 64], 16, dg[j],
+                                               k * 64 * 2, 0, 0);
   };
 
-  int ui[4], gj[WBN];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int r = wm * 64 + 16 * t + (lane & 15);
-    ui[t] = r * AKC + lds_chunk(r, lane >> 4) * 8;
-  }
-#pragma unroll
-  for (int t = 0; t < WBN; ++t) {
-    const int r = wn * 16 * WBN + 16 * t + (lane & 15);
-    gj[t] = r * AKC + lds_chunk(r, lane >> 4) * 8;
-  }
+  // fragment (row r, plane p, k chunk lane / 16) at halves r * 64 + sw8a(r, 4 p + lane / 16) * 8;
+  // the rows of tile t are 16 t * 64 halves further
+  const int lr = lane & 15, kc = lane >> 4;
+  const int ru = wm * 64 + lr, rg = wn * 16 * WBN + lr;
+  const int ui0 = ru * 64 + sw8a(ru, kc) * 8, ui1 = ru * 64 + sw8a(ru, 4 + kc) * 8;
+  const int gj0 = rg * 64 + sw8a(rg, kc) * 8, gj1 = rg * 64 + sw8a(rg, 4 + kc) * 8;
   using Frags = AFrags<WBN>;
   auto read_frags = [&](Frags& fr, const ABuf& bf) {
 #pragma unroll
-    for (int p = 0; p < 2; ++p) {
+    for (int t = 0; t < 4; ++t) {
+      fr.u[0][t] = *reinterpret_cast<const f16x8*>(&bf.u[ui0 + t * 16 * 64]);
+      fr.u[1][t] = *reinterpret_cast<const f16x8*>(&bf.u[ui1 + t * 16 * 64]);
+    }
 #pragma unroll
-      for (int t = 0; t < 4; ++t) fr.u[p][t] = *reinterpret_cast<const f16x8*>(&bf.u[p][ui[t]]);
-#pragma unroll
-      for (int t = 0; t < WBN; ++t) fr.g[p][t] = *reinterpret_cast<const f16x8*>(&bf.g[p][gj[t]]);
+    for (int t = 0; t < WBN; ++t) {
+      fr.g[0][t] = *reinterpret_cast<const f16x8*>(&bf.g[gj0 + t * 16 * 64]);
+      fr.g[1][t] = *reinterpret_cast<const f16x8*>(&bf.g[gj1 + t * 16 * 64]);
     }
   };
   // acc[tj][ti]: rows i (tile ti), columns v (tile tj)

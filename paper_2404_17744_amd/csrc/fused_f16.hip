@@ -77,11 +77,12 @@ void fused_f16_kernel(FusedArgs f) {
 
   // tile and pair range: XCD-aware order (workgroup b runs on XCD b mod 8; each
   // XCD owns the partial slots z = xcd, xcd + 8, ..., a block of consecutive
-  // pair ranges, and walks the tiles of one slot row by row).  With symmetric D
-  // only the tiles on or above the diagonal are walked (nb (nb + 1) / 2 of them;
-  // the grid has nb^2 per slot, the rest exit at once).  The integer divisions
-  // run on the vector unit; readfirstlane marks their results uniform so that
-  // buffer resources and offsets stay scalar.
+  // pair ranges, and walks the tiles of one slot in bands of two R blocks, P by
+  // P with R fastest, so its resident workgroups share panels in its L2).  With
+  // symmetric D only the tiles on or above the diagonal are walked (nb (nb + 1)
+  // / 2 of them; the grid has nb^2 per slot, the rest exit at once).  The
+  // integer divisions run on the vector unit; readfirstlane marks their results
+  // uniform so that buffer resources and offsets stay scalar.
   const int nb = (naux + TT - 1) / TT;
   const bool symm = f.sym != nullptr && *f.sym != 0;
   const int ntl = symm ? nb * (nb + 1) / 2 : nb * nb;
@@ -89,12 +90,22 @@ void fused_f16_kernel(FusedArgs f) {
   const int xcd = b % NXCD16, local = b / NXCD16;
   if (local >= ntl * (f.vsplit / NXCD16)) return;
   const int z = __builtin_amdgcn_readfirstlane(xcd + NXCD16 * (local / ntl));
-  int rb = 0, pb = local % ntl;
-  if (symm) {   // row rb of the upper triangle holds the nb - rb tiles P >= R
-    while (pb >= nb - rb) { pb -= nb - rb; ++rb; }
-    pb += rb;
+  int t = local % ntl, r0 = 0;
+  for (;;) {   // the band of rows r0, r0 + 1 (one row at the end when nb is odd)
+    const int rows = min(2, nb - r0);
+    const int cnt = symm ? (rows == 2 ? 2 * (nb - r0) - 1 : nb - r0) : rows * nb;
+    if (t < cnt) break;
+    t -= cnt;
+    r0 += 2;
+  }
+  int rb, pb;
+  if (symm) {   // (r0, r0), then (r0, p), (r0 + 1, p) for p > r0
+    rb = t == 0 ? r0 : r0 + (t - 1) % 2;
+    pb = t == 0 ? r0 : r0 + 1 + (t - 1) / 2;
   } else {
-    rb = pb / nb; pb -= rb * nb;
+    const int rows = min(2, nb - r0);
+    rb = r0 + t % rows;
+    pb = t / rows;
   }
   const int P0 = __builtin_amdgcn_readfirstlane(pb * TT);
   const int R0 = __builtin_amdgcn_readfirstlane(rb * TT);
