@@ -46,7 +46,9 @@ extern "C" {
  *   BF16X3 : every operand split into three bfloat16 terms, six products per
  *            product kept, FP32 accumulation.
  *   FP16X2 : every operand scaled by a power of two and split into two
- *            half-precision terms, three products per product, FP32 accumulation.
+ *            half-precision terms, three products per product, FP32 accumulation
+ *            (the intermediate A, formed on the device, takes its power of two
+ *            from a Cauchy-Schwarz bound computed before it is formed).
  * In every mode G is scaled per tau point by a power of two.  The sum over the
  * orbital index v that forms D_PR is accumulated in FP64 by the FP64 mode; the
  * other modes sum at most 8 consecutive v in FP32, then add those partial sums
