@@ -292,6 +292,240 @@ hipError_t a_launch(void (*kernel)(AStageArgs), const AStageArgs& g, hipStream_t
   return hipGetLastError();
 }
 
+
+// ---------------------------------------------------------------------------
+// Register-resident variant for ldk <= 320 (n <= 320).  G(beta - tau)^T of one
+// set is at most 320 x 320 x 2 planes of fp16 (400 KiB), which fits in the
+// register file of one compute unit (4 waves x 512 registers x 64 lanes x 4 B =
+// 512 KiB): wave w keeps the MFMA fragments of columns v in [16 NCT w, 16 NCT (w
+// + 1)) for every k chunk and plane (4 KST^2 registers, the compiler places them
+// in both register files; the matrix cores read AGPR operands directly).  Only
+// U then streams through LDS: a step is 32 rows i = P ldk + q of the padded row
+// space (one 32-wide q chunk of one P, all KST k chunks: 40 KiB at ldk = 320),
+// double-buffered one step ahead.  Per step a wave issues 2 x NCT x KST x 3
+// MFMAs against 2 x KST x 2 fragment reads, and the workgroup moves 4 KST KiB
+// from L2 to LDS; the streaming variant above re-reads its G panels from L2 for
+// every 128-row tile (2.5 times the U bytes at ldk = 320).
+//
+// Epilogue: the step's 32 rows of one v are one 128-byte line of A (both planes
+// of chunk q / 32 of row (v, P)); each wave stages its 16 NCT lines in LDS and
+// stores them as 16-byte pieces, eight lanes per line.  The stores of a step are
+// issued at the start of the next one (after its loads), so their completion
+// overlaps that step's matrix work.
+constexpr int RM = 32;          // rows i per step
+constexpr int RNW = 4, RNT = 64 * RNW;
+
+template <int KST> struct RBuf {
+  _Float16 u[KST][RM * 64];     // [chunk][row][plane][32], 16-byte chunks permuted by sw8a
+  // the lines of A computed from u: [wave][line v][plane][32 rows], the eight
+  // 16-byte pieces of line v permuted by XOR with v % 8
+  _Float16 stg[RNW][16 * (KST / 2)][64];
+};
+
+template <int KST>
+__device__ __forceinline__ void astage_r_body(const AStageArgs& g, RBuf<KST>& b0, RBuf<KST>& b1) {
+  constexpr int NCT = KST / 2;              // 16-column tiles per wave: 4 waves cover ldk columns
+  constexpr int LDK = 32 * KST;
+  constexpr int LD2 = 2 * LDK;              // halves per c32 row
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int nstep = g.naux * KST;
+  // block -> (set x, worker y); the sets of worker y are the blocks 8 (X (y / 8) +
+  // x) + y % 8, on one XCD, so U is fetched from HBM once for all of them
+  const int X = g.nsets;
+  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+  const int set = __builtin_amdgcn_readfirstlane(slot % X);
+  const int first = __builtin_amdgcn_readfirstlane((slot / X) * 8 + xcd);
+  const int stride = __builtin_amdgcn_readfirstlane(gridDim.x / X);
+  const int nst = __builtin_amdgcn_readfirstlane(first < nstep ? (nstep - 1 - first) / stride + 1 : 0);
+  if (nst == 0) return;
+
+  // this wave's G fragments: column v = 16 (NCT wave + t) + lane % 16, k = 32 c +
+  // 8 (lane / 16) .. + 7 of plane p (zero for v >= n)
+  // (rows v >= n lie past the end of the buffer resource and read as zero)
+  const __amdgpu_buffer_rsrc_t rG = make_rsrc(static_cast<const _Float16*>(g.Gb) + set * g.gb_set,
+                                              (int64_t)g.n * LD2 * 2);
+  f16x8 gr[NCT][KST][2];
+  // the first fragments live in AGPRs (the matrix cores read them there), as many
+  // as fit beside the accumulators; the rest and all other values in VGPRs
+  constexpr int NG_A = (256 - 4 * NCT) / 4 < 2 * NCT * KST ? (256 - 4 * NCT) / 4 : 2 * NCT * KST;
+  auto in_agpr = [](int t, int c, int p) { return (t * KST + c) * 2 + p < NG_A; };
+  // (loaded eight at a time, so that moving them to AGPRs waits for a batch, not a load)
+  constexpr int NF = 2 * NCT * KST;
+#pragma unroll
+  for (int f0 = 0; f0 < NF; f0 += 8) {
+#pragma unroll
+    for (int f = f0; f < f0 + 8 && f < NF; ++f) {
+      const int t = f / (2 * KST), c = (f / 2) % KST, p = f % 2;
+      const int v = 16 * (NCT * wave + t) + (lane & 15);
+      const uint32_t gv = (uint32_t)((v * LD2 + 8 * (lane >> 4)) * 2);
+      gr[t][c][p] = __builtin_bit_cast(
+          f16x8, __builtin_amdgcn_raw_buffer_load_b128(rG, gv, (c * 64 + 32 * p) * 2, 0));
+    }
+#pragma unroll
+    for (int f = f0; f < f0 + 8 && f < NF; ++f) {
+      const int t = f / (2 * KST), c = (f / 2) % KST, p = f % 2;
+      if (in_agpr(t, c, p)) __asm__ volatile("" : "+a"(gr[t][c][p]));
+    }
+  }
+
+  // memory to LDS: wave w moves rows 8 w .. 8 w + 7 of every chunk (one
+  // instruction per chunk: 8 rows x 128 bytes); lane l lands at row 8 w + l / 8,
+  // physical 16-byte chunk l % 8, and loads the logical chunk sw8a maps there
+  const _Float16* Ub = static_cast<const _Float16*>(g.U);
+  const int drow = 8 * wave + (lane >> 3);
+  const uint32_t dvoff = (uint32_t)((drow * LD2 + 8 * sw8a(drow, lane & 7)) * 2);
+  auto dma = [&](RBuf<KST>& bf, int s) {
+    const int st = first + s * stride, P = st / KST, q0 = 32 * (st - P * KST);
+    const int nv = min(RM, g.n - q0);   // rows q < n of this step (none past n)
+    const __amdgpu_buffer_rsrc_t r =
+        make_rsrc(Ub + ((int64_t)P * g.n + q0) * LD2, nv > 0 ? (int64_t)nv * LD2 * 2 : 0);
+#pragma unroll
+    for (int c = 0; c < KST; ++c)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(r, &bf.u[c][8 * wave * 64], 16, dvoff, c * 128, 0, 0);
+  };
+
+  // fragment (row 16 a + lane % 16, plane p, k chunk lane / 16) of chunk c
+  const int lr = lane & 15, kc = lane >> 4;
+  // (the permutation depends on the row mod 16, so half a is 16 rows further)
+  int uoff[2];
+#pragma unroll
+  for (int p = 0; p < 2; ++p) uoff[p] = lr * 64 + sw8a(lr, 4 * p + kc) * 8;
+  // the two 16-row halves of a step run one after the other on the same
+  // accumulators (16 x 16 NCT of A per wave)
+  f4 acc[NCT];
+  auto compute = [&](const RBuf<KST>& bf, int a) {
+    // the fragments of chunk c + 1 are read while chunk c's MFMAs run
+    f16x8 u[2], un[2];
+#pragma unroll
+    for (int p = 0; p < 2; ++p) un[p] = *reinterpret_cast<const f16x8*>(&bf.u[0][uoff[p] + a * 16 * 64]);
+#pragma unroll
+    for (int c = 0; c < KST; ++c) {
+#pragma unroll
+      for (int p = 0; p < 2; ++p) u[p] = un[p];
+      if (c + 1 < KST) {
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+          un[p] = *reinterpret_cast<const f16x8*>(&bf.u[c + 1][uoff[p] + a * 16 * 64]);
+      }
+#pragma unroll
+      for (int pp = 0; pp < 3; ++pp) {
+        const int pg = pp == 0 ? 1 : 0, pu = pp == 1 ? 1 : 0;
+#pragma unroll
+        for (int t = 0; t < NCT; ++t) {
+          if (in_agpr(t, c, pg)) __asm__ volatile("" : "+a"(gr[t][c][pg]));
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+              u[pu], gr[t][c][pg], (c == 0 && pp == 0) ? f4{0.f, 0.f, 0.f, 0.f} : acc[t], 0, 0, 0);
+        }
+      }
+    }
+  };
+
+  // the scale of A: 2^-ilogb(amax[set]), amax a bound on |A| times 2^-14
+  const float a_scale = (float)pow2_scale_f(g.amax + set);
+  _Float16* const C = g.A + set * g.a_set;
+  const int64_t c_j = (int64_t)g.naux * LD2;   // halves between v rows of A
+  typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+  // store offsets (bytes): lane part (line 16 NCT wave + lane / 8, piece lane % 8)
+  // and eight lines further per store (offsets below 2^31: checked on the host)
+  const uint32_t cvoff = (uint32_t)(((16 * NCT * wave + (lane >> 3)) * c_j + 8 * (lane & 7)) * 2);
+  const int cjstep = (int)(8 * c_j * 2);
+  // half a of the step: each lane's four consecutive rows of both planes into the
+  // wave's staging lines (v, c32 order)
+  auto stage_half = [&](RBuf<KST>& bf, int a) {
+    _Float16* const stg = &bf.stg[wave][0][0];
+#pragma unroll
+    for (int t = 0; t < NCT; ++t) {
+      h4 hi, lo;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float x = acc[t][r] * a_scale;
+        const _Float16 h = (_Float16)x;
+        hi[r] = h;
+        lo[r] = (_Float16)(x - (float)h);
+      }
+      // rows 16 a + 4 kc .. + 3: logical piece 2 a + kc / 2 (plane 0), 4 more (plane 1)
+      _Float16* o = stg + (16 * t + lr) * 64 + 4 * (kc & 1);
+      *reinterpret_cast<h4*>(o + 8 * ((2 * a + (kc >> 1)) ^ (lr & 7))) = hi;
+      *reinterpret_cast<h4*>(o + 8 * ((4 + 2 * a + (kc >> 1)) ^ (lr & 7))) = lo;
+    }
+  };
+  // the staged lines of step s: 16-byte pieces, eight lanes per line
+  auto store_step = [&](const RBuf<KST>& bf, int s) {
+    const int st = first + s * stride, P = st / KST, c0 = st - P * KST;
+    const _Float16* const stg = &bf.stg[wave][0][0];
+    // this wave's staging writes complete before its lanes read other lanes' lines
+    __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    // line of v at v c_j halves from the step's piece of row (0, P); rows v >= n
+    // lie past the end of the resource and are not written
+    const __amdgpu_buffer_rsrc_t rC =
+        make_rsrc(C + (int64_t)P * LD2 + c0 * 64, (int64_t)(g.n - 1) * c_j * 2 + 128);
+#pragma unroll
+    for (int j = 0; j < 2 * NCT; ++j) {
+      // line 8 j + lane / 8 (line % 8 = lane / 8), logical piece lane % 8
+      const u4 d = *reinterpret_cast<const u4*>(stg + (8 * j + (lane >> 3)) * 64 +
+                                                8 * ((lane & 7) ^ (lane >> 3)));
+      __builtin_amdgcn_raw_buffer_store_b128(d, rC, cvoff, j * cjstep, 0);
+    }
+    // the reads are done before the next step's staging writes
+    __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  };
+  auto run_step = [&](RBuf<KST>& bf) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      compute(bf, a);
+      stage_half(bf, a);
+    }
+  };
+
+  // one step ahead: at the top of step s its loads have landed (every wave's) and
+  // every wave is done with the other buffer, whose staged lines (step s - 1) are
+  // then stored before it takes the loads of step s + 1.  (The staging lines sit
+  // in the buffer they are computed from: LDS accesses that alias no pending
+  // memory-to-LDS load would otherwise wait for all of them.)
+  dma(b0, 0);
+  for (int s = 0; s < nst; s += 2) {
+    a_vm_lds_barrier();
+    if (s > 0) store_step(b1, s - 1);
+    if (s + 1 < nst) dma(b1, s + 1);
+    run_step(b0);
+    if (s + 1 >= nst) { store_step(b0, s); break; }
+    a_vm_lds_barrier();
+    store_step(b0, s);
+    if (s + 2 < nst) dma(b0, s + 2);
+    run_step(b1);
+    if (s + 2 >= nst) store_step(b1, s + 1);
+  }
+  __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+
+#define THCSOX_ASTAGE_R_KERNEL(K)                                                       \
+  __global__ __launch_bounds__(RNT) __attribute__((amdgpu_waves_per_eu(1, 1)))          \
+  void astage_f16r_kernel_##K(AStageArgs g) {                                           \
+    __shared__ __attribute__((aligned(16))) RBuf<K> b0;                                 \
+    __shared__ __attribute__((aligned(16))) RBuf<K> b1;                                 \
+    astage_r_body<K>(g, b0, b1);                                                        \
+  }
+THCSOX_ASTAGE_R_KERNEL(2)
+THCSOX_ASTAGE_R_KERNEL(4)
+THCSOX_ASTAGE_R_KERNEL(6)
+THCSOX_ASTAGE_R_KERNEL(8)
+THCSOX_ASTAGE_R_KERNEL(10)
+#undef THCSOX_ASTAGE_R_KERNEL
+
+hipError_t r_launch(void (*kernel)(AStageArgs), const AStageArgs& g, hipStream_t s) {
+  // persistent step workers, a multiple of eight, the sets of a worker on one XCD
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess)
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const unsigned X = (unsigned)g.nsets;
+  const unsigned nstep = (unsigned)g.naux * (unsigned)(g.ldk / RM);
+  unsigned workers = std::min(nstep, (unsigned)std::max(1, cus) / X);
+  workers = std::max(8u, workers / 8 * 8);
+  kernel<<<X * workers, RNT, 0, s>>>(g);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t astage_f16(const AStageArgs& g, hipStream_t s) {
@@ -301,6 +535,16 @@ hipError_t astage_f16(const AStageArgs& g, hipStream_t s) {
   if ((int64_t)g.naux * g.ldk + AM > 0x7fffffffLL ||
       (int64_t)(AM + 2 * g.n) * g.ldk * 4 > 0x7fffffffLL || (int64_t)320 * g.ldk * 4 > 0x7fffffffLL)
     return hipErrorInvalidValue;
+  // G in registers while ldk <= 320 and the byte offsets of A's rows (v, P) fit in
+  // 31 bits (the stores address a set from the step's row piece)
+  if ((int64_t)g.n * g.naux * g.ldk * 4 < 0x7fffffffLL) switch (g.ldk) {
+    case 64: return r_launch(astage_f16r_kernel_2, g, s);
+    case 128: return r_launch(astage_f16r_kernel_4, g, s);
+    case 192: return r_launch(astage_f16r_kernel_6, g, s);
+    case 256: return r_launch(astage_f16r_kernel_8, g, s);
+    case 320: return r_launch(astage_f16r_kernel_10, g, s);
+    default: break;
+  }
   if (g.n <= 128) return a_launch<2>(astage_f16_kernel_2, g, s);
   if (g.n <= 192) return a_launch<3>(astage_f16_kernel_3, g, s);
   if (g.n <= 256) return a_launch<4>(astage_f16_kernel_4, g, s);
