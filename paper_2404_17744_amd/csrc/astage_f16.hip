@@ -315,6 +315,31 @@ hipError_t a_launch(void (*kernel)(AStageArgs), const AStageArgs& g, hipStream_t
 constexpr int RM = 32;          // rows i per step
 constexpr int RNW = 4, RNT = 64 * RNW;
 
+typedef int i4 __attribute__((ext_vector_type(4)));
+// raw buffer resource words over [base, base + bytes) (reads past it return zero)
+__device__ __forceinline__ i4 raw_rsrc(const void* base, int bytes) {
+  const uint64_t a = reinterpret_cast<uint64_t>(base);
+  return i4{(int)(uint32_t)a, (int)((a >> 32) & 0xffff), bytes, 0x00020000};
+}
+// LDS byte address of a __shared__ location (the low half of its flat address)
+__device__ __forceinline__ uint32_t lds_addr(const void* p) {
+  return (uint32_t)reinterpret_cast<uint64_t>(p);
+}
+// Memory-to-LDS load of 16 bytes per lane (lane l lands at LDS lds + 16 l), issued
+// in inline assembly: the compiler does not track it, so it inserts no waits for
+// it before other LDS accesses (it cannot tell the staging lines and the other
+// buffer apart from the buffer being loaded).  The kernel waits for these loads
+// itself (s_waitcnt vmcnt(0) before each barrier) and touches the loaded buffer
+// only after that barrier.  Nothing else in the kernel uses m0.
+__device__ __forceinline__ void dma16_untracked(const i4& rsrc, uint32_t lds, uint32_t voff,
+                                                uint32_t soff) {
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"
+  __asm__ volatile("s_mov_b32 m0, %0\n\tbuffer_load_dwordx4 %1, %2, %3 offen lds"
+                   :: "s"(lds), "v"(voff), "s"(rsrc), "s"(soff) : "memory", "m0");
+#pragma clang diagnostic pop
+}
+
 template <int KST> struct RBuf {
   _Float16 u[KST][RM * 64];     // [chunk][row][plane][32], 16-byte chunks permuted by sw8a
   // the lines of A computed from u: [wave][line v][plane][32 rows], the eight
@@ -350,20 +375,24 @@ __device__ __forceinline__ void astage_r_body(const AStageArgs& g, RBuf<KST>& b0
   // as fit beside the accumulators; the rest and all other values in VGPRs
   constexpr int NG_A = (256 - 4 * NCT) / 4 < 2 * NCT * KST ? (256 - 4 * NCT) / 4 : 2 * NCT * KST;
   auto in_agpr = [](int t, int c, int p) { return (t * KST + c) * 2 + p < NG_A; };
-  // (loaded eight at a time, so that moving them to AGPRs waits for a batch, not a load)
-  constexpr int NF = 2 * NCT * KST;
+  // (loaded in batches of 16, the AGPR moves of a batch after the next batch is
+  // issued, so that they wait for about one batch's latency each)
+  constexpr int NF = 2 * NCT * KST, GB = 16;
+  auto gload = [&](int f) {
+    const int t = f / (2 * KST), c = (f / 2) % KST, p = f % 2;
+    const int v = 16 * (NCT * wave + t) + (lane & 15);
+    const uint32_t gv = (uint32_t)((v * LD2 + 8 * (lane >> 4)) * 2);
+    gr[t][c][p] = __builtin_bit_cast(
+        f16x8, __builtin_amdgcn_raw_buffer_load_b128(rG, gv, (c * 64 + 32 * p) * 2, 0));
+  };
 #pragma unroll
-  for (int f0 = 0; f0 < NF; f0 += 8) {
+  for (int f = 0; f < GB && f < NF; ++f) gload(f);
 #pragma unroll
-    for (int f = f0; f < f0 + 8 && f < NF; ++f) {
-      const int t = f / (2 * KST), c = (f / 2) % KST, p = f % 2;
-      const int v = 16 * (NCT * wave + t) + (lane & 15);
-      const uint32_t gv = (uint32_t)((v * LD2 + 8 * (lane >> 4)) * 2);
-      gr[t][c][p] = __builtin_bit_cast(
-          f16x8, __builtin_amdgcn_raw_buffer_load_b128(rG, gv, (c * 64 + 32 * p) * 2, 0));
-    }
+  for (int f0 = 0; f0 < NF; f0 += GB) {
 #pragma unroll
-    for (int f = f0; f < f0 + 8 && f < NF; ++f) {
+    for (int f = f0 + GB; f < f0 + 2 * GB && f < NF; ++f) gload(f);
+#pragma unroll
+    for (int f = f0; f < f0 + GB && f < NF; ++f) {
       const int t = f / (2 * KST), c = (f / 2) % KST, p = f % 2;
       if (in_agpr(t, c, p)) __asm__ volatile("" : "+a"(gr[t][c][p]));
     }
@@ -378,11 +407,9 @@ __device__ __forceinline__ void astage_r_body(const AStageArgs& g, RBuf<KST>& b0
   auto dma = [&](RBuf<KST>& bf, int s) {
     const int st = first + s * stride, P = st / KST, q0 = 32 * (st - P * KST);
     const int nv = min(RM, g.n - q0);   // rows q < n of this step (none past n)
-    const __amdgpu_buffer_rsrc_t r =
-        make_rsrc(Ub + ((int64_t)P * g.n + q0) * LD2, nv > 0 ? (int64_t)nv * LD2 * 2 : 0);
+    const i4 r = raw_rsrc(Ub + ((int64_t)P * g.n + q0) * LD2, nv > 0 ? nv * LD2 * 2 : 0);
 #pragma unroll
-    for (int c = 0; c < KST; ++c)
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(r, &bf.u[c][8 * wave * 64], 16, dvoff, c * 128, 0, 0);
+    for (int c = 0; c < KST; ++c) dma16_untracked(r, lds_addr(&bf.u[c][8 * wave * 64]), dvoff, c * 128);
   };
 
   // fragment (row 16 a + lane % 16, plane p, k chunk lane / 16) of chunk c
@@ -470,10 +497,17 @@ __device__ __forceinline__ void astage_r_body(const AStageArgs& g, RBuf<KST>& b0
     // the reads are done before the next step's staging writes
     __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
   };
-  auto run_step = [&](RBuf<KST>& bf) {
+  // a half whose rows are all past n (pad rows of A) is zero without its MFMAs
+  auto run_step = [&](RBuf<KST>& bf, int s) {
+    const int st = first + s * stride, q0 = 32 * (st - (st / KST) * KST);
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
-      compute(bf, a);
+      if (q0 + 16 * a < g.n) {
+        compute(bf, a);
+      } else {
+#pragma unroll
+        for (int t = 0; t < NCT; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+      }
       stage_half(bf, a);
     }
   };
@@ -488,12 +522,12 @@ __device__ __forceinline__ void astage_r_body(const AStageArgs& g, RBuf<KST>& b0
     a_vm_lds_barrier();
     if (s > 0) store_step(b1, s - 1);
     if (s + 1 < nst) dma(b1, s + 1);
-    run_step(b0);
+    run_step(b0, s);
     if (s + 1 >= nst) { store_step(b0, s); break; }
     a_vm_lds_barrier();
     store_step(b0, s);
     if (s + 2 < nst) dma(b0, s + 2);
-    run_step(b1);
+    run_step(b1, s + 1);
     if (s + 2 >= nst) store_step(b1, s + 1);
   }
   __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
