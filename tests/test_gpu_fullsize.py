@@ -7,7 +7,8 @@ every tau point).
 Bars: FP64 path 1e-10 relative on the sampled Sigma elements and 1e-8 Ha in
 energy; mixed paths 1e-6 Ha in energy and 1e-6 relative on the samples.
 Properties that hold at any size are checked too: Sigma(tau) is symmetric for
-symmetric inputs, and the mixed paths agree with the GPU FP64 path.  Seed 0 runs
+symmetric inputs, and the mixed paths agree with the GPU FP64 path.  At two tau
+points the whole Sigma array is compared with the oracle's, formed in the test.  Seed 0 runs
 all four precisions; every other seed with stored oracle values runs the FP64
 path and the fp16x2 path the throughput measurement uses.
 """
@@ -85,6 +86,30 @@ def test_fullsize_vs_oracle(case, precision):
             d = (S - case["S64"]).abs().max().item() / case["S64"].abs().max().item()
             print(f"  vs GPU FP64 path: max rel {d:.2e}")
             assert d <= 1e-6
+
+
+# whole Sigma(tau_k) arrays at this size: the oracle forms two tau points here
+WHOLE_TAU = (0, 63)
+
+
+def test_fullsize_whole_sigma(case):
+    """Every element of Sigma at two tau points (one of them away from the grid's
+    ends), FP64 and fp16x2 paths, against the oracle's THC-SOX sequence formed in
+    the test (FP64, about 7 s per tau point on 16 host threads)."""
+    from oracle import sox as osox
+    s, G = case["s"], case["G"].cpu().numpy()
+    m = G.shape[0]
+    print(f"case {NAME} seed 0 whole Sigma at tau {WHOLE_TAU}: oracle", flush=True)
+    U = osox.precontract_u(s.X, s.V)
+    ref = {k: osox.sigma_thc_paper(s.X, s.V, G[k], G[m - 1 - k], U=U) for k in WHOLE_TAU}
+    del U
+    for precision, bar in (("fp64", 1e-10), ("fp16x2", 1e-6)):
+        S, _, _ = _evaluate(case, precision)
+        Sn = S.cpu().numpy()
+        for k in WHOLE_TAU:
+            err = float(np.abs(Sn[k] - ref[k]).max() / np.abs(ref[k]).max())
+            print(f"  {precision} tau {k}: whole-array rel err {err:.2e}", flush=True)
+            assert err <= bar
 
 
 def _seeds_with_golden():
