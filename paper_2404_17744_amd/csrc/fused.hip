@@ -33,10 +33,9 @@ constexpr int NXCD = 8;      // accelerator complex dies of an MI355X
 template <int M> struct FusedCfg;
 template <> struct FusedCfg<MODE_F64> { static constexpr int WTI = 2, WTJ = 2, BAND = 1; };
 template <> struct FusedCfg<MODE_F32> { static constexpr int WTI = 4, WTJ = 3, BAND = 1; };
-template <> struct FusedCfg<MODE_BF16X3> { static constexpr int WTI = 3, WTJ = 3, BAND = 4; };
-// (the fp16x2 mode has its own kernel, fused_f16.hip)
+// (the fp16x2 and bf16x3 modes have their own kernels, fused_f16.hip and fused_bf3.hip)
 
-template <int M, bool AF32>
+template <int M>
 __global__ __launch_bounds__(NT) void fused_kernel(FusedArgs f) {
   using MT = ModeT<M>;
   using T = typename MT::T;
@@ -84,7 +83,6 @@ __global__ __launch_bounds__(NT) void fused_kernel(FusedArgs f) {
   const int64_t ldk = f.ldk;
   const int64_t u_row = (int64_t)f.n * ldk;        // elements between R rows of U
   const int64_t a_v = (int64_t)f.naux * ldk;       // elements between v slabs of A
-  const float a_scale = AF32 ? (float)pow2_scale_f(f.amax_a) : 1.f;
   const int rows_r = min(TR, f.naux - R0), rows_p = min(TP, f.naux - P0);
 
   const T* Gt = static_cast<const T*>(f.Gt) + R0 * ldk;
@@ -99,16 +97,14 @@ __global__ __launch_bounds__(NT) void fused_kernel(FusedArgs f) {
 
   Panel<T, TR> pG[NP], pU[NP];
   Panel<T, TP> pX[NP];
-  Panel<T, TP> pA[AF32 ? 1 : NP];
-  PanelF32<M == MODE_F64 || M == MODE_F32 ? MODE_F16X2 : M, TP> pA32;
+  Panel<T, TP> pA[NP];
 #pragma unroll
   for (int p = 0; p < NP; ++p) {
     pG[p].init(ldk, rows_r, tid);
     pU[p].init(u_row, rows_r, tid);
     pX[p].init(ldk, rows_p, tid);
-    if constexpr (!AF32) pA[p].init(ldk, rows_p, tid);
+    pA[p].init(ldk, rows_p, tid);
   }
-  if constexpr (AF32) pA32.init(ldk, rows_p, tid);
 
   auto load_stage = [&](int v, int k0) {
 #pragma unroll
@@ -117,15 +113,11 @@ __global__ __launch_bounds__(NT) void fused_kernel(FusedArgs f) {
       pX[p].load(rX[p], k0);
       pU[p].load(make_rsrc(U + p * f.u_plane + v * ldk, TR * u_row * ES), k0);
     }
-    if constexpr (AF32) {
-      pA32.load(make_rsrc(static_cast<const float*>(f.A) + v * a_v + P0 * ldk, TP * ldk * 4), k0);
-    } else {
 #pragma unroll
-      for (int p = 0; p < NP; ++p)
-        pA[p].load(make_rsrc(static_cast<const T*>(f.A) + p * f.a_plane + v * a_v + P0 * ldk,
-                             TP * ldk * ES),
-                   k0);
-    }
+    for (int p = 0; p < NP; ++p)
+      pA[p].load(make_rsrc(static_cast<const T*>(f.A) + p * f.a_plane + v * a_v + P0 * ldk,
+                           TP * ldk * ES),
+                 k0);
   };
 
   using DAcc = typename std::conditional<M == MODE_F64, double, float>::type;
@@ -180,15 +172,8 @@ __global__ __launch_bounds__(NT) void fused_kernel(FusedArgs f) {
       pU[p].store(sU[buf][p], tid);
       pX[p].store(sX[buf][p], tid);
     }
-    if constexpr (AF32) {
-      T* planes[NP];
 #pragma unroll
-      for (int p = 0; p < NP; ++p) planes[p] = sA[buf][p];
-      pA32.store(planes, a_scale, tid);
-    } else {
-#pragma unroll
-      for (int p = 0; p < NP; ++p) pA[p].store(sA[buf][p], tid);
-    }
+    for (int p = 0; p < NP; ++p) pA[p].store(sA[buf][p], tid);
   };
   // acc[ti][tj] += sum_k rows(sr) x rows(sc) over this stage's 32-wide k range
   auto gemm = [&](typename MT::Acc (&acc)[WTI][WTJ], T (*sr)[TR * LD], T (*sc)[TP * LD]) {
@@ -269,15 +254,15 @@ void fused_tile(int mode, int* rows, int* cols) {
   switch (mode) {
     case MODE_F64: tile_of<MODE_F64>(rows, cols); break;
     case MODE_F32: tile_of<MODE_F32>(rows, cols); break;
-    case MODE_BF16X3: tile_of<MODE_BF16X3>(rows, cols); break;
-    default: fused_f16_tile(rows, cols); break;
+    default: fused_f16_tile(rows, cols); break;   // fp16x2 and bf16x3: 128 x 128
   }
 }
 
 int fused_xcds() { return NXCD; }
 
 hipError_t sox_fused(int mode, const FusedArgs& f, hipStream_t s) {
-  if (mode == MODE_F16X2) return sox_fused_f16(f, s);   // own kernel and checks
+  if (mode == MODE_F16X2) return sox_fused_f16(f, s);   // own kernels and checks
+  if (mode == MODE_BF16X3) return sox_fused_bf3(f, s);
   int TR, TP;
   fused_tile(mode, &TR, &TP);
   if (f.vsplit % NXCD != 0 || (int64_t)f.vsplit * f.vchunk < f.n) return hipErrorInvalidValue;
@@ -287,12 +272,8 @@ hipError_t sox_fused(int mode, const FusedArgs& f, hipStream_t s) {
   if ((int64_t)std::max(TR, TP) * f.n * f.ldk * 8 > 0x7fffffffLL) return hipErrorInvalidValue;
   dim3 grid(cdiv(f.naux, TP) * cdiv(f.naux, TR) * f.vsplit);
   switch (mode) {
-    case MODE_F64: fused_kernel<MODE_F64, false><<<grid, NT, 0, s>>>(f); break;
-    case MODE_F32: fused_kernel<MODE_F32, false><<<grid, NT, 0, s>>>(f); break;
-    case MODE_BF16X3:
-      if (f.a_f32) fused_kernel<MODE_BF16X3, true><<<grid, NT, 0, s>>>(f);
-      else fused_kernel<MODE_BF16X3, false><<<grid, NT, 0, s>>>(f);
-      break;
+    case MODE_F64: fused_kernel<MODE_F64><<<grid, NT, 0, s>>>(f); break;
+    case MODE_F32: fused_kernel<MODE_F32><<<grid, NT, 0, s>>>(f); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

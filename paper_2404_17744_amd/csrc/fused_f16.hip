@@ -362,7 +362,7 @@ void fused_f16_tile(int* rows, int* cols) {
 hipError_t sox_fused_f16(const FusedArgs& f, hipStream_t s) {
   const int npair = (f.n + 1) / 2;
   const int pairs_max = (npair + f.vsplit - 1) / f.vsplit;   // longest pair range
-  if (f.a_f32 || f.vsplit % NXCD16 != 0 || f.ldk % KC != 0 || f.ldk < f.n ||
+  if (f.vsplit % NXCD16 != 0 || f.ldk % KC != 0 || f.ldk < f.n ||
       (f.dpart_f32 && pairs_max > FLUSH_PAIRS))
     return hipErrorInvalidValue;
   // buffer offsets inside one tile's rows of U (c32 rows of 4 ldk bytes) are 32-bit

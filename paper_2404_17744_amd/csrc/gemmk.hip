@@ -92,6 +92,43 @@ __global__ __launch_bounds__(NT) void gemmk_kernel(GemmKArgs g) {
 
   double lmax = 0.0;
   OutT* C = static_cast<OutT*>(g.C);
+  if constexpr (__is_same(OutT, __bf16)) {
+    // three bf16 planes; a lane's four outputs are four consecutive rows i of one
+    // column j: one 8-byte store per plane when they lie in one block of ci_in
+    // rows and the address is 8-byte aligned, else one store per element
+    typedef __bf16 b4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+    for (int ti = 0; ti < WTI; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < WTJ; ++tj) {
+        const int ib = i0 + wr * 16 * WTI + 16 * ti + out_row<M>(lane, 0);
+        const int j = j0 + wc * 16 * WTJ + 16 * tj + (lane & 15);
+        if (j >= g.N) continue;
+        b4 pl[3];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          __bf16 x[3];
+          Split<MODE_BF16X3>::run(g.alpha * (double)acc[ti][tj][r], x);
+#pragma unroll
+          for (int p = 0; p < 3; ++p) pl[p][r] = x[p];
+        }
+        const int64_t o = ((int64_t)ib / g.ci_in) * g.ci_out + ((int64_t)ib % g.ci_in) + (int64_t)j * g.c_j;
+        if (ib + 3 < g.M && ib % g.ci_in + 3 < g.ci_in && (o & 3) == 0 && (g.c_plane & 3) == 0) {
+#pragma unroll
+          for (int p = 0; p < 3; ++p) *reinterpret_cast<b4*>(C + o + p * g.c_plane) = pl[p];
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = ib + r;
+            if (i >= g.M) break;
+            const int64_t oi = ((int64_t)i / g.ci_in) * g.ci_out + ((int64_t)i % g.ci_in) + (int64_t)j * g.c_j;
+#pragma unroll
+            for (int p = 0; p < 3; ++p) C[oi + p * g.c_plane] = pl[p][r];
+          }
+        }
+      }
+    return;
+  }
 #pragma unroll
   for (int ti = 0; ti < WTI; ++ti)
 #pragma unroll
@@ -101,8 +138,9 @@ __global__ __launch_bounds__(NT) void gemmk_kernel(GemmKArgs g) {
         const int i = i0 + wr * 16 * WTI + 16 * ti + out_row<M>(lane, r);
         const int j = j0 + wc * 16 * WTJ + 16 * tj + (lane & 15);
         if (i < g.M && j < g.N) {
+          const int64_t o = ((int64_t)i / g.ci_in) * g.ci_out + ((int64_t)i % g.ci_in) + (int64_t)j * g.c_j;
           const OutT v = (OutT)(g.alpha * (double)acc[ti][tj][r]);
-          C[((int64_t)i / g.ci_in) * g.ci_out + ((int64_t)i % g.ci_in) + (int64_t)j * g.c_j] = v;
+          C[o] = v;
           lmax = fmax(lmax, fabs((double)v));
         }
       }
@@ -127,6 +165,15 @@ hipError_t launch_mode(bool out_f64, const GemmKArgs& g, hipStream_t s) {
 }
 
 }  // namespace
+
+hipError_t gemm_kmajor_bf3(const GemmKArgs& g, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0) return hipSuccess;
+  const int wtj = g.N <= 320 ? 10 : 5;
+  const unsigned grid = cdiv(g.M, 64) * cdiv(g.N, 32 * wtj);
+  if (wtj == 10) gemmk_kernel<MODE_BF16X3, 2, 10, __bf16><<<grid, NT, 0, s>>>(g);
+  else gemmk_kernel<MODE_BF16X3, 2, 5, __bf16><<<grid, NT, 0, s>>>(g);
+  return hipGetLastError();
+}
 
 hipError_t gemm_kmajor(int mode, bool out_f64, const GemmKArgs& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0) return hipSuccess;

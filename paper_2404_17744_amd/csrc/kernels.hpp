@@ -33,8 +33,13 @@ struct GemmKArgs {
   const void* B; int64_t ldb, b_plane;
   void* C; int64_t ci_in, ci_out, c_j;
   unsigned long long* amax;
+  int64_t c_plane;   // gemm_kmajor_bf3: elements between the output planes
 };
 hipError_t gemm_kmajor(int mode, bool out_f64, const GemmKArgs& g, hipStream_t s);
+// The same product in the bf16x3 mode with the output split into three bf16
+// planes (C + p * c_plane, p < 3) instead of FP32 (no scale: bf16 keeps FP32's
+// exponent range); amax is not used.
+hipError_t gemm_kmajor_bf3(const GemmKArgs& g, hipStream_t s);
 // The A stage of the fp16x2 mode for nsets tau points at once:
 //   A[set][v][P][q] = scale[set] * sum_s U[P][q][s] Gb[set][v][s]   (q < n; rows n <= q < ldk get 0)
 // All operands are fp16 planes in the c32 layout (row r, plane p, k at
@@ -53,17 +58,16 @@ hipError_t astage_f16(const AStageArgs& a, hipStream_t s);
 
 // The fused B/C/D stage for one tau point (v split over grid.z):
 //   Dpart[z][R][P] = sum_{v in split z} (sum_q Gt[R][q] A[v][P][q]) (sum_w U[R][v][w] GXt[P][w])
-// With a_f32, A is an FP32 array [n][naux][ldk] split into the mode's planes on
-// the fly after scaling by the power of two taken from *amax_a.  In the fp16x2
-// mode every operand (A included, already scaled) is in the c32 layout, the
-// plane strides are unused, and the v split counts pairs of v: split z covers
-// the pairs [z' np / vsplit, (z' + 1) np / vsplit) (np = ceil(n / 2)).
+// A holds the mode's planes (fp16x2: scaled by the power of two taken from
+// *amax_a, which the reduction divides out; otherwise unscaled).  In the fp16x2
+// mode every operand is in the c32 layout, the plane strides are unused, and
+// the v split counts pairs of v: split z covers the pairs [z' np / vsplit,
+// (z' + 1) np / vsplit) (np = ceil(n / 2)).
 struct FusedArgs {
   int n, naux, ldk, vsplit, vchunk;
   const void* Gt; const void* GXt; int64_t g_plane;   // [naux][ldk] planes
   const void* U; int64_t u_plane;                      // [naux][n][ldk] planes
-  const void* A; int64_t a_plane;                      // [n][naux][ldk] planes (or FP32)
-  bool a_f32;
+  const void* A; int64_t a_plane;                      // [n][naux][ldk] planes
   const unsigned long long* amax_a;
   double* Dpart;                                       // [vsplit][naux][naux]
   // Dpart holds FP32 partial tiles (reinterpreted as float*).  Only with v ranges
@@ -77,8 +81,11 @@ struct FusedArgs {
 };
 hipError_t sox_fused(int mode, const FusedArgs& f, hipStream_t s);
 void fused_tile(int mode, int* rows, int* cols);   // D tile one workgroup owns (R x P)
-// the fp16x2 kernel (FP32 A split on the fly), used by sox_fused for that mode
+// the fp16x2 kernel, used by sox_fused for that mode
 hipError_t sox_fused_f16(const FusedArgs& f, hipStream_t s);
+// the bf16x3 kernel (three bf16 planes, one v per pass), used by sox_fused for
+// that mode
+hipError_t sox_fused_bf3(const FusedArgs& f, hipStream_t s);
 void fused_f16_tile(int* rows, int* cols);
 int fused_xcds();   // vsplit must be a multiple of this (one v range per XCD in turn)
 

@@ -76,66 +76,5 @@ struct Panel {
   }
 };
 
-// Exact split of an FP32 value into 16-bit planes (x - hi is exact in FP32).
-template <int M> __device__ __forceinline__ void split_f(float x, typename ModeT<M>::T* o);
-template <> __device__ __forceinline__ void split_f<MODE_F16X2>(float x, _Float16* o) {
-  const _Float16 h = (_Float16)x;
-  o[0] = h;
-  o[1] = (_Float16)(x - (float)h);
-}
-template <> __device__ __forceinline__ void split_f<MODE_BF16X3>(float x, __bf16* o) {
-  const __bf16 h = (__bf16)x;
-  const float r1 = x - (float)h;
-  const __bf16 m = (__bf16)r1;
-  o[0] = h;
-  o[1] = m;
-  o[2] = (__bf16)(r1 - (float)m);
-}
-
-// A ROWS x BK panel of an FP32 array, split into the planes of mode M (after
-// scaling by a power of two) when written to LDS.
-template <int M, int ROWS>
-struct PanelF32 {
-  using T = typename ModeT<M>::T;
-  static constexpr int NP = ModeT<M>::NP;
-  static constexpr int UPR = BK / 4, NU = ROWS * UPR, PER = (NU + NT - 1) / NT;
-  uint32_t off[PER];
-  f4 r[PER];
-  __device__ __forceinline__ void init(int64_t row_stride, int valid_rows, int tid) {
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int u = tid + i * NT;
-      const int row = u / UPR, c = (u % UPR) * 4;
-      off[i] = (u < NU && row < valid_rows) ? (uint32_t)(((int64_t)row * row_stride + c) * 4)
-                                            : OOB;
-    }
-  }
-  __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t rs, int k0) {
-#pragma unroll
-    for (int i = 0; i < PER; ++i)
-      r[i] = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(rs, off[i], k0 * 4, 0));
-  }
-  __device__ __forceinline__ void store(T* const* s, float scale, int tid) const {
-    constexpr int LD = lds_ld<T>();
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int u = tid + i * NT;
-      const int row = u / UPR, c4 = u % UPR;   // 4-element piece: chunk c4 / 2, half c4 % 2
-      const int c = lds_chunk(row, c4 >> 1) * 8 + (c4 & 1) * 4;
-      if (NU % NT == 0 || u < NU) {
-        T o[4][NP];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) split_f<M>(r[i][e] * scale, o[e]);
-#pragma unroll
-        for (int p = 0; p < NP; ++p) {
-          typedef T T4 __attribute__((ext_vector_type(4)));
-          T4 w = {o[0][p], o[1][p], o[2][p], o[3][p]};
-          *reinterpret_cast<T4*>(s[p] + row * LD + c) = w;
-        }
-      }
-    }
-  }
-};
-
 }  // namespace
 }  // namespace thcsox

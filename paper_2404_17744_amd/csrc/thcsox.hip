@@ -138,7 +138,6 @@ struct thcsox_plan_s {
   int64_t u_plane = 0;
   void* A = nullptr;        // planes of [n][naux][ldk] (fp16x2: [a_sets] c32 rows [n][naux])
   int64_t a_plane = 0;
-  float* A32 = nullptr;     // [n][naux][ldk], bf16x3 only
   int a_sets = 1;           // tau points per A-stage launch (fp16x2: 2 while A is small)
   // fp16x2: the largest squared row norms of U ([0]) and of the screened core's
   // U ([1]), and of G(beta - tau)^T for each tau of a batch ([2 ..]): the A
@@ -378,7 +377,9 @@ int sigma_batch(thcsox_plan_s* p, const double* G, double* Sigma, double* Sthc_o
   }
   HIP_TRY(p->mark(THCSOX_STAGE_PROJECT, false));
 
-  const bool split_a = (mode == MODE_BF16X3 || mode == MODE_F16X2);
+  // fp16x2 scales A by a power of two (bound taken before the A stage); the
+  // bf16x3 A stage writes three unscaled bf16 planes (FP32's exponent range)
+  const bool scaled_a = mode == MODE_F16X2;
   for (int b = 0; b < nb; ++b) {
     const int k = k0 + b, kb = m - 1 - k;
     const int* sym = same_core && p->sym_mode == THCSOX_SYM_AUTO ? p->symflag + k : nullptr;
@@ -404,11 +405,14 @@ int sigma_batch(thcsox_plan_s* p, const double* G, double* Sigma, double* Sthc_o
         ga.B = static_cast<const char*>(p->Gb) + (size_t)b * n * ldk * es;
         ga.ldb = ldk; ga.b_plane = p->gb_plane;
         ga.ci_in = n; ga.ci_out = ldk; ga.c_j = (int64_t)naux * ldk;
-        // FP32 A in the bf16x3 mode: the fused kernel splits it into planes with
-        // the scale from max|A|
-        ga.C = split_a ? static_cast<void*>(p->A32) : p->A;
-        ga.amax = split_a ? p->am_a() + k : nullptr;
-        HIP_TRY(gemm_kmajor(mode, mode == MODE_F64, ga, s));
+        ga.C = p->A;
+        ga.amax = nullptr;
+        if (mode == MODE_BF16X3) {
+          ga.c_plane = p->a_plane;
+          HIP_TRY(gemm_kmajor_bf3(ga, s));
+        } else {
+          HIP_TRY(gemm_kmajor(mode, mode == MODE_F64, ga, s));
+        }
       }
       HIP_TRY(p->mark(THCSOX_STAGE_A, false));
     }
@@ -419,15 +423,10 @@ int sigma_batch(thcsox_plan_s* p, const double* G, double* Sigma, double* Sthc_o
     f.GXt = static_cast<const char*>(p->GX) + (size_t)b * naux * lrow * es;
     f.g_plane = p->g_plane;
     f.U = cores.UC; f.u_plane = p->u_plane;
-    if (c32) {   // A already split and scaled by the A stage
-      f.A = static_cast<const _Float16*>(p->A) + aset * a_set;
-      f.a_f32 = false;
-    } else {
-      f.A = split_a ? static_cast<const void*>(p->A32) : p->A;
-      f.a_f32 = split_a;
-    }
+    // A already in the mode's planes (fp16x2: split and scaled by the A stage)
+    f.A = c32 ? static_cast<const void*>(static_cast<const _Float16*>(p->A) + aset * a_set) : p->A;
     f.a_plane = p->a_plane;
-    f.amax_a = split_a ? p->am_a() + k : nullptr;
+    f.amax_a = scaled_a ? p->am_a() + k : nullptr;
     f.Dpart = p->Dpart; f.dpart_f32 = p->dpart_f32;
     f.sym = sym;
     HIP_TRY(p->mark(THCSOX_STAGE_FUSED, true));
@@ -440,7 +439,7 @@ int sigma_batch(thcsox_plan_s* p, const double* G, double* Sigma, double* Sthc_o
     d.Sthc = Sthc_out ? Sthc_out + (int64_t)k * aa : p->Sthc + (int64_t)b * aa;
     d.s_ld = naux;
     d.amax_gt = p->am_gt() + k; d.amax_gx = p->am_gx() + k; d.amax_gb = p->am_g() + kb;
-    d.amax_a = split_a ? p->am_a() + k : nullptr;
+    d.amax_a = scaled_a ? p->am_a() + k : nullptr;
     d.amax_u = (mode == MODE_F64) ? nullptr : cores.amaxA;
     d.amax_u2 = (mode == MODE_F64) ? nullptr : cores.amaxC;
     d.sym = sym;
@@ -682,7 +681,7 @@ int thcsox_plan(thcsox_plan_t* out, int n, int naux, int ntau, double beta,
       // (X, V and the per-tau scalars in FP64, U, A, the partial tiles)
       const double fixed = 8.0 * ((double)n * naux + (double)naux * naux + 7.0 * ntau + 2.0) +
                            (double)p->np * p->esize * naux * n * ldk +
-                           (p->np > 1 ? 4.0 * p->a_sets : (double)p->esize) * n * naux * ldk +
+                           (double)p->np * p->esize * p->a_sets * n * naux * ldk +
                            (p->dpart_f32 ? 4.0 : 8.0) * p->vsplit * (double)naux * naux +
                            temps + (1 << 20);
       cap = std::min(cap, (double)workspace_limit - fixed);
@@ -700,12 +699,8 @@ int thcsox_plan(thcsox_plan_t* out, int n, int naux, int ntau, double beta,
   if ((rc = p->alloc(&p->E, 1))) return bail(rc);
   if ((rc = p->alloc(&tmp, np * es * (size_t)p->u_plane))) return bail(rc);
   p->U = tmp;
-  if (precision == THCSOX_BF16X3) {
-    if ((rc = p->alloc(&p->A32, (size_t)p->a_plane))) return bail(rc);
-  } else {
-    if ((rc = p->alloc(&tmp, np * es * (size_t)p->a_sets * p->a_plane))) return bail(rc);
-    p->A = tmp;
-  }
+  if ((rc = p->alloc(&tmp, np * es * (size_t)p->a_sets * p->a_plane))) return bail(rc);
+  p->A = tmp;
   if (precision == THCSOX_FP16X2 && (rc = p->alloc(&p->norm2, (size_t)2 + p->tb)))
     return bail(rc);
   if ((rc = p->alloc(&tmp, np * es * (size_t)p->g_plane))) return bail(rc);
@@ -739,8 +734,6 @@ int thcsox_plan(thcsox_plan_t* out, int n, int naux, int ntau, double beta,
     return hip_bail(e, "zero A");
   if ((e = hipMemsetAsync(p->symflag, 0, sizeof(int) * (size_t)ntau, s)))
     return hip_bail(e, "zero flags");
-  if (p->A32 && (e = hipMemsetAsync(p->A32, 0, sizeof(float) * (size_t)p->a_plane, s)))
-    return hip_bail(e, "zero A32");
   if ((rc = p->alloc(&p->V, (size_t)naux * naux))) return bail(rc);
   if ((e = hipMemcpyAsync(p->V, V_dev, sizeof(double) * (size_t)naux * naux,
                           hipMemcpyDeviceToDevice, s)))
