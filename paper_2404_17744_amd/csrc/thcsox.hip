@@ -564,8 +564,10 @@ int thcsox_plan(thcsox_plan_t* out, int n, int naux, int ntau, double beta,
     fused_tile(precision, &TR, &TP);
     auto fits = [&](int64_t nn) {
       const int64_t l = precision == THCSOX_FP16X2 ? (nn + 63) / 64 * 64 : (nn + 31) / 32 * 32;
-      // bytes per k of an operand row: FP64 8; fp16x2 4 (both planes in one c32 row)
-      const int64_t es = precision == THCSOX_FP16X2 ? 4 : 8;
+      // bytes per k of an operand row addressed by one resource: FP64 8 (FP32
+      // counted at 8 too); fp16x2 4 (both planes in one c32 row); bf16x3 2 (one
+      // resource per plane)
+      const int64_t es = precision == THCSOX_FP16X2 ? 4 : precision == THCSOX_BF16X3 ? 2 : 8;
       // in double: exact near the bound, and no wrap-around for huge n
       return (double)std::max(TR, TP) * (double)nn * (double)l * (double)es <= 2147483647.0;
     };
