@@ -169,9 +169,9 @@ hipError_t launch_mode(bool out_f64, const GemmKArgs& g, hipStream_t s) {
 hipError_t gemm_kmajor_bf3(const GemmKArgs& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
   const int wtj = g.N <= 320 ? 10 : 5;
-  const unsigned grid = cdiv(g.M, 64) * cdiv(g.N, 32 * wtj);
-  if (wtj == 10) gemmk_kernel<MODE_BF16X3, 2, 10, __bf16><<<grid, NT, 0, s>>>(g);
-  else gemmk_kernel<MODE_BF16X3, 2, 5, __bf16><<<grid, NT, 0, s>>>(g);
+  const unsigned grid = cdiv(g.M, 128) * cdiv(g.N, 32 * wtj);
+  if (wtj == 10) gemmk_kernel<MODE_BF16X3, 4, 10, __bf16><<<grid, NT, 0, s>>>(g);
+  else gemmk_kernel<MODE_BF16X3, 4, 5, __bf16><<<grid, NT, 0, s>>>(g);
   return hipGetLastError();
 }
 
