@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libthcsox.so")
 OBJ = os.path.join(os.path.dirname(HERE), "_build")
-SOURCES = ["kernels.hip", "gemmk.hip", "astage_f16.hip", "fused.hip", "fused_f16.hip", "fused_bf3.hip",
+SOURCES = ["kernels.hip", "gemmk.hip", "astage_f16.hip", "astage_bf3.hip", "fused.hip", "fused_f16.hip", "fused_bf3.hip",
            "thcsox.hip", "dyson.hip", "loopctl.hip", "direct.hip", "mlp.hip", "irgrid.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

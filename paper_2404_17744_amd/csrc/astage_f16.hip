@@ -315,31 +315,6 @@ hipError_t a_launch(void (*kernel)(AStageArgs), const AStageArgs& g, hipStream_t
 constexpr int RM = 32;          // rows i per step
 constexpr int RNW = 4, RNT = 64 * RNW;
 
-typedef int i4 __attribute__((ext_vector_type(4)));
-// raw buffer resource words over [base, base + bytes) (reads past it return zero)
-__device__ __forceinline__ i4 raw_rsrc(const void* base, int bytes) {
-  const uint64_t a = reinterpret_cast<uint64_t>(base);
-  return i4{(int)(uint32_t)a, (int)((a >> 32) & 0xffff), bytes, 0x00020000};
-}
-// LDS byte address of a __shared__ location (the low half of its flat address)
-__device__ __forceinline__ uint32_t lds_addr(const void* p) {
-  return (uint32_t)reinterpret_cast<uint64_t>(p);
-}
-// Memory-to-LDS load of 16 bytes per lane (lane l lands at LDS lds + 16 l), issued
-// in inline assembly: the compiler does not track it, so it inserts no waits for
-// it before other LDS accesses (it cannot tell the staging lines and the other
-// buffer apart from the buffer being loaded).  The kernel waits for these loads
-// itself (s_waitcnt vmcnt(0) before each barrier) and touches the loaded buffer
-// only after that barrier.  Nothing else in the kernel uses m0.
-__device__ __forceinline__ void dma16_untracked(const i4& rsrc, uint32_t lds, uint32_t voff,
-                                                uint32_t soff) {
-#pragma clang diagnostic push
-#pragma clang diagnostic ignored "-Winline-asm"
-  __asm__ volatile("s_mov_b32 m0, %0\n\tbuffer_load_dwordx4 %1, %2, %3 offen lds"
-                   :: "s"(lds), "v"(voff), "s"(rsrc), "s"(soff) : "memory", "m0");
-#pragma clang diagnostic pop
-}
-
 template <int KST> struct RBuf {
   _Float16 u[KST][RM * 64];     // [chunk][row][plane][32], 16-byte chunks permuted by sw8a
   // the lines of A computed from u: [wave][line v][plane][32 rows], the eight

@@ -55,6 +55,22 @@ struct AStageArgs {
   const unsigned long long* amax;
 };
 hipError_t astage_f16(const AStageArgs& a, hipStream_t s);
+// The A stage of the bf16x3 mode for one tau point:
+//   A[p][v][P][q] = plane p of the bf16x3 split of sum_s U[P][q][s] Gb[v][s]
+//   (q < n; rows n <= q < ldk get 0)
+// U rows (P, q) and Gb rows v (G(beta - tau)^T) are three bf16 planes of ldk
+// elements per row (u_plane, gb_plane elements apart), A rows (v, P) with k = q
+// (a_plane apart).  Only for ldk = 32 ceil(n / 32) <= 320 with byte offsets in
+// 31 bits (astage_bf3_fits); otherwise hipErrorInvalidValue (use gemm_kmajor_bf3).
+struct AStageB3Args {
+  int naux, n, ldk;
+  const void* U; int64_t u_plane;
+  const void* Gb; int64_t gb_plane;
+  void* A; int64_t a_plane;
+  int wx0, wx1;   // set by the launcher
+};
+bool astage_bf3_fits(int n, int naux, int ldk);
+hipError_t astage_bf3(const AStageB3Args& a, hipStream_t s);
 
 // The fused B/C/D stage for one tau point (v split over grid.z):
 //   Dpart[z][R][P] = sum_{v in split z} (sum_q Gt[R][q] A[v][P][q]) (sum_w U[R][v][w] GXt[P][w])

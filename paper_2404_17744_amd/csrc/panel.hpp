@@ -40,6 +40,31 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, in
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, n, 0x00020000);
 }
 
+typedef int i4 __attribute__((ext_vector_type(4)));
+// raw buffer resource words over [base, base + bytes) (reads past it return zero)
+__device__ __forceinline__ i4 raw_rsrc(const void* base, int bytes) {
+  const uint64_t a = reinterpret_cast<uint64_t>(base);
+  return i4{(int)(uint32_t)a, (int)((a >> 32) & 0xffff), bytes, 0x00020000};
+}
+// LDS byte address of a __shared__ location (the low half of its flat address)
+__device__ __forceinline__ uint32_t lds_addr(const void* p) {
+  return (uint32_t)reinterpret_cast<uint64_t>(p);
+}
+// Memory-to-LDS load of 16 bytes per lane (lane l lands at LDS lds + 16 l), issued
+// in inline assembly: the compiler does not track it, so it inserts no waits for
+// it before other LDS accesses (it cannot tell other LDS data apart from the
+// buffer being loaded).  The kernel waits for these loads itself (s_waitcnt
+// vmcnt(0) before each barrier) and touches the loaded buffer only after that
+// barrier.  Nothing else in the kernel uses m0.
+__device__ __forceinline__ void dma16_untracked(const i4& rsrc, uint32_t lds, uint32_t voff,
+                                                uint32_t soff) {
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"
+  __asm__ volatile("s_mov_b32 m0, %0\n\tbuffer_load_dwordx4 %1, %2, %3 offen lds"
+                   :: "s"(lds), "v"(voff), "s"(rsrc), "s"(soff) : "memory", "m0");
+#pragma clang diagnostic pop
+}
+
 // A ROWS x BK panel of a K-major array, staged through registers in 16-byte
 // units.  Each thread's byte offsets inside the panel are fixed for the whole
 // kernel (rows past the valid range point out of the buffer and load zero).

@@ -398,6 +398,14 @@ int sigma_batch(thcsox_plan_s* p, const double* G, double* Sigma, double* Sthc_o
         ast.A = static_cast<_Float16*>(p->A); ast.a_set = a_set;
         ast.amax = p->am_a() + k;
         HIP_TRY(astage_f16(ast, s));
+      } else if (mode == MODE_BF16X3 && astage_bf3_fits(n, naux, ldk)) {
+        AStageB3Args ab{};
+        ab.naux = naux; ab.n = n; ab.ldk = ldk;
+        ab.U = cores.UA; ab.u_plane = p->u_plane;
+        ab.Gb = static_cast<const char*>(p->Gb) + (size_t)b * n * ldk * es;
+        ab.gb_plane = p->gb_plane;
+        ab.A = p->A; ab.a_plane = p->a_plane;
+        HIP_TRY(astage_bf3(ab, s));
       } else {
         GemmKArgs ga{};
         ga.M = naux * n; ga.N = n; ga.kpad = ldk; ga.alpha = 1.0;

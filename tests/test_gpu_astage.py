@@ -1,4 +1,4 @@
-"""GPU parity of the fp16x2 A stage, A_Pqv = sum_s U_Pqs G_sv(beta - tau), at the
+"""GPU parity of the fp16x2 and bf16x3 A stages, A_Pqv = sum_s U_Pqs G_sv(beta - tau), at the
 orbital counts that select each of its kernels, through Sigma (every element
 of A enters it) against the oracle's THC-SOX sequence.
 
@@ -16,6 +16,15 @@ An odd tau count leaves the last A-stage launch with a single tau point (the
 launch forms two at a time).  The smaller counts (n = 1 .. 150 and 300) are in
 the edge, parity and full-size tests.  Bar: 2e-6 of max |Sigma|, as the other
 split-precision parity tests.
+
+The bf16x3 A stage keeps G(beta - tau) in registers while ldk = 32 ceil(n / 32)
+is at most 320: one kernel per chunk count 1 .. 10, with the 16-column tiles in
+one block of up to 12 (n <= 192: 1, 2 or 3 tiles per wave) or in two blocks
+(12 tiles and 1 or 2 tiles per wave).  The cases cover every chunk count, both
+block splits, a block of exactly 12 tiles (n = 192), full and ragged last
+tiles, steps wholly past n (32 ceil(n / 32) - n >= 16) and the streaming kernel
+beyond (n = 321).  Bar: 2e-7 of max |Sigma| (the bf16x3 path reaches a few
+1e-9; one dropped plane product or a wrong plane costs about 2^-16).
 """
 import numpy as np
 import pytest
@@ -50,3 +59,29 @@ def test_astage_kernels_fp16x2(dev, case):
         err = float(np.abs(S[k] - ref[k]).max() / np.abs(ref[k]).max())
         print(f"  tau {k}: rel err {err:.2e}", flush=True)
         assert err <= TOL
+
+
+BF3_TOL = 2e-7
+BF3_CASES = [(20, 37, 2), (50, 40, 2), (96, 44, 2), (128, 40, 2), (150, 48, 2), (192, 40, 2),
+             (200, 52, 2), (256, 40, 2), (270, 46, 2), (289, 40, 2), (320, 56, 2), (321, 48, 2)]
+
+
+@pytest.mark.parametrize("case", BF3_CASES, ids=[f"n{a}_naux{b}_ntau{c}" for a, b, c in BF3_CASES])
+def test_astage_kernels_bf16x3(dev, case):
+    n, naux, ntau = case
+    print(f"case n{n} naux{naux} ntau{ntau} bf16x3 A stage", flush=True)
+    s = synth.make_system(n, naux, seed=60 + n)
+    tau, w = synth.cheb_tau_grid(ntau, BETA)
+    G = synth.g0_tau(s, tau, BETA)
+    ref = osox.sigma_all_tau(osox.sigma_thc_paper, G, s.X, s.V)
+    plan = thcsox.Plan(torch.from_numpy(s.X).to(dev), torch.from_numpy(s.V).to(dev), tau, w,
+                       BETA, precision="bf16x3")
+    S = plan.sigma(torch.from_numpy(G).to(dev))
+    torch.cuda.synchronize()
+    S = S.cpu().numpy()
+    plan.close()
+    assert np.isfinite(S).all()
+    for k in range(ntau):
+        err = float(np.abs(S[k] - ref[k]).max() / np.abs(ref[k]).max())
+        print(f"  tau {k}: rel err {err:.2e}", flush=True)
+        assert err <= BF3_TOL
