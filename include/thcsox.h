@@ -84,9 +84,9 @@ typedef struct thcsox_plan_s* thcsox_plan_t;
  *                    the caller may free them when this call returns.
  *   precision      : one of THCSOX_FP64 .. THCSOX_FP16X2.  The fused kernels
  *                    address one tile's rows of U with 32-bit buffer offsets,
- *                    which bounds n: n <= 2047 (FP64), 1440 (FP32), 2880
- *                    (BF16X3, one resource per plane), 2047 (FP16X2, whose
- *                    rows hold both planes); larger n is THCSOX_EINVAL.
+ *                    which bounds n: n <= 2047 (FP64, FP32), 2880 (BF16X3,
+ *                    one resource per plane), 2047 (FP16X2, whose rows hold
+ *                    both planes); larger n is THCSOX_EINVAL.
  *   workspace_limit: upper bound in bytes on everything the plan allocates,
  *                    the temporaries of building U (freed before this call
  *                    returns) included (0 = no bound).  The number of tau

@@ -1,4 +1,5 @@
-// The fused B/C/D stage of the THC-SOX sequence (one tau point):
+// The fused B/C/D stage of the THC-SOX sequence (one tau point), FP64 mode, and
+// the dispatch of the other modes' kernels:
 //
 //   D_PR = sum_v C_RvP B_PRv,   B_PRv = sum_q G_Rq A_Pqv,   C_RvP = sum_w U_Rvw G_wP
 //
@@ -6,10 +7,10 @@
 // it forms both length-n contractions on matrix cores,
 //   accB[R][P] = sum_q Gt[R][q] A[v][P][q]      accC[R][P] = sum_w U[R][v][w] GXt[P][w]
 // which land in the same MFMA output layout, so B o C is a register-to-register
-// product.  In FP64 mode it is accumulated in FP64 registers; in the other modes
-// in FP32 registers for at most FLUSH_V consecutive v, then added into the
-// workgroup's FP64 tile of D in global memory (which only that workgroup
-// touches), so the sum over v is FP64 across chunks.  Neither B (naux^2 n) nor
+// product.  In FP64 mode it is accumulated in FP64 registers; the template also
+// holds a reduced-precision form (FP32 registers for at most FLUSH_V consecutive
+// v, then added into the workgroup's FP64 tile of D) that is not launched: only
+// the FP64 mode runs this kernel.  Neither B (naux^2 n) nor
 // C ever reaches memory.  Operands are staged through LDS one (v, 32-wide k chunk) stage at a
 // time; the next stage's global loads are issued before the current stage's
 // MFMAs (register prefetch), so loads overlap the matrix work.
@@ -28,12 +29,11 @@ constexpr int NXCD = 8;      // accelerator complex dies of an MI355X
 
 // MFMA tiles per wave (rows x cols); the workgroup is 2 x 2 waves.  Sized so
 // that two stages of operand panels fit the 160 KiB of LDS.  BAND: R blocks per
-// band of the tile walk (measured at n = 300: 1 is 5 % faster than 4 for FP64
-// and FP32, 2 % slower for bf16x3).
+// band of the tile walk (measured at n = 300: 1 is 5 % faster than 4 for FP64).
 template <int M> struct FusedCfg;
 template <> struct FusedCfg<MODE_F64> { static constexpr int WTI = 2, WTJ = 2, BAND = 1; };
-template <> struct FusedCfg<MODE_F32> { static constexpr int WTI = 4, WTJ = 3, BAND = 1; };
-// (the fp16x2 and bf16x3 modes have their own kernels, fused_f16.hip and fused_bf3.hip)
+// (the FP32 and fp16x2 modes run the two-v kernel of fused_f16.hip, bf16x3 that of
+// fused_bf3.hip)
 
 template <int M>
 __global__ __launch_bounds__(NT) void fused_kernel(FusedArgs f) {
@@ -253,15 +253,14 @@ template <int M> void tile_of(int* rows, int* cols) {
 void fused_tile(int mode, int* rows, int* cols) {
   switch (mode) {
     case MODE_F64: tile_of<MODE_F64>(rows, cols); break;
-    case MODE_F32: tile_of<MODE_F32>(rows, cols); break;
-    default: fused_f16_tile(rows, cols); break;   // fp16x2 and bf16x3: 128 x 128
+    default: fused_f16_tile(rows, cols); break;   // FP32, fp16x2 and bf16x3: 128 x 128
   }
 }
 
 int fused_xcds() { return NXCD; }
 
 hipError_t sox_fused(int mode, const FusedArgs& f, hipStream_t s) {
-  if (mode == MODE_F16X2) return sox_fused_f16(f, s);   // own kernels and checks
+  if (mode == MODE_F16X2 || mode == MODE_F32) return sox_fused_pairs(mode, f, s);   // own checks
   if (mode == MODE_BF16X3) return sox_fused_bf3(f, s);
   int TR, TP;
   fused_tile(mode, &TR, &TP);
@@ -273,7 +272,6 @@ hipError_t sox_fused(int mode, const FusedArgs& f, hipStream_t s) {
   dim3 grid(cdiv(f.naux, TP) * cdiv(f.naux, TR) * f.vsplit);
   switch (mode) {
     case MODE_F64: fused_kernel<MODE_F64><<<grid, NT, 0, s>>>(f); break;
-    case MODE_F32: fused_kernel<MODE_F32><<<grid, NT, 0, s>>>(f); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

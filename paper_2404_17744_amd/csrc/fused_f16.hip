@@ -1,13 +1,17 @@
-// The fused B/C/D stage in the fp16x2 mode, 128 x 128 tiles of D per workgroup:
+// The fused B/C/D stage in the fp16x2 and FP32 modes, 128 x 128 tiles of D per
+// workgroup:
 //
 //   D_PR = sum_v C_RvP B_PRv,   B_PRv = sum_q G_Rq A_Pqv,   C_RvP = sum_w U_Rvw G_wP
 //
-// Every operand is a power-of-two scaled value split into two fp16 planes
-// x = x0 + x1; a product is formed from the plane products x1 y0 + x0 y1 + x0 y0
-// on the f16 matrix cores (16x16x32, FP32 accumulation).  The operands are
-// K-major rows with the two planes interleaved per 32-wide k chunk (layout c32:
-// row r, plane p, k at r * 2 ldk + (k / 32) * 64 + 32 p + k % 32), so one
-// 128-byte request fetches both planes of a row's chunk.
+// fp16x2: every operand is a power-of-two scaled value split into two fp16
+// planes x = x0 + x1; a product is formed from the plane products x1 y0 + x0 y1
+// + x0 y0 on the f16 matrix cores (16x16x32, FP32 accumulation).  The operands
+// are K-major rows with the two planes interleaved per 32-wide k chunk (layout
+// c32: row r, plane p, k at r * 2 ldk + (k / 32) * 64 + 32 p + k % 32), so one
+// 128-byte request fetches both planes of a row's chunk.  FP32: plain K-major
+// FP32 rows, whose 32-wide k chunks are 128 bytes too, so both modes share the
+// loads, the LDS layout and the schedule below; a chunk is eight 16x16x4 FP32
+// MFMAs per tile instead of three 16x16x32 f16 ones.
 //
 // Work split.  A workgroup owns a 128 x 128 tile of D and a range of v, taken
 // two v at a time: the k loop of a pair forms B and C for both v at once, so
@@ -20,7 +24,7 @@
 // D += B1 o C1 + B2 o C2.
 //
 // Pipeline.  A k chunk is two half stages, each three panels of 128 rows x 32 k
-// x 2 planes (48 KiB): the B half (G, A_v1, A_v2) in LDS buffer sB and the C
+// x 2 planes (FP32: one plane of 4-byte elements; 48 KiB either way): the B half (G, A_v1, A_v2) in LDS buffer sB and the C
 // half (GX, U_v1, U_v2) in sC.  With 64 KiB for D the workgroup uses the full
 // 160 KiB of LDS.  Chunk t runs as
 //   phase B(t): barrier (C(t) is in sC, every wave has read B(t) from sB);
@@ -65,11 +69,11 @@ __device__ __forceinline__ void vm_lds_barrier() {
   __asm__ volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
-__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(1, 1)))
-void fused_f16_kernel(FusedArgs f) {
-  __shared__ __attribute__((aligned(16))) Half sB;   // G, A_v1, A_v2
-  __shared__ __attribute__((aligned(16))) Half sC;   // GX, U_v1, U_v2
-  __shared__ __attribute__((aligned(16))) f4 sD[NW * 16 * 64];
+// M = MODE_F16X2 or MODE_F32.  sB: G, A_v1, A_v2; sC: GX, U_v1, U_v2; sD: the
+// partial sum of D.
+template <int M>
+__device__ __forceinline__ void fused_pair_body(const FusedArgs& f, Half& sB, Half& sC, f4* sD) {
+  constexpr bool F32 = M == MODE_F32;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wr = wave >> 1, wc = wave & 1;
@@ -175,12 +179,17 @@ void fused_f16_kernel(FusedArgs f) {
     }
   };
 
-  // fragment (row r, plane p, k chunk lane / 16) at halves r * 64 + sw8(r, 4 p + lane / 16) * 8;
-  // sw8 depends on r mod 16 only, so the rows of tile t are 16 t * 64 halves further
+  // fp16x2: fragment (row r, plane p, k chunk lane / 16) at halves r * 64 + sw8(r, 4 p +
+  // lane / 16) * 8.  FP32: the 16x16x4 MFMA takes one k per lane group, and any
+  // assignment of the chunk's 32 k to its eight MFMAs j and four lane groups serves
+  // when both operands use it: lane group g takes k = 8 g + j, two 16-byte reads
+  // at logical chunks 2 g and 2 g + 1 (in "planes" 0 and 1 below).  sw8 depends on
+  // r mod 16 only, so the rows of tile t are 16 t * 64 halves further.
   const int lr = lane & 15, kc = lane >> 4;
   const int rr = wr * 64 + lr, rc = wc * 64 + lr;
-  const int fr0 = rr * 64 + sw8(rr, kc) * 8, fr1 = rr * 64 + sw8(rr, 4 + kc) * 8;
-  const int fc0 = rc * 64 + sw8(rc, kc) * 8, fc1 = rc * 64 + sw8(rc, 4 + kc) * 8;
+  const int c0 = F32 ? 2 * kc : kc, c1 = F32 ? 2 * kc + 1 : 4 + kc;
+  const int fr0 = rr * 64 + sw8(rr, c0) * 8, fr1 = rr * 64 + sw8(rr, c1) * 8;
+  const int fc0 = rc * 64 + sw8(rc, c0) * 8, fc1 = rc * 64 + sw8(rc, c1) * 8;
   // fragments of one half stage: the shared operand s (G or GX) and the per-v
   // operands m1, m2 (A_v or U_v), [plane][tile]
   struct Frags { f16x8 s[2][4], m1[2][4], m2[2][4]; };
@@ -213,20 +222,38 @@ void fused_f16_kernel(FusedArgs f) {
   for (int ti = 0; ti < 4; ++ti)
 #pragma unroll
     for (int tj = 0; tj < 4; ++tj) B1[ti][tj] = B2[ti][tj] = C1[ti][tj] = C2[ti][tj] = zero;
-  // B products: acc[ti][tj] += G[ti] . A_m[tj] (planes x1 y0 + x0 y1 + x0 y0)
+  // FP32: operand j (k = 8 g + j) of a fragment pair
+  auto el = [](const f16x8& lo, const f16x8& hi, int j) {
+    return j < 4 ? __builtin_bit_cast(f4, lo)[j] : __builtin_bit_cast(f4, hi)[j - 4];
+  };
+  // B products: acc[ti][tj] += G[ti] . A_m[tj] (fp16x2: planes x1 y0 + x0 y1 + x0 y0;
+  // FP32: eight 16x16x4 products, the two v interleaved)
   auto mfmaB = [&](const Frags& fr, bool first) {
 #pragma unroll
     for (int ti = 0; ti < 4; ++ti)
 #pragma unroll
       for (int tj = 0; tj < 4; ++tj) {
-        f4 a1 = first ? zero : B1[ti][tj];
-        a1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(fr.s[1][ti], fr.m1[0][tj], a1, 0, 0, 0);
-        a1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(fr.s[0][ti], fr.m1[1][tj], a1, 0, 0, 0);
-        B1[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fr.s[0][ti], fr.m1[0][tj], a1, 0, 0, 0);
-        f4 a2 = first ? zero : B2[ti][tj];
-        a2 = __builtin_amdgcn_mfma_f32_16x16x32_f16(fr.s[1][ti], fr.m2[0][tj], a2, 0, 0, 0);
-        a2 = __builtin_amdgcn_mfma_f32_16x16x32_f16(fr.s[0][ti], fr.m2[1][tj], a2, 0, 0, 0);
-        B2[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fr.s[0][ti], fr.m2[0][tj], a2, 0, 0, 0);
+        if constexpr (F32) {
+          f4 a1 = first ? zero : B1[ti][tj];
+          f4 a2 = first ? zero : B2[ti][tj];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const float g = el(fr.s[0][ti], fr.s[1][ti], j);
+            a1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g, el(fr.m1[0][tj], fr.m1[1][tj], j), a1, 0, 0, 0);
+            a2 = __builtin_amdgcn_mfma_f32_16x16x4f32(g, el(fr.m2[0][tj], fr.m2[1][tj], j), a2, 0, 0, 0);
+          }
+          B1[ti][tj] = a1;
+          B2[ti][tj] = a2;
+        } else {
+          f4 a1 = first ? zero : B1[ti][tj];
+          a1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(fr.s[1][ti], fr.m1[0][tj], a1, 0, 0, 0);
+          a1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(fr.s[0][ti], fr.m1[1][tj], a1, 0, 0, 0);
+          B1[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fr.s[0][ti], fr.m1[0][tj], a1, 0, 0, 0);
+          f4 a2 = first ? zero : B2[ti][tj];
+          a2 = __builtin_amdgcn_mfma_f32_16x16x32_f16(fr.s[1][ti], fr.m2[0][tj], a2, 0, 0, 0);
+          a2 = __builtin_amdgcn_mfma_f32_16x16x32_f16(fr.s[0][ti], fr.m2[1][tj], a2, 0, 0, 0);
+          B2[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fr.s[0][ti], fr.m2[0][tj], a2, 0, 0, 0);
+        }
       }
   };
   // C products: acc[ti][tj] += U_m[ti] . GX[tj]
@@ -235,14 +262,27 @@ void fused_f16_kernel(FusedArgs f) {
     for (int ti = 0; ti < 4; ++ti)
 #pragma unroll
       for (int tj = 0; tj < 4; ++tj) {
-        f4 a1 = first ? zero : C1[ti][tj];
-        a1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(fr.m1[1][ti], fr.s[0][tj], a1, 0, 0, 0);
-        a1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(fr.m1[0][ti], fr.s[1][tj], a1, 0, 0, 0);
-        C1[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fr.m1[0][ti], fr.s[0][tj], a1, 0, 0, 0);
-        f4 a2 = first ? zero : C2[ti][tj];
-        a2 = __builtin_amdgcn_mfma_f32_16x16x32_f16(fr.m2[1][ti], fr.s[0][tj], a2, 0, 0, 0);
-        a2 = __builtin_amdgcn_mfma_f32_16x16x32_f16(fr.m2[0][ti], fr.s[1][tj], a2, 0, 0, 0);
-        C2[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fr.m2[0][ti], fr.s[0][tj], a2, 0, 0, 0);
+        if constexpr (F32) {
+          f4 a1 = first ? zero : C1[ti][tj];
+          f4 a2 = first ? zero : C2[ti][tj];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const float x = el(fr.s[0][tj], fr.s[1][tj], j);
+            a1 = __builtin_amdgcn_mfma_f32_16x16x4f32(el(fr.m1[0][ti], fr.m1[1][ti], j), x, a1, 0, 0, 0);
+            a2 = __builtin_amdgcn_mfma_f32_16x16x4f32(el(fr.m2[0][ti], fr.m2[1][ti], j), x, a2, 0, 0, 0);
+          }
+          C1[ti][tj] = a1;
+          C2[ti][tj] = a2;
+        } else {
+          f4 a1 = first ? zero : C1[ti][tj];
+          a1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(fr.m1[1][ti], fr.s[0][tj], a1, 0, 0, 0);
+          a1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(fr.m1[0][ti], fr.s[1][tj], a1, 0, 0, 0);
+          C1[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fr.m1[0][ti], fr.s[0][tj], a1, 0, 0, 0);
+          f4 a2 = first ? zero : C2[ti][tj];
+          a2 = __builtin_amdgcn_mfma_f32_16x16x32_f16(fr.m2[1][ti], fr.s[0][tj], a2, 0, 0, 0);
+          a2 = __builtin_amdgcn_mfma_f32_16x16x32_f16(fr.m2[0][ti], fr.s[1][tj], a2, 0, 0, 0);
+          C2[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fr.m2[0][ti], fr.s[0][tj], a2, 0, 0, 0);
+        }
       }
   };
 
@@ -314,11 +354,13 @@ void fused_f16_kernel(FusedArgs f) {
   // spread a phase's 12 memory-to-LDS loads over its 96 MFMAs (one per 8):
   // a load the texture unit cannot take yet stalls its wave, and with one wave
   // per SIMD nothing else would keep the matrix core busy meanwhile
+  // (FP32: 256 MFMAs per phase, one load per 21)
+  constexpr int MPL = F32 ? 21 : 8;
   auto spread = [&]() {
 #pragma unroll
     for (int i = 0; i < 12; ++i) {
-      __builtin_amdgcn_sched_group_barrier(0x010, 1, 0);   // one memory instruction
-      __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);   // eight MFMAs
+      __builtin_amdgcn_sched_group_barrier(0x010, 1, 0);     // one memory instruction
+      __builtin_amdgcn_sched_group_barrier(0x008, MPL, 0);   // MPL MFMAs
     }
   };
   auto chunk = [&](bool first) {
@@ -350,6 +392,22 @@ void fused_f16_kernel(FusedArgs f) {
   flush(done <= FLUSH_PAIRS);   // also writes zeros for an empty range
 }
 
+__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void fused_f16_kernel(FusedArgs f) {
+  __shared__ __attribute__((aligned(16))) Half sB;
+  __shared__ __attribute__((aligned(16))) Half sC;
+  __shared__ __attribute__((aligned(16))) f4 sD[NW * 16 * 64];
+  fused_pair_body<MODE_F16X2>(f, sB, sC, sD);
+}
+
+__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void fused_f32_kernel(FusedArgs f) {
+  __shared__ __attribute__((aligned(16))) Half sB;
+  __shared__ __attribute__((aligned(16))) Half sC;
+  __shared__ __attribute__((aligned(16))) f4 sD[NW * 16 * 64];
+  fused_pair_body<MODE_F32>(f, sB, sC, sD);
+}
+
 inline unsigned cdiv16(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
 }  // namespace
@@ -359,16 +417,18 @@ void fused_f16_tile(int* rows, int* cols) {
   *cols = TT;
 }
 
-hipError_t sox_fused_f16(const FusedArgs& f, hipStream_t s) {
+hipError_t sox_fused_pairs(int mode, const FusedArgs& f, hipStream_t s) {
+  if (mode != MODE_F16X2 && mode != MODE_F32) return hipErrorInvalidValue;
   const int npair = (f.n + 1) / 2;
   const int pairs_max = (npair + f.vsplit - 1) / f.vsplit;   // longest pair range
   if (f.vsplit % NXCD16 != 0 || f.ldk % KC != 0 || f.ldk < f.n ||
       (f.dpart_f32 && pairs_max > FLUSH_PAIRS))
     return hipErrorInvalidValue;
-  // buffer offsets inside one tile's rows of U (c32 rows of 4 ldk bytes) are 32-bit
+  // buffer offsets inside one tile's rows of U (rows of 4 ldk bytes) are 32-bit
   if ((int64_t)TT * f.n * f.ldk * 4 > 0x7fffffffLL) return hipErrorInvalidValue;
   const unsigned nb = cdiv16(f.naux, TT);
-  fused_f16_kernel<<<dim3(nb * nb * f.vsplit), NTH, 0, s>>>(f);
+  if (mode == MODE_F16X2) fused_f16_kernel<<<dim3(nb * nb * f.vsplit), NTH, 0, s>>>(f);
+  else fused_f32_kernel<<<dim3(nb * nb * f.vsplit), NTH, 0, s>>>(f);
   return hipGetLastError();
 }
 

@@ -76,9 +76,9 @@ hipError_t astage_bf3(const AStageB3Args& a, hipStream_t s);
 //   Dpart[z][R][P] = sum_{v in split z} (sum_q Gt[R][q] A[v][P][q]) (sum_w U[R][v][w] GXt[P][w])
 // A holds the mode's planes (fp16x2: scaled by the power of two taken from
 // *amax_a, which the reduction divides out; otherwise unscaled).  In the fp16x2
-// mode every operand is in the c32 layout, the plane strides are unused, and
-// the v split counts pairs of v: split z covers the pairs [z' np / vsplit,
-// (z' + 1) np / vsplit) (np = ceil(n / 2)).
+// mode every operand is in the c32 layout and the plane strides are unused; in
+// the fp16x2 and FP32 modes the v split counts pairs of v: split z covers the
+// pairs [z' np / vsplit, (z' + 1) np / vsplit) (np = ceil(n / 2)).
 struct FusedArgs {
   int n, naux, ldk, vsplit, vchunk;
   const void* Gt; const void* GXt; int64_t g_plane;   // [naux][ldk] planes
@@ -97,8 +97,8 @@ struct FusedArgs {
 };
 hipError_t sox_fused(int mode, const FusedArgs& f, hipStream_t s);
 void fused_tile(int mode, int* rows, int* cols);   // D tile one workgroup owns (R x P)
-// the fp16x2 kernel, used by sox_fused for that mode
-hipError_t sox_fused_f16(const FusedArgs& f, hipStream_t s);
+// the two-v kernel of the fp16x2 and FP32 modes, used by sox_fused for them
+hipError_t sox_fused_pairs(int mode, const FusedArgs& f, hipStream_t s);
 // the bf16x3 kernel (three bf16 planes, one v per pass), used by sox_fused for
 // that mode
 hipError_t sox_fused_bf3(const FusedArgs& f, hipStream_t s);

@@ -572,10 +572,9 @@ int thcsox_plan(thcsox_plan_t* out, int n, int naux, int ntau, double beta,
     fused_tile(precision, &TR, &TP);
     auto fits = [&](int64_t nn) {
       const int64_t l = precision == THCSOX_FP16X2 ? (nn + 63) / 64 * 64 : (nn + 31) / 32 * 32;
-      // bytes per k of an operand row addressed by one resource: FP64 8 (FP32
-      // counted at 8 too); fp16x2 4 (both planes in one c32 row); bf16x3 2 (one
-      // resource per plane)
-      const int64_t es = precision == THCSOX_FP16X2 ? 4 : precision == THCSOX_BF16X3 ? 2 : 8;
+      // bytes per k of an operand row addressed by one resource: FP64 8; FP32 4;
+      // fp16x2 4 (both planes in one c32 row); bf16x3 2 (one resource per plane)
+      const int64_t es = precision == THCSOX_FP64 ? 8 : precision == THCSOX_BF16X3 ? 2 : 4;
       // in double: exact near the bound, and no wrap-around for huge n
       return (double)std::max(TR, TP) * (double)nn * (double)l * (double)es <= 2147483647.0;
     };
@@ -639,8 +638,9 @@ int thcsox_plan(thcsox_plan_t* out, int n, int naux, int ntau, double beta,
     const long tiles = (long)((naux + TR - 1) / TR) * ((naux + TP - 1) / TP);
     int best = nx;
     double best_eff = -1.0;
-    // the fp16x2 kernel takes v in pairs and splits the pairs
-    const int nv = precision == THCSOX_FP16X2 ? (n + 1) / 2 : n;
+    // the fp16x2 and FP32 kernel takes v in pairs and splits the pairs
+    const bool pairs = precision == THCSOX_FP16X2 || precision == THCSOX_FP32;
+    const int nv = pairs ? (n + 1) / 2 : n;
     for (int vs = nx; vs <= std::max(nx, std::min(8 * nx, nv)); vs += nx) {
       const long wg = tiles * (vs / nx);                 // workgroups per XCD
       const long rounds = (wg + per_xcd - 1) / per_xcd;
@@ -655,7 +655,7 @@ int thcsox_plan(thcsox_plan_t* out, int n, int naux, int ntau, double beta,
     // n = 300, naux = 1800: 2-4 % faster than the balance choice above, full
     // and symmetric paths).
     if (precision != THCSOX_FP64) {
-      const int per = precision == THCSOX_FP16X2 ? 4 : 8;   // pairs or v per range
+      const int per = pairs ? 4 : 8;   // pairs or v per range
       const int vs8 = ((nv + per - 1) / per + nx - 1) / nx * nx;
       const double dbytes = 4.0 * vs8 * (double)naux * naux;   // FP32 partial tiles
       const bool fits = dbytes <= 2.0e9 &&
@@ -664,7 +664,7 @@ int thcsox_plan(thcsox_plan_t* out, int n, int naux, int ntau, double beta,
     }
     p->vsplit = best;
     // longest v range (ranges are balanced over the XCDs)
-    p->vchunk = precision == THCSOX_FP16X2 ? 2 * ((nv + best - 1) / best) : (n + best - 1) / best;
+    p->vchunk = pairs ? 2 * ((nv + best - 1) / best) : (n + best - 1) / best;
     // ranges of at most 8 v are one FP32 partial sum each: store them as FP32
     p->dpart_f32 = precision != THCSOX_FP64 && p->vchunk <= 8;
   }

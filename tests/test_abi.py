@@ -80,7 +80,7 @@ def test_plan_argument_checks_without_device(L):
     rc = L.thcsox_plan(ctypes.byref(out), 8, 32, 4, 100.0, None, w, None, None, 0, 0, None)
     assert rc == -1 and b"tau_host" in L.thcsox_last_error()
     # orbital counts past the fused kernels' 32-bit buffer offsets, per precision
-    for prec, nmax in ((0, 2047), (1, 1440), (2, 2880), (3, 2047)):
+    for prec, nmax in ((0, 2047), (1, 2047), (2, 2880), (3, 2047)):
         rc = L.thcsox_plan(ctypes.byref(out), nmax + 1, 32, 4, 100.0, tau, w, None, None, prec,
                            0, None)
         assert rc == -1 and f"n <= {nmax})".encode() in L.thcsox_last_error()
