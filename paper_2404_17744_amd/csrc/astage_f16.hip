@@ -322,8 +322,13 @@ template <int KST> struct RBuf {
   _Float16 stg[RNW][16 * (KST / 2)][64];
 };
 
-template <int KST>
+// M = MODE_F16X2, or MODE_F32: FP32 K-major rows, whose 32-wide k chunks are
+// 128 bytes as in c32, so the loads, the LDS layout and the stores are the same;
+// a chunk is eight 16x16x4 FP32 MFMAs per tile (lane group g takes k = 8 g + j,
+// 32 contiguous bytes, in both operands), and A is written unscaled as FP32.
+template <int M, int KST>
 __device__ __forceinline__ void astage_r_body(const AStageArgs& g, RBuf<KST>& b0, RBuf<KST>& b1) {
+  constexpr bool F32 = M == MODE_F32;
   constexpr int NCT = KST / 2;              // 16-column tiles per wave: 4 waves cover ldk columns
   constexpr int LDK = 32 * KST;
   constexpr int LD2 = 2 * LDK;              // halves per c32 row
@@ -353,12 +358,13 @@ __device__ __forceinline__ void astage_r_body(const AStageArgs& g, RBuf<KST>& b0
   // (loaded in batches of 16, the AGPR moves of a batch after the next batch is
   // issued, so that they wait for about one batch's latency each)
   constexpr int NF = 2 * NCT * KST, GB = 16;
+  // (FP32: the two 16-byte pieces 2 (lane / 16) and 2 (lane / 16) + 1 of the chunk)
   auto gload = [&](int f) {
     const int t = f / (2 * KST), c = (f / 2) % KST, p = f % 2;
     const int v = 16 * (NCT * wave + t) + (lane & 15);
-    const uint32_t gv = (uint32_t)((v * LD2 + 8 * (lane >> 4)) * 2);
+    const uint32_t gv = (uint32_t)((v * LD2 + (F32 ? 16 : 8) * (lane >> 4)) * 2);
     gr[t][c][p] = __builtin_bit_cast(
-        f16x8, __builtin_amdgcn_raw_buffer_load_b128(rG, gv, (c * 64 + 32 * p) * 2, 0));
+        f16x8, __builtin_amdgcn_raw_buffer_load_b128(rG, gv, (c * 64 + (F32 ? 8 : 32) * p) * 2, 0));
   };
 #pragma unroll
   for (int f = 0; f < GB && f < NF; ++f) gload(f);
@@ -392,7 +398,7 @@ __device__ __forceinline__ void astage_r_body(const AStageArgs& g, RBuf<KST>& b0
   // (the permutation depends on the row mod 16, so half a is 16 rows further)
   int uoff[2];
 #pragma unroll
-  for (int p = 0; p < 2; ++p) uoff[p] = lr * 64 + sw8a(lr, 4 * p + kc) * 8;
+  for (int p = 0; p < 2; ++p) uoff[p] = lr * 64 + sw8a(lr, F32 ? 2 * kc + p : 4 * p + kc) * 8;
   // the two 16-row halves of a step run one after the other on the same
   // accumulators (16 x 16 NCT of A per wave)
   f4 acc[NCT];
@@ -410,21 +416,36 @@ __device__ __forceinline__ void astage_r_body(const AStageArgs& g, RBuf<KST>& b0
         for (int p = 0; p < 2; ++p)
           un[p] = *reinterpret_cast<const f16x8*>(&bf.u[c + 1][uoff[p] + a * 16 * 64]);
       }
+      if constexpr (F32) {
+        auto el = [](const f16x8& lo, const f16x8& hi, int e) {
+          return e < 4 ? __builtin_bit_cast(f4, lo)[e] : __builtin_bit_cast(f4, hi)[e - 4];
+        };
 #pragma unroll
-      for (int pp = 0; pp < 3; ++pp) {
-        const int pg = pp == 0 ? 1 : 0, pu = pp == 1 ? 1 : 0;
+        for (int e = 0; e < 8; ++e)
 #pragma unroll
-        for (int t = 0; t < NCT; ++t) {
-          if (in_agpr(t, c, pg)) __asm__ volatile("" : "+a"(gr[t][c][pg]));
-          acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
-              u[pu], gr[t][c][pg], (c == 0 && pp == 0) ? f4{0.f, 0.f, 0.f, 0.f} : acc[t], 0, 0, 0);
+          for (int t = 0; t < NCT; ++t) {
+            if (in_agpr(t, c, e / 4)) __asm__ volatile("" : "+a"(gr[t][c][e / 4]));
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                el(u[0], u[1], e), el(gr[t][c][0], gr[t][c][1], e),
+                (c == 0 && e == 0) ? f4{0.f, 0.f, 0.f, 0.f} : acc[t], 0, 0, 0);
+          }
+      } else {
+#pragma unroll
+        for (int pp = 0; pp < 3; ++pp) {
+          const int pg = pp == 0 ? 1 : 0, pu = pp == 1 ? 1 : 0;
+#pragma unroll
+          for (int t = 0; t < NCT; ++t) {
+            if (in_agpr(t, c, pg)) __asm__ volatile("" : "+a"(gr[t][c][pg]));
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                u[pu], gr[t][c][pg], (c == 0 && pp == 0) ? f4{0.f, 0.f, 0.f, 0.f} : acc[t], 0, 0, 0);
+          }
         }
       }
     }
   };
 
-  // the scale of A: 2^-ilogb(amax[set]), amax a bound on |A| times 2^-14
-  const float a_scale = (float)pow2_scale_f(g.amax + set);
+  // the scale of A (fp16x2): 2^-ilogb(amax[set]), amax a bound on |A| times 2^-14
+  const float a_scale = F32 ? 1.f : (float)pow2_scale_f(g.amax + set);
   _Float16* const C = g.A + set * g.a_set;
   const int64_t c_j = (int64_t)g.naux * LD2;   // halves between v rows of A
   typedef _Float16 h4 __attribute__((ext_vector_type(4)));
@@ -436,6 +457,13 @@ __device__ __forceinline__ void astage_r_body(const AStageArgs& g, RBuf<KST>& b0
   // wave's staging lines (v, c32 order)
   auto stage_half = [&](RBuf<KST>& bf, int a) {
     _Float16* const stg = &bf.stg[wave][0][0];
+    if constexpr (F32) {
+      // rows 16 a + 4 kc .. + 3: logical piece 4 a + kc of the line
+#pragma unroll
+      for (int t = 0; t < NCT; ++t)
+        *reinterpret_cast<f4*>(stg + (16 * t + lr) * 64 + 8 * ((4 * a + kc) ^ (lr & 7))) = acc[t];
+      return;
+    }
 #pragma unroll
     for (int t = 0; t < NCT; ++t) {
       h4 hi, lo;
@@ -508,18 +536,23 @@ __device__ __forceinline__ void astage_r_body(const AStageArgs& g, RBuf<KST>& b0
   __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
 
-#define THCSOX_ASTAGE_R_KERNEL(K)                                                       \
+#define THCSOX_ASTAGE_R_KERNEL(NAME, M, K)                                              \
   __global__ __launch_bounds__(RNT) __attribute__((amdgpu_waves_per_eu(1, 1)))          \
-  void astage_f16r_kernel_##K(AStageArgs g) {                                           \
+  void NAME(AStageArgs g) {                                                             \
     __shared__ __attribute__((aligned(16))) RBuf<K> b0;                                 \
     __shared__ __attribute__((aligned(16))) RBuf<K> b1;                                 \
-    astage_r_body<K>(g, b0, b1);                                                        \
+    astage_r_body<M, K>(g, b0, b1);                                                     \
   }
-THCSOX_ASTAGE_R_KERNEL(2)
-THCSOX_ASTAGE_R_KERNEL(4)
-THCSOX_ASTAGE_R_KERNEL(6)
-THCSOX_ASTAGE_R_KERNEL(8)
-THCSOX_ASTAGE_R_KERNEL(10)
+THCSOX_ASTAGE_R_KERNEL(astage_f16r_kernel_2, MODE_F16X2, 2)
+THCSOX_ASTAGE_R_KERNEL(astage_f16r_kernel_4, MODE_F16X2, 4)
+THCSOX_ASTAGE_R_KERNEL(astage_f16r_kernel_6, MODE_F16X2, 6)
+THCSOX_ASTAGE_R_KERNEL(astage_f16r_kernel_8, MODE_F16X2, 8)
+THCSOX_ASTAGE_R_KERNEL(astage_f16r_kernel_10, MODE_F16X2, 10)
+THCSOX_ASTAGE_R_KERNEL(astage_f32r_kernel_2, MODE_F32, 2)
+THCSOX_ASTAGE_R_KERNEL(astage_f32r_kernel_4, MODE_F32, 4)
+THCSOX_ASTAGE_R_KERNEL(astage_f32r_kernel_6, MODE_F32, 6)
+THCSOX_ASTAGE_R_KERNEL(astage_f32r_kernel_8, MODE_F32, 8)
+THCSOX_ASTAGE_R_KERNEL(astage_f32r_kernel_10, MODE_F32, 10)
 #undef THCSOX_ASTAGE_R_KERNEL
 
 hipError_t r_launch(void (*kernel)(AStageArgs), const AStageArgs& g, hipStream_t s) {
@@ -558,6 +591,23 @@ hipError_t astage_f16(const AStageArgs& g, hipStream_t s) {
   if (g.n <= 192) return a_launch<3>(astage_f16_kernel_3, g, s);
   if (g.n <= 256) return a_launch<4>(astage_f16_kernel_4, g, s);
   return a_launch<5>(astage_f16_kernel_5, g, s);   // 320 columns per workgroup, more beyond
+}
+
+bool astage_f32_fits(int n, int naux, int ldk) {
+  return n > 0 && naux > 0 && ldk >= n && ldk % 64 == 0 && ldk <= 320 &&
+         (int64_t)n * naux * ldk * 4 < 0x7fffffffLL;
+}
+
+hipError_t astage_f32(const AStageArgs& g, hipStream_t s) {
+  if (g.naux <= 0 || g.n <= 0) return hipSuccess;
+  if (g.nsets != 1 || !astage_f32_fits(g.n, g.naux, g.ldk)) return hipErrorInvalidValue;
+  switch (g.ldk) {
+    case 64: return r_launch(astage_f32r_kernel_2, g, s);
+    case 128: return r_launch(astage_f32r_kernel_4, g, s);
+    case 192: return r_launch(astage_f32r_kernel_6, g, s);
+    case 256: return r_launch(astage_f32r_kernel_8, g, s);
+    default: return r_launch(astage_f32r_kernel_10, g, s);
+  }
 }
 
 }  // namespace thcsox

@@ -55,6 +55,13 @@ struct AStageArgs {
   const unsigned long long* amax;
 };
 hipError_t astage_f16(const AStageArgs& a, hipStream_t s);
+// The same stage in the FP32 mode for one tau point (nsets = 1; amax, a_set
+// unused): U, Gb and A are FP32 K-major rows of ldk elements (A passed as the
+// address of its FP32 array), A written unscaled.  Only for ldk a multiple of 64
+// up to 320 with A's byte offsets in 31 bits (astage_f32_fits); otherwise
+// hipErrorInvalidValue (use gemm_kmajor).
+bool astage_f32_fits(int n, int naux, int ldk);
+hipError_t astage_f32(const AStageArgs& a, hipStream_t s);
 // The A stage of the bf16x3 mode for one tau point:
 //   A[p][v][P][q] = plane p of the bf16x3 split of sum_s U[P][q][s] Gb[v][s]
 //   (q < n; rows n <= q < ldk get 0)

@@ -398,6 +398,13 @@ int sigma_batch(thcsox_plan_s* p, const double* G, double* Sigma, double* Sthc_o
         ast.A = static_cast<_Float16*>(p->A); ast.a_set = a_set;
         ast.amax = p->am_a() + k;
         HIP_TRY(astage_f16(ast, s));
+      } else if (mode == MODE_F32 && astage_f32_fits(n, naux, ldk)) {
+        AStageArgs ast{};
+        ast.naux = naux; ast.n = n; ast.ldk = ldk; ast.nsets = 1;
+        ast.U = cores.UA;
+        ast.Gb = static_cast<const char*>(p->Gb) + (size_t)b * n * ldk * es;
+        ast.A = static_cast<_Float16*>(p->A);
+        HIP_TRY(astage_f32(ast, s));
       } else if (mode == MODE_BF16X3 && astage_bf3_fits(n, naux, ldk)) {
         AStageB3Args ab{};
         ab.naux = naux; ab.n = n; ab.ldk = ldk;

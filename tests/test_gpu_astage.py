@@ -1,4 +1,4 @@
-"""GPU parity of the fp16x2 and bf16x3 A stages, A_Pqv = sum_s U_Pqs G_sv(beta - tau), at the
+"""GPU parity of the fp16x2, bf16x3 and FP32 A stages, A_Pqv = sum_s U_Pqs G_sv(beta - tau), at the
 orbital counts that select each of its kernels, through Sigma (every element
 of A enters it) against the oracle's THC-SOX sequence.
 
@@ -25,6 +25,11 @@ block splits, a block of exactly 12 tiles (n = 192), full and ragged last
 tiles, steps wholly past n (32 ceil(n / 32) - n >= 16) and the streaming kernel
 beyond (n = 321).  Bar: 2e-7 of max |Sigma| (the bf16x3 path reaches a few
 1e-9; one dropped plane product or a wrong plane costs about 2^-16).
+
+The FP32 A stage runs the fp16x2 register kernel's FP32 form while ldk =
+32 ceil(n / 32) is a multiple of 64 up to 320 (2, 4, 6, 8 or 10 k chunks),
+and the streaming kernel otherwise (n = 150: ldk = 160; n = 321).  Bar: 2e-6
+of max |Sigma|, as the other FP32 parity tests.
 """
 import numpy as np
 import pytest
@@ -85,3 +90,29 @@ def test_astage_kernels_bf16x3(dev, case):
         err = float(np.abs(S[k] - ref[k]).max() / np.abs(ref[k]).max())
         print(f"  tau {k}: rel err {err:.2e}", flush=True)
         assert err <= BF3_TOL
+
+
+F32_TOL = 2e-6
+F32_CASES = [(40, 37, 2), (100, 44, 3), (150, 40, 2), (180, 48, 2), (250, 40, 2), (300, 52, 2),
+             (320, 40, 2), (321, 44, 2)]
+
+
+@pytest.mark.parametrize("case", F32_CASES, ids=[f"n{a}_naux{b}_ntau{c}" for a, b, c in F32_CASES])
+def test_astage_kernels_fp32(dev, case):
+    n, naux, ntau = case
+    print(f"case n{n} naux{naux} ntau{ntau} fp32 A stage", flush=True)
+    s = synth.make_system(n, naux, seed=80 + n)
+    tau, w = synth.cheb_tau_grid(ntau, BETA)
+    G = synth.g0_tau(s, tau, BETA)
+    ref = osox.sigma_all_tau(osox.sigma_thc_paper, G, s.X, s.V)
+    plan = thcsox.Plan(torch.from_numpy(s.X).to(dev), torch.from_numpy(s.V).to(dev), tau, w,
+                       BETA, precision="fp32")
+    S = plan.sigma(torch.from_numpy(G).to(dev))
+    torch.cuda.synchronize()
+    S = S.cpu().numpy()
+    plan.close()
+    assert np.isfinite(S).all()
+    for k in range(ntau):
+        err = float(np.abs(S[k] - ref[k]).max() / np.abs(ref[k]).max())
+        print(f"  tau {k}: rel err {err:.2e}", flush=True)
+        assert err <= F32_TOL
