@@ -62,12 +62,18 @@ def timed_steps(plan, Gd, S, steps, torch, k_end=None):
 
 
 def fused_source_hash():
-    """Hash of the sources that make up the fused kernel."""
+    """Hash of the sources that make up the fp16x2 fused kernel: its file, the
+    headers it includes and the definition of its argument struct."""
     import hashlib
+    import re
     h = hashlib.sha256()
-    for f in ("fused.hip", "fused_f16.hip", "panel.hpp", "mfma.hpp", "kernels.hpp"):
-        with open(os.path.join(ROOT, "paper_2404_17744_amd", "csrc", f), "rb") as fh:
+    csrc = os.path.join(ROOT, "paper_2404_17744_amd", "csrc")
+    for f in ("fused_f16.hip", "panel.hpp", "mfma.hpp"):
+        with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
+    with open(os.path.join(csrc, "kernels.hpp")) as fh:
+        m = re.search(r"struct FusedArgs \{.*?\n\};", fh.read(), re.S)
+    h.update(m.group(0).encode())
     return h.hexdigest()[:16]
 
 
