@@ -351,11 +351,13 @@ __device__ __forceinline__ void fused_pair_body(const FusedArgs& f, Half& sB, Ha
     vm_lds_barrier();
     readB(fb);
   }
-  // spread a phase's 12 memory-to-LDS loads over its 96 MFMAs (one per 8):
-  // a load the texture unit cannot take yet stalls its wave, and with one wave
-  // per SIMD nothing else would keep the matrix core busy meanwhile
-  // (FP32: 256 MFMAs per phase, one load per 21)
-  constexpr int MPL = F32 ? 21 : 8;
+  // interleave a phase's 12 memory-to-LDS loads with its first MFMAs, one load
+  // per MPL of them: a load the texture unit cannot take yet stalls its wave,
+  // and with one wave per SIMD nothing else would keep the matrix core busy
+  // meanwhile, while loads issued late have less time to land (measured at n =
+  // 300: fp16x2, 96 MFMAs per phase, fastest at 3 of 1, 2, 3, 4, 8; FP32, 256
+  // MFMAs per phase, at 16 of 10, 12, 16, 21)
+  constexpr int MPL = F32 ? 16 : 3;
   auto spread = [&]() {
 #pragma unroll
     for (int i = 0; i < 12; ++i) {
