@@ -6,6 +6,9 @@ reference (it matches the oracle to 1e-10 at n=8, 100 and 300):
 
 * the fp16x2 path (in the configuration the throughput measurement uses)
   against the FP64 path on two tau points: 1e-6 relative in Sigma;
+* the FP32 and bf16x3 paths against the FP64 path on the same points, 1e-6
+  (their fused kernels with FP64 partial tiles over ranges of more than 8 v,
+  and the A stage's kernels for ldk > 320);
 * Sigma(tau) symmetric for the symmetric inputs;
 * the symmetric-D path against the full path;
 * homogeneity Sigma[c G] = c^3 Sigma[G] (c a power of two, so exact up to the
@@ -67,6 +70,20 @@ def test_paperscale_mixed_vs_fp64(case):
     assert _rel(S64, np.transpose(S64, (0, 2, 1))) <= 1e-12
     assert _rel(S16, np.transpose(S16, (0, 2, 1))) <= 1e-6
     case["S16"] = S16
+    case["S64"] = S64
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_paperscale_fp32_bf16x3_vs_fp64(case, precision):
+    S64 = case.get("S64")
+    if S64 is None:
+        print(f"case {NAME} fp64 k={KS}", flush=True)
+        S64 = case["S64"] = _sigma(case, "fp64")
+    print(f"case {NAME} {precision} k={KS}", flush=True)
+    S = _sigma(case, precision)
+    err = _rel(S, S64)
+    print(f"  {precision} vs fp64 max rel {err:.2e}")
+    assert err <= 1e-6
 
 
 def test_paperscale_symmetric_path_and_homogeneity(case):
